@@ -1,0 +1,154 @@
+/*
+ * iht.h -- C ABI of the MI355X (gfx950) hot path of iterative hard thresholding for GWAS.
+ *
+ * Method: Keys, Chen & Lange, "Iterative hard thresholding for model selection in genome-wide
+ * association studies" (arXiv:1608.01398). The library minimises the least-squares loss
+ * f(beta) = 1/2 ||y - A beta||^2 (Methods, eq. leastsquaresloss) subject to at most k nonzero SNP
+ * effects, with A = [X_st | Z | 1]: X_st the standardised genotype matrix (Methods, "Bandwidth
+ * optimization of IHT"), Z dense non-genetic covariates and an intercept, both unpenalised
+ * (Results: SexOCPG and principal components enter as covariates).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: IHT_OK (0) on success; > 0 means a valid result with a warning; < 0 is an error,
+ *    raised before any device work is enqueued whenever it is an argument error. Details of the
+ *    last error on the calling thread: iht_last_error(). No C++ exception crosses this ABI.
+ *  - `stream` is a hipStream_t (NULL = the default stream). All device work is enqueued on it.
+ *    Device-pointer outputs are valid once the stream has been synchronised. Calls that return
+ *    host-side values (iht_fit's n_iter, the status of iht_project and iht_fit) synchronise the
+ *    stream themselves.
+ *  - Ownership: the caller owns every input and output buffer and keeps it alive for the call;
+ *    handles own their device memory and free it in the matching *_destroy.
+ *  - Threading: a handle must not be used by two threads at once; distinct handles are independent.
+ *  - Genotypes: PLINK 1 SNP-major .bed rows. SNP j occupies `row_bytes` bytes; subject i is in byte
+ *    i/4 at bits 2(i%4) (low) and 2(i%4)+1 (high); two-bit value 0 = homozygous first allele
+ *    (dosage 0), 1 = missing, 2 = heterozygous (dosage 1), 3 = homozygous second allele (dosage 2).
+ *  - Standardisation (Methods, "Bandwidth optimization of IHT"; Results, "Simulation"): over the
+ *    subject set T of a stats handle, u_j is the mean of the observed dosages, sigma_j^2 the
+ *    population variance of the mean-imputed column over all |T| subjects, v_j = 1/sigma_j
+ *    (v_j = 0 when sigma_j = 0), and x_st(i,j) = v_j (x_ij - u_j) with missing entries exactly 0.
+ */
+#ifndef IHT_H
+#define IHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define IHT_OK 0
+#define IHT_NOT_CONVERGED 1 /* max_iter reached; outputs hold the last iterate          */
+#define IHT_STALLED 2       /* backtracking budget exhausted; outputs hold the last accepted iterate */
+#define IHT_EINVAL (-1)     /* bad argument (NULL, sizes, k out of range, subset not 0/1) */
+#define IHT_ENOMEM (-2)     /* device allocation failed                                   */
+#define IHT_EDEVICE (-3)    /* a HIP runtime call or kernel launch failed                 */
+#define IHT_ENONFINITE (-4) /* NaN or Inf in y, Z, r or w                                 */
+#define IHT_EUNSUPPORTED (-5)
+
+/* arithmetic of the gradient pass */
+#define IHT_FP64 0 /* table entries and accumulation in FP64 (default)                     */
+#define IHT_FP32 1 /* table entries in FP32, per-tile FP32 sums accumulated in FP64         */
+
+/* iht_geno_create flags: where `bed` lives */
+#define IHT_HOST_PTR 0
+#define IHT_DEVICE_PTR 1
+
+/* Largest sparsity level the device projection accepts. */
+#define IHT_MAX_K 4096
+
+typedef struct iht_geno iht_geno;   /* resident, re-tiled genotype matrix on one device */
+typedef struct iht_stats iht_stats; /* u, v [p] FP64 and the subject set T they were computed on */
+
+/* Options of iht_fit. The paper fixes none of them (Methods, "IHT step sizes" only asks 0<c<<1). */
+typedef struct iht_opts {
+    double tol;            /* stop when S+ = S and ||beta+ - beta||_inf <= tol*max(1,||beta+||_inf); default 1e-10 */
+    int32_t max_iter;      /* default 200                                                   */
+    int32_t max_backtrack; /* step halvings allowed per iteration; default 50               */
+    double c;              /* omega = (1-c)||d||^2/||A d||^2, 0 < c < 1; default 0.01        */
+    double shrink;         /* mu <- shrink*mu on each backtrack, 0 < shrink < 1; default 0.5 */
+    int32_t precision;     /* IHT_FP64 or IHT_FP32 for the gradient pass; default IHT_FP64   */
+} iht_opts;
+
+/* Fill *o with the defaults above. */
+void iht_opts_default(iht_opts *o);
+
+/*
+ * Upload (if IHT_HOST_PTR) and re-tile a PLINK SNP-major matrix once onto the current device
+ * (Methods, "Parallelization of IHT": the compressed matrix is pushed to the device once).
+ *   bed        [p][row_bytes] bytes, host or device memory per `flags`; only read during the call.
+ *   n, p       subjects and SNPs, n >= 1, p >= 1, n <= 2^24, p <= 2^31 - 8192.
+ *   row_bytes  >= ceil(n/4); bits past subject n-1 are ignored.
+ *   out        receives the handle.
+ * Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. The stream is synchronised before returning.
+ */
+int iht_geno_create(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, int32_t flags, void *stream, iht_geno **out);
+int iht_geno_destroy(iht_geno *g);
+/* n, p of a handle (either output may be NULL). */
+int iht_geno_shape(const iht_geno *g, int64_t *n, int64_t *p);
+
+/*
+ * Per-SNP standardisation cache u, v over the subject set T (Methods, "Bandwidth optimization of
+ * IHT": precompute and cache the means and inverse standard deviations).
+ *   subset  host array of n bytes, each 0 or 1 (1 = subject in T), or NULL for all n subjects;
+ *           |T| >= 1. A solve on T equals the solve on the matrix restricted to the rows in T.
+ * The counts are exact integers and u_j, sigma_j^2, sqrt and 1/sqrt are single IEEE operations,
+ * so u and v are bitwise reproducible. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE.
+ */
+int iht_stats_create(const iht_geno *g, const uint8_t *subset, void *stream, iht_stats **out);
+int iht_stats_destroy(iht_stats *s);
+/* Copy u and v (device pointers, p doubles each; either may be NULL) out of a stats handle. */
+int iht_stats_read(const iht_stats *s, double *u, double *v, void *stream);
+
+/*
+ * Gradient pass g = X_st^T r over T (Methods, eq. normal_grad: g = -grad f at r = y - X beta).
+ *   r  device [n] FP64 residuals; entries of subjects outside T are ignored.
+ *   g  device [p] FP64 output.
+ *   precision  IHT_FP64 or IHT_FP32.
+ * Every SNP column is decoded and standardised on the fly from the packed bytes (Methods,
+ * "Bandwidth optimization of IHT"). Errors: IHT_EINVAL (stats of another matrix, bad precision),
+ * IHT_EDEVICE. Asynchronous; r must stay valid until the stream reaches the work.
+ */
+int iht_gradient(const iht_geno *g, const iht_stats *s, const double *r, double *grad, int32_t precision, void *stream);
+
+/*
+ * Hard-threshold projection P_Sk (Methods, eq. ihta and the text after it): keep the k entries of
+ * largest |w|, ties broken towards the lower index, zero the rest.
+ *   w        device [p] FP64, finite.
+ *   support  device [k] int64 output, ascending.
+ *   w_out    device [p] FP64 output (w on the support, 0 elsewhere) or NULL.
+ *   1 <= k <= min(p, IHT_MAX_K).
+ * Errors: IHT_EINVAL, IHT_ENONFINITE (detected on the device; the call synchronises), IHT_EDEVICE.
+ */
+int iht_project(const double *w, int64_t p, int32_t k, int64_t *support, double *w_out, void *stream);
+
+/*
+ * Full IHT solve (Methods, eq. ihta with the normalised step and the omega backtracking rule of
+ * "IHT step sizes"): beta <- P_Sk[beta + mu A^T(y - A beta)], beta^0 = 0,
+ * mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2 with C the unpenalised columns; when the support
+ * changes, mu is halved until mu < omega = (1-c)||beta+ - beta||^2 / ||A(beta+ - beta)||^2.
+ *   y          device [n] FP64 trait; entries outside T are ignored.
+ *   Z          device FP32 covariates, column-major [n x cz] (covariate c at Z + c*n), or NULL if cz = 0.
+ *   intercept  1 to include an unpenalised column of ones.
+ *   k          1 <= k <= min(p, IHT_MAX_K) SNPs in the model.
+ *   opts       NULL for the defaults.
+ *   support    device [k] int64 output, ascending SNP indices.
+ *   beta_S     device [k] FP64 output, effects on `support`.
+ *   beta_cov   device [cz + intercept] FP64 output (covariates, then intercept), or NULL if empty.
+ *   loss_trace device [max_iter + 1] FP64 output: f at beta^0 .. beta^{n_iter}.
+ *   n_iter     host int32 output: iterations performed.
+ * Returns IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED, or an error (IHT_EINVAL, IHT_ENONFINITE,
+ * IHT_ENOMEM, IHT_EDEVICE). Synchronises the stream.
+ */
+int iht_fit(const iht_geno *g, const iht_stats *s, const double *y, const float *Z, int32_t cz, int32_t intercept, int32_t k,
+            const iht_opts *opts, int64_t *support, double *beta_S, double *beta_cov, double *loss_trace, int32_t *n_iter,
+            void *stream);
+
+const char *iht_status_str(int status);
+const char *iht_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IHT_H */

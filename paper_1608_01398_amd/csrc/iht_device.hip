@@ -1,0 +1,1048 @@
+// iht_device.hip -- gfx950 kernels of the IHT hot path.
+//
+// Hot loop (gradient pass, Methods: eq. normal_grad with on-the-fly standardisation):
+//   g_j = v_j * ( D_j - u_j * (R - M_j) ),   D_j = sum_i dose_ij r_i,   M_j = sum_{i missing} r_i,
+// with r the residual centred over the subject set (R = sum r, ~0). This is X_st^T r written with the
+// paper's identity X_st = X diag(v) - 1 u^T diag(v) (Methods, "Bandwidth optimization of IHT") and
+// mean-imputed missing entries (x~ = u_j, so they contribute 0). Centring is exact in real
+// arithmetic because every standardised column sums to zero over the subject set.
+//
+// D_j and M_j come from a table in LDS built per subject tile from the residual: for each group of
+// 4 subjects and each of the 256 possible packed bytes, (sum of dose*r, sum of missing*r). One
+// 16-byte LDS lookup then replaces the decode and 4 multiply-adds of 4 genotypes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "iht_internal.h"
+
+namespace iht {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 stream_load(const uint4* p) {
+  const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(x.x, x.y, x.z, x.w);
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint2 stream_load2(const uint2* p) {
+  const u32x2 x = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+  return make_uint2(x.x, x.y);
+}
+
+__device__ __forceinline__ uint32_t atomic_load_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deterministic block sum over 1024 threads (wave tree, then the 16 wave totals in order).
+__device__ double block_sum(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    sh[32] = t;
+  }
+  __syncthreads();
+  return sh[32];
+}
+
+__device__ double block_max(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, sh[i]);
+    sh[32] = t;
+  }
+  __syncthreads();
+  return sh[32];
+}
+
+// Exclusive suffix sum over the threads of a 1024-thread block: returns sum of `x` over threads > tid.
+__device__ uint32_t block_excl_suffix(uint32_t x, uint32_t* sc /* [1024] */) {
+  const int t = threadIdx.x;
+  const int pos = 1023 - t;
+  __syncthreads();
+  sc[pos] = x;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t add = (pos >= off) ? sc[pos - off] : 0u;
+    __syncthreads();
+    sc[pos] += add;
+    __syncthreads();
+  }
+  return sc[pos] - x;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Re-tile PLINK SNP-major rows into [tile][p_pad][8 B] with a per-SNP byte rotation.
+
+__global__ __launch_bounds__(256) void k_retile(const uint8_t* __restrict__ raw, int64_t row, int64_t n, int64_t p,
+                                                int64_t p_pad, int64_t ntiles, uint8_t* __restrict__ tiled) {
+  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg >= ntiles * p_pad) return;
+  const int64_t t = seg / p_pad, j = seg - t * p_pad;
+  uint32_t w[2] = {0u, 0u};
+  if (j < p) {
+    const int rot = (int)(j & (kSegBytes - 1));
+#pragma unroll
+    for (int b = 0; b < kSegBytes; ++b) {
+      const int64_t src = t * kSegBytes + ((b + rot) & (kSegBytes - 1));  // byte of the PLINK row
+      uint32_t val = 0;
+      if (src < row && src * 4 < n) {
+        val = raw[j * row + src];
+        const int64_t keep = n - src * 4;  // subjects of this byte that exist
+        if (keep < 4) val &= (1u << (2 * keep)) - 1u;
+      }
+      w[b >> 2] |= val << (8 * (b & 3));
+    }
+  }
+  *reinterpret_cast<uint2*>(tiled + seg * kSegBytes) = make_uint2(w[0], w[1]);
+}
+
+// ------------------------------------------------------------------------------------------------
+// a2: exact genotype class counts over the subject set -> u, v (Methods, "Bandwidth optimization").
+
+__device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {  // bit q -> bit 2q
+  return (m & 1u) | ((m & 2u) << 1) | ((m & 4u) << 2) | ((m & 8u) << 3);
+}
+
+__global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
+                                               const uint32_t* __restrict__ mask_bits, int64_t nT, double* __restrict__ u,
+                                               double* __restrict__ v) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  const int rot = (int)(j & (kSegBytes - 1));
+  uint32_t het = 0, hom = 0, mis = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const uint32_t m32 = mask_bits[t];
+    const uint2 d = tiled[t * p_pad + j];
+    const uint32_t dw[2] = {d.x, d.y};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      uint32_t mm = 0;
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int grp = (4 * q + bb + rot) & (kSegBytes - 1);
+        mm |= spread_nibble((m32 >> (4 * grp)) & 15u) << (8 * bb);
+      }
+      const uint32_t lo = dw[q] & 0x55555555u, hi = (dw[q] >> 1) & 0x55555555u;
+      het += __popc(hi & ~lo & mm);
+      hom += __popc(hi & lo & mm);
+      mis += __popc(lo & ~hi & mm);
+    }
+  }
+  const int64_t nobs = nT - (int64_t)mis;
+  if (nobs == 0) {
+    u[j] = 0.0;
+    v[j] = 0.0;
+    return;
+  }
+  const int64_t s1 = (int64_t)het + 2 * (int64_t)hom;
+  const int64_t s2 = (int64_t)het + 4 * (int64_t)hom;
+  const int64_t num = nobs * s2 - s1 * s1;
+  u[j] = __ddiv_rn((double)s1, (double)nobs);
+  if (num == 0) {
+    v[j] = 0.0;
+    return;
+  }
+  const double var = __ddiv_rn((double)num, (double)(nobs * nT));
+  v[j] = __ddiv_rn(1.0, __dsqrt_rn(var));
+}
+
+// ------------------------------------------------------------------------------------------------
+// a4: the gradient pass.
+
+// LDS table: one 256-byte row per packed byte value v (0..255), 64 KB in all. FP64 rows hold
+// [buffer 0: 8 groups x (T, M) 16 B][buffer 1: same]; FP32 rows hold [buffer 0 copy 0: 8 x 8 B]
+// [buffer 0 copy 1][buffer 1 copy 0][buffer 1 copy 1]. The buffer is an immediate offset (+128).
+// At every lookup step the 8 (FP64, 16-byte reads) or 16 (FP32, two copies) lanes served together
+// read 8 different groups, which tile all 32 banks: no conflicts for any data.
+template <bool F32>
+struct Tab;
+template <>
+struct Tab<false> {
+  static constexpr uint32_t kGroupShift = 4;
+  __device__ static uint32_t slot_base(int lane) { return 0u; }
+};
+template <>
+struct Tab<true> {
+  static constexpr uint32_t kGroupShift = 3;
+  __device__ static uint32_t slot_base(int lane) { return (uint32_t)((lane >> 3) & 1) * 64u; }
+};
+
+__device__ __forceinline__ double dose_of(int c) { return c == 3 ? 2.0 : (c == 2 ? 1.0 : 0.0); }
+__device__ __forceinline__ double miss_of(int c) { return c == 1 ? 1.0 : 0.0; }
+
+// Builder thread (group gb, byte values low7 and low7 + 128): T(v) = sum_k dose(c_k(v)) r_k and
+// M(v) = sum_k [c_k(v) missing] r_k over the group's 4 subjects, summed in subject order.
+template <bool F32>
+__device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int low7, const double (&r)[4]) {
+  const int c0 = low7 & 3, c1 = (low7 >> 2) & 3, c2 = (low7 >> 4) & 3;
+  const double T6 = (dose_of(c0) * r[0] + dose_of(c1) * r[1]) + dose_of(c2) * r[2];
+  const double M6 = (miss_of(c0) * r[0] + miss_of(c1) * r[1]) + miss_of(c2) * r[2];
+  const int b6 = low7 >> 6;  // low bit of the fourth subject's code
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int c3 = b6 | (m << 1);
+    const double T = T6 + dose_of(c3) * r[3];
+    const double M = M6 + miss_of(c3) * r[3];
+    char* row = lds + ((low7 + 128 * m) << 8) + buf * 128;
+    if constexpr (F32) {
+      const float2 e = make_float2((float)T, (float)M);
+      *reinterpret_cast<float2*>(row + (gb << 3)) = e;
+      *reinterpret_cast<float2*>(row + 64 + (gb << 3)) = e;
+    } else {
+      *reinterpret_cast<double2*>(row + (gb << 4)) = make_double2(T, M);
+    }
+  }
+}
+
+// Lookups and rotation-invariant tile sum of one SNP's 8-byte segment (buffer BUF).
+// The pairings {b, b+4}, {b, b+2}, {0, 1} of byte positions map to the same pairings of subject
+// groups for every rotation, and + is commutative, so the tile sum depends only on the column's
+// bytes: identical columns give bitwise identical gradients.
+template <bool F32, int BUF>
+__device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)[2], const uint2 d, double& accT,
+                                         double& accM) {
+  using acc_t = typename std::conditional<F32, float, double>::type;
+  acc_t PT[4], PM[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    acc_t vt[2], vm[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = c + 4 * h;
+      const uint32_t dw = h ? d.y : d.x;
+      // byte0 = slot offset of step b, byte1 = packed value, bytes 2-3 = 0
+      const uint32_t sel = (4u + (uint32_t)c) | ((uint32_t)c << 8) | (0x0Cu << 16) | (0x0Cu << 24);
+      const uint32_t addr = __builtin_amdgcn_perm(offs[h], dw, sel) + BUF * 128;
+      if constexpr (F32) {
+        const float2 e = *reinterpret_cast<const float2*>(lds + addr);
+        vt[h] = e.x;
+        vm[h] = e.y;
+      } else {
+        const double2 e = *reinterpret_cast<const double2*>(lds + addr);
+        vt[h] = e.x;
+        vm[h] = e.y;
+      }
+      (void)b;
+    }
+    PT[c] = vt[0] + vt[1];
+    PM[c] = vm[0] + vm[1];
+  }
+  accT += (double)((PT[0] + PT[2]) + (PT[1] + PT[3]));
+  accM += (double)((PM[0] + PM[2]) + (PM[1] + PM[3]));
+}
+
+// Residual of the 4 subjects of group gb in tile t, centred on the subject-set mean, 0 outside it.
+__device__ __forceinline__ void group_residual(const double* __restrict__ r, const double* __restrict__ mask, int64_t n,
+                                               int t, int gb, double mean, double (&out)[4]) {
+  const int64_t i0 = (int64_t)t * kTileSubjects + gb * 4;
+  const double4 m4 = *reinterpret_cast<const double4*>(mask + i0);
+  const double mk[4] = {m4.x, m4.y, m4.z, m4.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = (i0 + k < n && mk[k] != 0.0) ? r[i0 + k] - mean : 0.0;
+}
+
+template <int NS, bool F32>
+__global__ __launch_bounds__(1024, 1) void k_pass(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
+                                                  int32_t tps, int64_t n, const double* __restrict__ r,
+                                                  const double* __restrict__ mask, int64_t nT, const double* __restrict__ u,
+                                                  const double* __restrict__ v, FitState* __restrict__ fs,
+                                                  double* __restrict__ g, double2* __restrict__ partial) {
+  __shared__ __attribute__((aligned(16))) uint4 lds_raw[4096];  // 256 rows x 256 B
+  __shared__ double red[40];
+  char* lds = reinterpret_cast<char*>(lds_raw);
+  constexpr uint32_t GS = Tab<F32>::kGroupShift;
+
+  const int tid = threadIdx.x;
+  // Centre the residual over the subject set: X_st^T 1_T = 0, so the gradient is unchanged and
+  // the table entries stay small. R = sum of the centred residual (~0) enters the epilogue.
+  double mean, R;
+  {
+    double s1 = 0.0;
+    for (int64_t i = tid; i < n; i += kPassThreads) s1 += (mask[i] != 0.0) ? r[i] : 0.0;
+    mean = block_sum(s1, red) / (double)nT;
+    double s2 = 0.0;
+    for (int64_t i = tid; i < n; i += kPassThreads) s2 += (mask[i] != 0.0) ? r[i] - mean : 0.0;
+    R = block_sum(s2, red);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+      fs->mean = mean;
+      fs->Rsum = R;
+    }
+  }
+  const int64_t jb = (int64_t)blockIdx.x * (kPassThreads * NS) + tid;
+  const int t0 = blockIdx.y * tps;
+  const int t1 = min(ntiles, t0 + tps);
+  const uint32_t rot = (uint32_t)tid & 7u;  // == j & 7 for every SNP slot of this lane
+
+  // offs[h] byte c = slot offset of step b = c + 4h: group (b + rot) mod 8.
+  uint32_t offs[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint32_t o = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o |= (Tab<F32>::slot_base(tid) + ((((uint32_t)(c + 4 * h) + rot) & 7u) << GS)) << (8 * c);
+    offs[h] = o;
+  }
+  const int gb = tid & 7, low7 = tid >> 3;
+  const uint2* src = tiled + jb;
+
+  double accT[NS], accM[NS];
+  uint2 dA[NS], dB[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    accT[s] = 0.0;
+    accM[s] = 0.0;
+    dA[s] = stream_load2(src + (int64_t)t0 * p_pad + s * kPassThreads);
+  }
+  {
+    double rr[4];
+    group_residual(r, mask, n, t0, gb, mean, rr);
+    build_entries<F32>(lds, 0, gb, low7, rr);
+  }
+  __syncthreads();
+
+  // Two tiles per trip with explicit register sets A (even tiles, buffer 0) and B (odd tiles,
+  // buffer 1): each half prefetches the next tile and builds its table while the current tile is
+  // consumed. A prefetch past the last tile reads one shared 8-byte word instead (no branch).
+  const int npairs = (t1 - t0) >> 1;
+  for (int pr = 0; pr < npairs; ++pr) {
+    const int t = t0 + 2 * pr;
+    {
+      double rr[4];
+      group_residual(r, mask, n, t + 1, gb, mean, rr);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) dB[s] = stream_load2(src + (int64_t)(t + 1) * p_pad + s * kPassThreads);
+      build_entries<F32>(lds, 1, gb, low7, rr);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        tile_sum<F32, 0>(lds, offs, dA[s], accT[s], accM[s]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();
+    }
+    {
+      const bool real = t + 2 < t1;
+      const int tc = real ? t + 2 : t1 - 1;
+      double rr[4];
+      group_residual(r, mask, n, tc, gb, mean, rr);
+      const uint2* nx = real ? src + (int64_t)tc * p_pad : tiled;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) dA[s] = stream_load2(real ? nx + s * kPassThreads : nx);
+      build_entries<F32>(lds, 0, gb, low7, rr);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        tile_sum<F32, 1>(lds, offs, dB[s], accT[s], accM[s]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __syncthreads();
+    }
+  }
+  if ((t1 - t0) & 1) {  // last tile of an odd count: already in A / buffer 0
+#pragma unroll
+    for (int s = 0; s < NS; ++s) tile_sum<F32, 0>(lds, offs, dA[s], accT[s], accM[s]);
+  }
+
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int64_t j = jb + s * kPassThreads;
+    if (j < p) {
+      if (partial) {
+        partial[(int64_t)blockIdx.y * p_pad + j] = make_double2(accT[s], accM[s]);
+      } else {
+        g[j] = v[j] * (accT[s] - u[j] * (R - accM[s]));
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pass_finalize(const double2* __restrict__ partial, int32_t split, int64_t p,
+                                                       int64_t p_pad, const double* __restrict__ u,
+                                                       const double* __restrict__ v, const FitState* __restrict__ fs,
+                                                       double* __restrict__ g) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  double D = 0.0, M = 0.0;
+  for (int s = 0; s < split; ++s) {
+    const double2 e = partial[(int64_t)s * p_pad + j];
+    D += e.x;
+    M += e.y;
+  }
+  g[j] = v[j] * (D - u[j] * (fs->Rsum - M));
+}
+
+// ------------------------------------------------------------------------------------------------
+// a9: decode + standardise support columns into a [kc][n_pad] FP64 cache.
+
+__global__ __launch_bounds__(256) void k_decode_cols(const uint8_t* __restrict__ tiled, int64_t p_pad, int64_t n_pad,
+                                                     const int64_t* __restrict__ cols, int32_t kc,
+                                                     const double* __restrict__ u, const double* __restrict__ v,
+                                                     const double* __restrict__ mask, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= n_pad || q >= kc) return;
+  const int64_t j = cols[q];
+  const int64_t t = i / kTileSubjects;
+  const int grp = (int)((i % kTileSubjects) >> 2);
+  const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
+  const uint8_t byte = tiled[(t * p_pad + j) * kSegBytes + b];
+  const int code = (byte >> (2 * (i & 3))) & 3;
+  double x = 0.0;
+  if (mask[i] != 0.0 && code != 1) {
+    const double d = (code == 0) ? 0.0 : (double)(code - 1);
+    x = v[j] * (d - u[j]);
+  }
+  out[(int64_t)q * n_pad + i] = x;
+}
+
+// ------------------------------------------------------------------------------------------------
+// a6: top-k of |w| with ties to the lower index.
+// Level 0: 8192-bin histogram of key bits 62..50 (key = IEEE bits of |w|) -> threshold bucket.
+// Collect: keys above the bucket are selected; keys in it are candidates. The last block finds the
+// exact remainder among the candidates by radix select on the unique 96-bit key (|w| bits, ~index),
+// then sorts the k indices ascending.
+
+struct SrcW {
+  const double* w;
+  __device__ double at(int64_t j) const { return w[j]; }
+};
+struct SrcStep {
+  const double* beta;
+  const double* g;
+  double mu;
+  __device__ double at(int64_t j) const { return __dadd_rn(beta[j], __dmul_rn(mu, g[j])); }
+};
+
+__device__ __forceinline__ uint64_t abs_key(double w) { return (uint64_t)__double_as_longlong(fabs(w)); }
+
+// Returns (bucket, count above) for the need-th largest over nb bins held in LDS h; the owning
+// thread writes them to out[0], out[1]; all threads see them after the final barrier.
+__device__ void find_bucket(const uint32_t* h, int nb, uint32_t need, uint32_t* sc, uint32_t* out) {
+  const int per = nb / 1024;
+  const int t = threadIdx.x;
+  uint32_t local = 0;
+  for (int q = 0; q < per; ++q) local += h[t * per + q];
+  uint32_t cum = block_excl_suffix(local, sc);
+  for (int q = per - 1; q >= 0; --q) {
+    const uint32_t c = h[t * per + q];
+    if (cum < need && cum + c >= need) {
+      out[0] = (uint32_t)(t * per + q);
+      out[1] = cum;
+      out[2] = c;
+    }
+    cum += c;
+  }
+  __syncthreads();
+}
+
+template <class Src>
+__global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
+                                                    int32_t k, TopkWork tw) {
+  __shared__ uint32_t h[kTopkBins0];
+  __shared__ uint32_t sc[1024];
+  __shared__ uint32_t res[4];
+  __shared__ uint32_t ticket;
+  if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
+  for (int i = threadIdx.x; i < kTopkBins0; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * chunk, e = min(p, b + chunk);
+  bool bad = false;
+  for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) {
+    const double w = src.at(j);
+    bad |= !isfinite(w);
+    atomicAdd(&h[(uint32_t)(abs_key(w) >> 50) & (kTopkBins0 - 1)], 1u);
+  }
+  if (bad) atomicOr(&tw.state[3], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < kTopkBins0; i += blockDim.x)
+    if (h[i]) atomicAdd(&tw.hist[i], h[i]);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) ticket = atomicAdd(&tw.counters[0], 1u);
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  __threadfence();
+  for (int i = threadIdx.x; i < kTopkBins0; i += blockDim.x) {
+    h[i] = atomic_load_u32(&tw.hist[i]);
+    tw.hist[i] = 0u;
+  }
+  __syncthreads();
+  find_bucket(h, kTopkBins0, (uint32_t)k, sc, res);
+  if (threadIdx.x == 0) {
+    tw.state[0] = res[0];
+    tw.state[1] = res[1];
+    tw.state[2] = res[2];
+    tw.counters[0] = 0u;
+  }
+}
+
+template <class Src>
+__global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
+                                                       int32_t k, TopkWork tw, int64_t* __restrict__ support,
+                                                       double* __restrict__ vals) {
+  __shared__ uint32_t h[4096];
+  __shared__ uint32_t sc[1024];
+  __shared__ int32_t sel[kTopkMaxK];
+  __shared__ uint32_t res[4];
+  __shared__ uint32_t ticket, nsel_l;
+  if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
+  const uint32_t bucket = tw.state[0];
+  const int64_t b = (int64_t)blockIdx.x * chunk, e = min(p, b + chunk);
+  for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) {
+    const uint64_t key = abs_key(src.at(j));
+    const uint32_t bin = (uint32_t)(key >> 50) & (kTopkBins0 - 1);
+    if (bin > bucket) {
+      const uint32_t pos = atomicAdd(&tw.counters[2], 1u);
+      if (pos < (uint32_t)kTopkMaxK) tw.sel[pos] = (int32_t)j;
+    } else if (bin == bucket) {
+      const uint32_t pos = atomicAdd(&tw.counters[3], 1u);
+      tw.cand_key[pos] = key;
+      tw.cand_idx[pos] = (int32_t)j;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) ticket = atomicAdd(&tw.counters[1], 1u);
+  __syncthreads();
+  if (ticket != gridDim.x - 1) return;
+  __threadfence();
+
+  const uint32_t n_above = atomic_load_u32(&tw.counters[2]);
+  const uint32_t n_cand = atomic_load_u32(&tw.counters[3]);
+  for (uint32_t q = threadIdx.x; q < n_above; q += blockDim.x) sel[q] = __hip_atomic_load(&tw.sel[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t need = (uint32_t)k - n_above;
+
+  // Radix select of the need-th largest 96-bit key c = (|w| bits << 32) | ~index over candidates.
+  typedef unsigned __int128 u128;
+  u128 prefix = 0;
+  uint32_t need_c = need;
+  for (int L = 0; L < 8; ++L) {
+    const int shift = 84 - 12 * L;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
+      const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
+                     (u128)(0xFFFFFFFFu - (uint32_t)__hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if ((c >> (shift + 12)) == prefix) atomicAdd(&h[(uint32_t)(c >> shift) & 0xFFFu], 1u);
+    }
+    __syncthreads();
+    find_bucket(h, 4096, need_c, sc, res);
+    prefix = (prefix << 12) | (u128)res[0];
+    need_c -= res[1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nsel_l = n_above;
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
+    const int32_t idx = __hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
+                   (u128)(0xFFFFFFFFu - (uint32_t)idx);
+    if (c >= prefix) {
+      const uint32_t pos = atomicAdd(&nsel_l, 1u);
+      if (pos < (uint32_t)kTopkMaxK) sel[pos] = idx;
+    }
+  }
+  __syncthreads();
+  const uint32_t nsel = nsel_l;
+  if (nsel != (uint32_t)k && threadIdx.x == 0) atomicOr(&tw.state[3], 2u);
+  // bitonic sort of the k selected indices, ascending
+  int N = 1;
+  while (N < k) N <<= 1;
+  for (int q = threadIdx.x; q < N; q += blockDim.x)
+    if (q >= k) sel[q] = 0x7FFFFFFF;
+  __syncthreads();
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < N / 2; i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const int32_t a = sel[lo], c2 = sel[hi];
+        if ((a > c2) == asc) {
+          sel[lo] = c2;
+          sel[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    support[q] = sel[q];
+    if (vals) vals[q] = src.at(sel[q]);
+  }
+  if (threadIdx.x == 0) {
+    tw.counters[1] = 0u;
+    tw.counters[2] = 0u;
+    tw.counters[3] = 0u;
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Solve steps (one workgroup each; n and k are small next to the pass).
+
+__global__ __launch_bounds__(1024) void k_check_finite(const double* __restrict__ y, const float* __restrict__ Z, int64_t n,
+                                                       int32_t cz, const double* __restrict__ mask, FitState* fs) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int b = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (mask[i] == 0.0) continue;
+    if (!isfinite(y[i])) b = 1;
+    for (int c = 0; c < cz; ++c)
+      if (!isfinite(Z[(int64_t)c * n + i])) b = 1;
+  }
+  if (b) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) fs->nonfinite = bad;
+}
+
+// r = mask (y - A_{cols,C} b); loss = 1/2 ||r||^2 (eq. leastsquaresloss); covariate gradient gc = A_C^T r.
+__global__ __launch_bounds__(1024) void k_residual(const double* __restrict__ y, const double* __restrict__ X,
+                                                   const double* __restrict__ bvals, int32_t kc, Unpen U,
+                                                   const double* __restrict__ bc, const double* __restrict__ mask,
+                                                   int64_t n, int64_t n_pad, double* __restrict__ r, double* __restrict__ gc,
+                                                   double* __restrict__ trace, int32_t trace_idx, FitState* fs) {
+  __shared__ double sh[40];
+  __shared__ double bl[kTopkMaxK];
+  __shared__ double bcl[kMaxUnpenalized];
+  const int nc = U.cz + U.icpt;
+  for (int q = threadIdx.x; q < kc; q += blockDim.x) bl[q] = bvals[q];
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) bcl[q] = bc[q];
+  __syncthreads();
+  double rr = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double ri = 0.0;
+    if (mask[i] != 0.0) {
+      double s = 0.0;
+      for (int q = 0; q < kc; ++q) s += X[(int64_t)q * n_pad + i] * bl[q];
+      for (int c = 0; c < U.cz; ++c) s += (double)U.Z[(int64_t)c * n + i] * bcl[c];
+      if (U.icpt) s += 1.0 * bcl[U.cz];
+      ri = y[i] - s;
+    }
+    r[i] = ri;
+    rr += ri * ri;
+  }
+  const double loss = 0.5 * block_sum(rr, sh);
+  for (int c = 0; c < nc; ++c) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+      const double a = (c < U.cz) ? (double)U.Z[(int64_t)c * n + i] : 1.0;
+      s += (mask[i] != 0.0) ? a * r[i] : 0.0;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) gc[c] = s;
+  }
+  if (threadIdx.x == 0) {
+    trace[trace_idx] = loss;
+    fs->loss = loss;
+  }
+}
+
+// a5: mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2.
+__global__ __launch_bounds__(1024) void k_mu(const double* __restrict__ Xs, const int64_t* __restrict__ S, int32_t k,
+                                             const double* __restrict__ g, Unpen U, const double* __restrict__ gc,
+                                             const double* __restrict__ mask, int64_t n, int64_t n_pad, FitState* fs) {
+  __shared__ double sh[40];
+  __shared__ double gl[kTopkMaxK];
+  __shared__ double gcl[kMaxUnpenalized];
+  const int nc = U.cz + U.icpt;
+  for (int q = threadIdx.x; q < k; q += blockDim.x) gl[q] = g[S[q]];
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) gcl[q] = gc[q];
+  __syncthreads();
+  double num = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < k; ++q) num += gl[q] * gl[q];
+    for (int q = 0; q < nc; ++q) num += gcl[q] * gcl[q];
+  }
+  double dd = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (mask[i] == 0.0) continue;
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s += Xs[(int64_t)q * n_pad + i] * gl[q];
+    for (int c = 0; c < U.cz; ++c) s += (double)U.Z[(int64_t)c * n + i] * gcl[c];
+    if (U.icpt) s += 1.0 * gcl[U.cz];
+    dd += s * s;
+  }
+  const double den = block_sum(dd, sh);
+  if (threadIdx.x == 0) {
+    fs->num = num;
+    fs->den = den;
+    fs->den_zero = (den == 0.0);
+    fs->mu = (den == 0.0) ? 0.0 : num / den;
+  }
+}
+
+// a7: support comparison, unpenalised proposal bcp = bc + mu gc, and (if the support moved)
+// omega = (1-c)||Delta||^2 / ||A Delta||^2 over S u S+ u C with accept = mu < omega.
+__global__ __launch_bounds__(1024) void k_bt_check(const int64_t* __restrict__ S, const double* __restrict__ Xs,
+                                                   const int64_t* __restrict__ Sp, const double* __restrict__ Xp,
+                                                   const double* __restrict__ betap, int32_t k,
+                                                   const double* __restrict__ beta, Unpen U, const double* __restrict__ bc,
+                                                   const double* __restrict__ gc, double* __restrict__ bcp, double c,
+                                                   const double* __restrict__ mask, int64_t n, int64_t n_pad, FitState* fs,
+                                                   int32_t* __restrict__ uidx /* [2k] */, double* __restrict__ udel /* [2k] */) {
+  __shared__ double sh[40];
+  __shared__ double dcl[kMaxUnpenalized];
+  __shared__ int same_s, nu_s;
+  __shared__ double dd_s;
+  const int nc = U.cz + U.icpt;
+  const double mu = fs->mu;
+  if (threadIdx.x == 0) {
+    int same = 1;
+    for (int q = 0; q < k; ++q)
+      if (S[q] != Sp[q]) same = 0;
+    same_s = same;
+    double dd = 0.0;
+    int nu = 0;
+    if (!same) {
+      // merge S and S+ ascending; uidx encodes the column source: q (from Xs) or -(q+1) (from Xp)
+      int a = 0, b = 0;
+      while (a < k || b < k) {
+        if (b >= k || (a < k && S[a] < Sp[b])) {
+          const double d = 0.0 - beta[S[a]];
+          uidx[nu] = a;
+          udel[nu++] = d;
+          dd += d * d;
+          ++a;
+        } else if (a >= k || Sp[b] < S[a]) {
+          const double d = betap[b] - 0.0;
+          uidx[nu] = -(b + 1);
+          udel[nu++] = d;
+          dd += d * d;
+          ++b;
+        } else {
+          const double d = betap[b] - beta[S[a]];
+          uidx[nu] = -(b + 1);
+          udel[nu++] = d;
+          dd += d * d;
+          ++a;
+          ++b;
+        }
+      }
+    }
+    for (int q = 0; q < nc; ++q) {
+      const double np = bc[q] + mu * gc[q];
+      bcp[q] = np;
+      const double d = np - bc[q];
+      dcl[q] = d;
+      dd += d * d;
+    }
+    nu_s = nu;
+    dd_s = dd;
+  }
+  __syncthreads();
+  if (same_s) {
+    if (threadIdx.x == 0) {
+      fs->same = 1;
+      fs->accept = 1;
+      fs->omega = 0.0;
+    }
+    return;
+  }
+  const int nu = nu_s;
+  double sa = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    if (mask[i] == 0.0) continue;
+    double s = 0.0;
+    for (int q = 0; q < nu; ++q) {
+      const int src = uidx[q];
+      const double x = (src >= 0) ? Xs[(int64_t)src * n_pad + i] : Xp[(int64_t)(-src - 1) * n_pad + i];
+      s += x * udel[q];
+    }
+    for (int cc = 0; cc < U.cz; ++cc) s += (double)U.Z[(int64_t)cc * n + i] * dcl[cc];
+    if (U.icpt) s += 1.0 * dcl[U.cz];
+    sa += s * s;
+  }
+  const double dA = block_sum(sa, sh);
+  if (threadIdx.x == 0) {
+    const double omega = (1.0 - c) * dd_s / dA;
+    fs->same = 0;
+    fs->omega = omega;
+    fs->accept = (mu < omega);
+  }
+}
+
+__global__ void k_shrink(FitState* fs, double shrink) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) fs->mu = fs->mu * shrink;
+}
+
+// Convergence test (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf)), then beta <- beta+.
+// When S+ = S the union of the supports is S itself, so the infinity norms run over S+ and C.
+__global__ __launch_bounds__(1024) void k_commit(int64_t* __restrict__ S, const int64_t* __restrict__ Sp,
+                                                 const double* __restrict__ betap, int32_t k, double* __restrict__ beta,
+                                                 double* __restrict__ bc, const double* __restrict__ bcp, int32_t nc,
+                                                 double tol, FitState* fs) {
+  __shared__ double sh[40];
+  __shared__ int same_s;
+  if (threadIdx.x == 0) same_s = 1;
+  __syncthreads();
+  double dmax = 0.0, bmax = 0.0;
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    if (S[q] != Sp[q]) atomicAnd(&same_s, 0);
+    dmax = fmax(dmax, fabs(betap[q] - beta[Sp[q]]));
+    bmax = fmax(bmax, fabs(betap[q]));
+  }
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+    dmax = fmax(dmax, fabs(bcp[q] - bc[q]));
+    bmax = fmax(bmax, fabs(bcp[q]));
+  }
+  dmax = block_max(dmax, sh);
+  bmax = block_max(bmax, sh);
+  const int same = same_s;
+  const int conv = same && dmax <= tol * fmax(1.0, bmax);
+  __syncthreads();
+  for (int q = threadIdx.x; q < k; q += blockDim.x) beta[S[q]] = 0.0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    beta[Sp[q]] = betap[q];
+    S[q] = Sp[q];
+  }
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) bc[q] = bcp[q];
+  if (threadIdx.x == 0) {
+    fs->conv = conv;
+    fs->same = same;
+    fs->dmax = dmax;
+    fs->bmax = bmax;
+  }
+}
+
+__global__ void k_output(const int64_t* __restrict__ S, int32_t k, const double* __restrict__ beta,
+                         const double* __restrict__ bc, int32_t nc, int64_t* __restrict__ support,
+                         double* __restrict__ beta_S, double* __restrict__ beta_cov) {
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    support[q] = S[q];
+    beta_S[q] = beta[S[q]];
+  }
+  for (int q = threadIdx.x; q < nc; q += blockDim.x) beta_cov[q] = bc[q];
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ x, int32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0u;
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = val;
+}
+
+__global__ void k_scatter(const int64_t* __restrict__ idx, const double* __restrict__ vals, int32_t k,
+                          double* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < k) out[idx[q]] = vals[q];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Pass geometry: NS SNPs per lane and `split` subject ranges per SNP block, chosen so one launch
+// fills the 256 CUs about once (one 1024-thread workgroup per CU: 128 KB of LDS each).
+struct PassGeom {
+  int ns;
+  int split;
+  int tps;
+  int64_t groups;
+};
+
+PassGeom pass_geometry(const Layout& L, int precision) {
+  // 2 SNPs per lane: 4 would spill registers.
+  const int cand64[2] = {2, 1}, cand32[3] = {2, 1, 1};
+  const int* cand = precision == 1 ? cand32 : cand64;
+  const int ncand = precision == 1 ? 3 : 2;
+  PassGeom G{1, 1, (int)L.ntiles, 0};
+  for (int ci = 0; ci < ncand; ++ci) {
+    const int ns = cand[ci];
+    const int64_t groups = (L.p + (int64_t)kPassThreads * ns - 1) / ((int64_t)kPassThreads * ns);
+    if (groups * 2 >= 256 || ns == 1 || (groups >= 64 && L.ntiles >= 8)) {
+      int split = (int)std::max<int64_t>(1, 256 / groups);
+      split = (int)std::min<int64_t>(split, L.ntiles);
+      const int tps = (int)((L.ntiles + split - 1) / split);
+      split = (int)((L.ntiles + tps - 1) / tps);
+      G = PassGeom{ns, split, tps, groups};
+      break;
+    }
+  }
+  return G;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// Launchers
+
+hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L, uint8_t* tiled, hipStream_t st) {
+  const int64_t segs = L.ntiles * L.p_pad;
+  const int64_t blocks = (segs + 255) / 256;
+  hipLaunchKernelGGL(k_retile, dim3((unsigned)blocks), dim3(256), 0, st, raw, row_bytes, L.n, L.p, L.p_pad, L.ntiles, tiled);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
+                        hipStream_t st) {
+  const int64_t blocks = (L.p + 255) / 256;
+  hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad,
+                     L.ntiles, mask_bits, nT, u, v);
+  return hipGetLastError();
+}
+
+size_t gradient_partial_bytes(const Layout& L) {
+  size_t b = 0;
+  for (int prec = 0; prec < 2; ++prec) {
+    const PassGeom G = pass_geometry(L, prec);
+    if (G.split > 1) b = std::max(b, (size_t)G.split * (size_t)L.p_pad * sizeof(double2));
+  }
+  return b;
+}
+
+template <int NS>
+static void launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* r,
+                           const double* mask, int64_t nT, const double* u, const double* v, FitState* fs, double* g,
+                           double2* partial) {
+  if constexpr (NS <= 2) {
+    if (!f32) {
+      hipLaunchKernelGGL((k_pass<NS, false>), grid, dim3(kPassThreads), 0, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n,
+                         r, mask, nT, u, v, fs, g, partial);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_pass<NS, true>), grid, dim3(kPassThreads), 0, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n, r,
+                     mask, nT, u, v, fs, g, partial);
+}
+
+hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
+                           const double* u, const double* v, FitState* fs, int precision, double* g, double* partial,
+                           hipStream_t st) {
+  const PassGeom G = pass_geometry(L, precision);
+  const dim3 grid((unsigned)G.groups, (unsigned)G.split);
+  double2* part = (G.split > 1) ? reinterpret_cast<double2*>(partial) : nullptr;
+  const bool f32 = precision == 1;
+  const uint2* t4 = reinterpret_cast<const uint2*>(tiled);
+  if (G.ns == 4 && f32)
+    launch_pass_ns<4>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+  else if (G.ns == 2)
+    launch_pass_ns<2>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+  else
+    launch_pass_ns<1>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (part) {
+    hipLaunchKernelGGL(k_pass_finalize, dim3((unsigned)((L.p + 255) / 256)), dim3(256), 0, st, part, G.split, L.p, L.p_pad, u,
+                       v, fs, g);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_decode_cols(const uint8_t* tiled, const Layout& L, const int64_t* cols, int32_t kc, const double* u,
+                              const double* v, const double* mask, double* out, hipStream_t st) {
+  if (kc <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((L.n_pad + 255) / 256), (unsigned)kc);
+  hipLaunchKernelGGL(k_decode_cols, grid, dim3(256), 0, st, tiled, L.p_pad, L.n_pad, cols, kc, u, v, mask, out);
+  return hipGetLastError();
+}
+
+size_t topk_cand_capacity_bytes(int64_t p) { return (size_t)p * (sizeof(uint64_t) + sizeof(int32_t)); }
+
+static const int64_t kTopkChunk = 4096;
+
+template <class Src>
+static hipError_t launch_topk(Src src, const double* mu_ptr, int64_t p, int32_t k, const TopkWork& tw, int64_t* support,
+                              double* vals, hipStream_t st) {
+  const int64_t blocks = (p + kTopkChunk - 1) / kTopkChunk;
+  hipLaunchKernelGGL((k_topk_hist<Src>), dim3((unsigned)blocks), dim3(1024), 0, st, src, mu_ptr, p, kTopkChunk, k, tw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_topk_collect<Src>), dim3((unsigned)blocks), dim3(1024), 0, st, src, mu_ptr, p, kTopkChunk, k, tw,
+                     support, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_w(const double* w, int64_t p, int32_t k, const TopkWork& tw, int64_t* support, double* vals,
+                         hipStream_t st) {
+  return launch_topk(SrcW{w}, nullptr, p, k, tw, support, vals, st);
+}
+
+hipError_t launch_topk_step(const double* beta, const double* g, const double* mu, int64_t p, int32_t k, const TopkWork& tw,
+                            int64_t* support, double* vals, hipStream_t st) {
+  return launch_topk(SrcStep{beta, g, 0.0}, mu, p, k, tw, support, vals, st);
+}
+
+hipError_t launch_check_finite(const double* y, const float* Z, int64_t n, int32_t cz, const double* mask, FitState* fs,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(1024), 0, st, y, Z, n, cz, mask, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* y, const double* X, const double* bvals, int32_t kc, Unpen U, const double* bc,
+                           const double* mask, const Layout& L, double* r, double* gc, double* trace, int32_t trace_idx,
+                           FitState* fs, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, st, y, X, bvals, kc, U, bc, mask, L.n, L.n_pad, r, gc, trace,
+                     trace_idx, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_mu(const double* Xs, const int64_t* S, int32_t k, const double* g, Unpen U, const double* gc,
+                     const double* mask, const Layout& L, FitState* fs, hipStream_t st) {
+  hipLaunchKernelGGL(k_mu, dim3(1), dim3(1024), 0, st, Xs, S, k, g, U, gc, mask, L.n, L.n_pad, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_bt_check(const int64_t* S, const double* Xs, const int64_t* Sp, const double* Xp, const double* betap_vals,
+                           int32_t k, const double* beta, Unpen U, const double* bc, const double* gc, double* bcp, double c,
+                           const double* mask, const Layout& L, FitState* fs, double* work, hipStream_t st) {
+  int32_t* uidx = reinterpret_cast<int32_t*>(work);
+  double* udel = work + k;  // work holds >= 3k doubles: [2k int32 | 2k doubles]
+  hipLaunchKernelGGL(k_bt_check, dim3(1), dim3(1024), 0, st, S, Xs, Sp, Xp, betap_vals, k, beta, U, bc, gc, bcp, c, mask, L.n,
+                     L.n_pad, fs, uidx, udel);
+  return hipGetLastError();
+}
+
+hipError_t launch_shrink(FitState* fs, double shrink, hipStream_t st) {
+  hipLaunchKernelGGL(k_shrink, dim3(1), dim3(64), 0, st, fs, shrink);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(int64_t* S, const int64_t* Sp, const double* betap_vals, int32_t k, double* beta, double* bc,
+                         const double* bcp, int32_t nc, double tol, FitState* fs, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1024), 0, st, S, Sp, betap_vals, k, beta, bc, bcp, nc, tol, fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_output(const int64_t* S, int32_t k, const double* beta, const double* bc, int32_t nc, int64_t* support,
+                         double* beta_S, double* beta_cov, hipStream_t st) {
+  hipLaunchKernelGGL(k_output, dim3(1), dim3(1024), 0, st, S, k, beta, bc, nc, support, beta_S, beta_cov);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* x, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* x, int64_t n, double val, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, idx, vals, k, out);
+  return hipGetLastError();
+}
+
+}  // namespace iht

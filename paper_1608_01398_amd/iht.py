@@ -1,0 +1,235 @@
+"""ctypes binding of libiht.so (the C ABI in include/iht.h).
+
+Argument marshalling only: every step of the IHT path runs in the library's HIP kernels. torch
+supplies device memory and the current stream. There is no CPU fallback: if the library is not
+built, or no HIP device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libiht.so")
+
+OK, NOT_CONVERGED, STALLED = 0, 1, 2
+EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+HOST_PTR, DEVICE_PTR = 0, 1
+MAX_K = 4096
+
+EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
+           "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_project", "iht_fit", "iht_status_str",
+           "iht_last_error")
+
+
+class IHTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
+                ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libiht.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1608_01398_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    L.iht_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    L.iht_opts_default.restype = None
+    L.iht_geno_create.argtypes = [P, I64, I64, I64, I32, P, PP]
+    L.iht_geno_destroy.argtypes = [P]
+    L.iht_geno_shape.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    L.iht_stats_create.argtypes = [P, P, P, PP]
+    L.iht_stats_destroy.argtypes = [P]
+    L.iht_stats_read.argtypes = [P, P, P, P]
+    L.iht_gradient.argtypes = [P, P, P, P, I32, P]
+    L.iht_project.argtypes = [P, I64, I32, P, P, P]
+    L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
+    for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
+              "iht_stats_read", "iht_gradient", "iht_project", "iht_fit"):
+        getattr(L, f).restype = ctypes.c_int
+    L.iht_status_str.argtypes = [ctypes.c_int]
+    L.iht_status_str.restype = ctypes.c_char_p
+    L.iht_last_error.argtypes = []
+    L.iht_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, allow_warnings=False):
+    if rc < 0 or (rc > 0 and not allow_warnings):
+        L = load()
+        raise IHTError(rc, L.iht_last_error().decode() or L.iht_status_str(rc).decode())
+    return rc
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: the IHT library runs only on the GPU")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw):
+    o = Opts()
+    load().iht_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Geno:
+    """Resident, re-tiled PLINK genotype matrix (iht_geno_create)."""
+
+    def __init__(self, bed, n: int):
+        torch = _torch()
+        L = load()
+        self._h = ctypes.c_void_p()
+        if isinstance(bed, torch.Tensor):
+            if bed.dtype != torch.uint8 or bed.dim() != 2:
+                raise TypeError("bed must be a 2-D uint8 tensor [p, row_bytes]")
+            bed = bed.contiguous()
+            flags = DEVICE_PTR if bed.is_cuda else HOST_PTR
+            ptr = ctypes.c_void_p(bed.data_ptr())
+            p, rb = bed.shape
+            keep = bed
+        else:
+            keep = np.ascontiguousarray(bed, dtype=np.uint8)
+            p, rb = keep.shape
+            flags = HOST_PTR
+            ptr = keep.ctypes.data_as(ctypes.c_void_p)
+        _check(L.iht_geno_create(ptr, n, p, rb, flags, _stream(), ctypes.byref(self._h)))
+        del keep
+        self.n, self.p = int(n), int(p)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().iht_geno_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Stats:
+    """u, v over a subject subset (iht_stats_create)."""
+
+    def __init__(self, geno: Geno, subset=None):
+        L = load()
+        self.geno = geno
+        self._h = ctypes.c_void_p()
+        m = None
+        if subset is not None:
+            m = np.ascontiguousarray(subset, dtype=np.uint8)
+            if m.shape != (geno.n,):
+                raise ValueError("subset must have n entries")
+        _check(L.iht_stats_create(geno._h, None if m is None else m.ctypes.data_as(ctypes.c_void_p), _stream(),
+                                  ctypes.byref(self._h)))
+
+    def read(self):
+        torch = _torch()
+        u = torch.empty(self.geno.p, dtype=torch.float64, device="cuda")
+        v = torch.empty(self.geno.p, dtype=torch.float64, device="cuda")
+        _check(load().iht_stats_read(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()), _stream()))
+        return u, v
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().iht_stats_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gradient(geno: Geno, stats: Stats, r, precision: int = FP64, out=None):
+    """g = X_st^T r (iht_gradient). r: float64 CUDA tensor [n]."""
+    torch = _torch()
+    rp = _dev(r, torch.float64, (geno.n,), "r")
+    if out is None:
+        out = torch.empty(geno.p, dtype=torch.float64, device=r.device)
+    gp = _dev(out, torch.float64, (geno.p,), "out")
+    _check(load().iht_gradient(geno._h, stats._h, rp, gp, precision, _stream()))
+    return out
+
+
+def project(w, k: int):
+    """(support int64 [k] ascending, w_out [p]) of the k largest |w| (iht_project)."""
+    torch = _torch()
+    wp = _dev(w, torch.float64, None, "w")
+    p = w.shape[0]
+    sup = torch.empty(k, dtype=torch.int64, device=w.device)
+    out = torch.empty(p, dtype=torch.float64, device=w.device)
+    _check(load().iht_project(wp, p, k, ctypes.c_void_p(sup.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream()))
+    return sup, out
+
+
+def fit(geno: Geno, stats: Stats, y, k: int, Z=None, intercept: bool = True, **opts):
+    """Full IHT solve (iht_fit). y: float64 CUDA [n]; Z: float32 CUDA [c, n] (column-major [n x c]) or None.
+
+    Returns dict(status, support, beta_S, beta_cov, loss_trace, n_iter) with device tensors.
+    """
+    torch = _torch()
+    o = default_opts(**opts)
+    yp = _dev(y, torch.float64, (geno.n,), "y")
+    cz = 0
+    zp = None
+    if Z is not None:
+        cz = Z.shape[0]
+        zp = _dev(Z, torch.float32, (cz, geno.n), "Z")
+    nc = cz + (1 if intercept else 0)
+    dev = y.device
+    sup = torch.empty(k, dtype=torch.int64, device=dev)
+    bS = torch.empty(k, dtype=torch.float64, device=dev)
+    bc = torch.empty(max(nc, 1), dtype=torch.float64, device=dev)
+    trace = torch.full((o.max_iter + 1,), float("nan"), dtype=torch.float64, device=dev)
+    nit = ctypes.c_int32(0)
+    rc = load().iht_fit(geno._h, stats._h, yp, zp, cz, 1 if intercept else 0, k, ctypes.byref(o),
+                        ctypes.c_void_p(sup.data_ptr()), ctypes.c_void_p(bS.data_ptr()),
+                        ctypes.c_void_p(bc.data_ptr()) if nc else None, ctypes.c_void_p(trace.data_ptr()),
+                        ctypes.byref(nit), _stream())
+    _check(rc, allow_warnings=True)
+    it = nit.value
+    return dict(status=rc, support=sup, beta_S=bS, beta_cov=bc[:nc], loss_trace=trace[:it + 1], n_iter=it)

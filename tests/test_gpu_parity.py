@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same seeded inputs.
+
+Bars: u, v bitwise; FP64 gradient norm-wise relative error <= 1e-12 (and element-wise within 1e-12
+of ||g||_inf); FP32 gradient <= 2e-6 norm-wise; identical supports; beta within 1e-6 relative;
+loss traces within 1e-9 relative; identical iteration counts and status.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1608_01398_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1608_01398_amd import iht  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def rel(a, b):
+    d = np.linalg.norm(np.asarray(a) - np.asarray(b))
+    s = np.linalg.norm(np.asarray(b))
+    return d / s if s > 0 else d
+
+
+# ------------------------------------------------------------------ stats
+
+@pytest.mark.parametrize("n,p,subset", [(1, 5, None), (31, 9, None), (33, 8200, None), (1001, 300, None),
+                                        (1000, 10_000, None), (1000, 2000, 611), (2049, 700, 1024)])
+def test_stats_bitwise(n, p, subset):
+    say(f"stats n={n} p={p} subset={subset}")
+    bed, _ = synth.make_genotypes(n, p, seed=n + p)
+    m = synth.make_subset(n, subset, 5) if subset else None
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g, m)
+    u, v = (x.cpu().numpy() for x in s.read())
+    ur, vr = oracle.stats(bed, n, m)
+    assert np.array_equal(u, ur)
+    assert np.array_equal(v, vr)
+
+
+def test_stats_degenerate_columns():
+    n = 70
+    codes = np.zeros((5, n), dtype=np.uint8)
+    codes[0] = synth.CODE_HOM_A2
+    codes[1] = synth.CODE_MISSING
+    codes[2, :] = synth.CODE_HET
+    codes[2, ::3] = synth.CODE_MISSING
+    codes[3, ::2] = synth.CODE_HOM_A2
+    codes[4] = np.random.default_rng(0).integers(0, 4, n)
+    bed = synth.pack_codes(codes)
+    s = iht.Stats(iht.Geno(bed, n))
+    u, v = (x.cpu().numpy() for x in s.read())
+    ur, vr = oracle.stats(bed, n)
+    assert np.array_equal(u, ur) and np.array_equal(v, vr)
+
+
+# ------------------------------------------------------------------ gradient
+
+GRAD_CASES = [(1, 3), (5, 17), (32, 8192), (33, 8193), (100, 1), (1001, 1234), (1000, 10_000), (2500, 40_000)]
+
+
+@pytest.mark.parametrize("n,p", GRAD_CASES)
+@pytest.mark.parametrize("precision", [iht.FP64, iht.FP32])
+def test_gradient_parity(n, p, precision):
+    say(f"gradient n={n} p={p} precision={precision}")
+    bed, _ = synth.make_genotypes(n, p, seed=3 * n + p)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    rng = np.random.default_rng(n)
+    for shift in (0.0, 3.0):
+        r = rng.standard_normal(n) + shift
+        got = iht.gradient(g, s, dev(r), precision).cpu().numpy()
+        u, v = oracle.stats(bed, n)
+        ref = oracle.gradient(bed, n, u, v, r)
+        if np.linalg.norm(ref) == 0:
+            assert np.abs(got).max() < 1e-9
+            continue
+        if precision == iht.FP64:
+            assert rel(got, ref) <= 1e-12, rel(got, ref)
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        else:
+            assert rel(got, ref) <= 2e-6, rel(got, ref)
+
+
+def test_gradient_subset_ignores_rows_outside():
+    n, p = 1500, 5000
+    bed, _ = synth.make_genotypes(n, p, seed=77)
+    m = synth.make_subset(n, 1111, 9)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g, m)
+    r = np.random.default_rng(1).standard_normal(n)
+    r_bad = r.copy()
+    r_bad[m == 0] = np.nan
+    got = iht.gradient(g, s, dev(r_bad)).cpu().numpy()
+    u, v = oracle.stats(bed, n, m)
+    ref = oracle.gradient(bed, n, u, v, r, m)
+    assert rel(got, ref) <= 1e-12
+
+
+def test_gradient_identical_columns_bitwise():
+    n, p = 777, 4000
+    bed, _ = synth.make_genotypes(n, p, seed=5)
+    for a, b in [(0, 1), (3, 100), (17, 3999), (8, 2048)]:
+        bed[b] = bed[a]
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    r = np.random.default_rng(2).standard_normal(n)
+    for prec in (iht.FP64, iht.FP32):
+        got = iht.gradient(g, s, dev(r), prec).cpu().numpy()
+        for a, b in [(0, 1), (3, 100), (17, 3999), (8, 2048)]:
+            assert got[a] == got[b], (prec, a, b)
+
+
+def test_gradient_deterministic():
+    n, p = 3000, 20_000
+    bed, _ = synth.make_genotypes(n, p, seed=6)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    r = dev(np.random.default_rng(3).standard_normal(n))
+    a = iht.gradient(g, s, r).cpu().numpy()
+    b = iht.gradient(g, s, r).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------ projection
+
+@pytest.mark.parametrize("p,k", [(1, 1), (10, 10), (257, 7), (5000, 64), (100_000, 20), (300_000, 4096)])
+def test_project_parity(p, k):
+    say(f"project p={p} k={k}")
+    rng = np.random.default_rng(p + k)
+    w = np.round(rng.standard_normal(p), 2)  # many exact ties
+    w[rng.integers(0, p, max(1, p // 10))] *= -1
+    sup, out = iht.project(dev(w), k)
+    rs, ro = oracle.project(w, k)
+    assert np.array_equal(sup.cpu().numpy(), rs)
+    assert np.array_equal(out.cpu().numpy(), ro)
+
+
+def test_project_all_equal_and_zeros():
+    for w in (np.zeros(10_000), np.ones(12_345), np.concatenate([np.zeros(5000), [3.0, -3.0], np.zeros(5000)])):
+        for k in (1, 2, 3, 100):
+            sup, _ = iht.project(dev(w), k)
+            rs, _ = oracle.project(w, k)
+            assert np.array_equal(sup.cpu().numpy(), rs)
+
+
+def test_project_rejects_nonfinite():
+    w = np.ones(100)
+    w[50] = np.inf
+    with pytest.raises(iht.IHTError) as e:
+        iht.project(dev(w), 3)
+    assert e.value.code == iht.ENONFINITE
+
+
+# ------------------------------------------------------------------ fit
+
+def run_both(prob, k, Z=None, subset=None, precision=iht.FP64, **opts):
+    n = prob["n"]
+    g = iht.Geno(prob["bed"], n)
+    s = iht.Stats(g, subset)
+    res = iht.fit(g, s, dev(prob["y"]), k, Z=None if Z is None else dev(Z, torch.float32), intercept=True,
+                  precision=precision, **opts)
+    got = {key: (val.cpu().numpy() if hasattr(val, "cpu") else val) for key, val in res.items()}
+    ref = oracle.fit(prob["bed"], n, prob["y"], k, Z=Z, intercept=True, subset=subset, **opts)
+    return got, ref
+
+
+def assert_fit_parity(got, ref, same_iters=True):
+    assert got["status"] == ref["status"], (got["status"], ref["status"])
+    assert np.array_equal(got["support"], ref["support"]), (got["support"], ref["support"])
+    scale = np.abs(ref["beta_S"]).max()
+    assert np.abs(got["beta_S"] - ref["beta_S"]).max() <= 1e-6 * scale
+    if len(ref["beta_cov"]):
+        np.testing.assert_allclose(got["beta_cov"], ref["beta_cov"], rtol=1e-6, atol=1e-6 * scale)
+    if same_iters:
+        assert got["n_iter"] == ref["n_iter"], (got["n_iter"], ref["n_iter"])
+        np.testing.assert_allclose(got["loss_trace"], ref["loss_trace"], rtol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fit_c1_parity(seed):
+    prob = synth.make_problem("c1", seed)
+    say(f"fit c1 seed={seed}")
+    got, ref = run_both(prob, prob["k"])
+    assert_fit_parity(got, ref)
+
+
+def test_fit_covariates_and_subset():
+    prob = synth.make_problem("c5", seed=4, n=1200, p=6000)
+    m = synth.make_subset(prob["n"], 900, 3)
+    say("fit covariates+subset")
+    got, ref = run_both(prob, 12, Z=prob["Z"], subset=m)
+    assert_fit_parity(got, ref)
+
+
+@pytest.mark.parametrize("k", [1, 3, 50])
+def test_fit_small_k_and_ragged(k):
+    prob = synth.make_problem("c1", seed=9, n=1001, p=8193)
+    say(f"fit ragged k={k}")
+    got, ref = run_both(prob, k)
+    assert_fit_parity(got, ref)
+
+
+def test_fit_backtracking_ld_instance():
+    rng = np.random.default_rng(5)
+    n, p = 600, 3000
+    bed, q = synth.make_genotypes(n, p, 5)
+    codes = synth.unpack_codes(bed, n)
+    for a in range(0, 40, 2):
+        flip = rng.random(n) < 0.03
+        codes[a + 1] = np.where(flip, codes[a + 7], codes[a])
+    bed = synth.pack_codes(codes)
+    y, *_ = synth.make_trait(bed, n, q, 10, (0.3, 0.8), 5)
+    prob = dict(bed=bed, n=n, p=p, y=y)
+    for k in (5, 12):
+        got, ref = run_both(prob, k, max_iter=300)
+        assert_fit_parity(got, ref)
+        got2, ref2 = run_both(prob, k, max_backtrack=0, max_iter=300)
+        assert_fit_parity(got2, ref2)
+
+
+def test_fit_status_max_iter_and_nonfinite():
+    prob = synth.make_problem("c1", seed=2)
+    got, ref = run_both(prob, 10, max_iter=1)
+    assert got["status"] == iht.NOT_CONVERGED
+    assert_fit_parity(got, ref)
+    g = iht.Geno(prob["bed"], prob["n"])
+    s = iht.Stats(g)
+    y = prob["y"].copy()
+    y[7] = np.nan
+    with pytest.raises(iht.IHTError) as e:
+        iht.fit(g, s, dev(y), 10)
+    assert e.value.code == iht.ENONFINITE
+
+
+def test_fit_deterministic():
+    prob = synth.make_problem("c1", seed=3)
+    g = iht.Geno(prob["bed"], prob["n"])
+    s = iht.Stats(g)
+    y = dev(prob["y"])
+    a = iht.fit(g, s, y, 10)
+    b = iht.fit(g, s, y, 10)
+    for key in ("support", "beta_S", "loss_trace"):
+        assert torch.equal(a[key], b[key])
