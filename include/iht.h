@@ -78,7 +78,7 @@ void iht_opts_default(iht_opts *o);
  * Upload (if IHT_HOST_PTR) and re-tile a PLINK SNP-major matrix once onto the current device
  * (Methods, "Parallelization of IHT": the compressed matrix is pushed to the device once).
  *   bed        [p][row_bytes] bytes, host or device memory per `flags`; only read during the call.
- *   n, p       subjects and SNPs, n >= 1, p >= 1, n <= 2^24, p <= 2^31 - 8192.
+ *   n, p       subjects and SNPs, n >= 1, p >= 1, n <= 2^24, p <= 2^28 - 8192.
  *   row_bytes  >= ceil(n/4); bits past subject n-1 are ignored.
  *   out        receives the handle.
  * Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. The stream is synchronised before returning.

@@ -154,7 +154,7 @@ int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes,
   if (!out) return fail(IHT_EINVAL, "iht_geno_create: out is NULL");
   *out = nullptr;
   if (!bed) return fail(IHT_EINVAL, "iht_geno_create: bed is NULL");
-  if (n < 1 || p < 1 || n > (int64_t(1) << 24) || p > (int64_t(1) << 31) - kSnpAlign)
+  if (n < 1 || p < 1 || n > (int64_t(1) << 24) || p > (int64_t(1) << 28) - kSnpAlign)
     return fail(IHT_EINVAL, "iht_geno_create: n or p out of range");
   if (row_bytes < (n + 3) / 4) return fail(IHT_EINVAL, "iht_geno_create: row_bytes < ceil(n/4)");
   if (flags != IHT_HOST_PTR && flags != IHT_DEVICE_PTR) return fail(IHT_EINVAL, "iht_geno_create: bad flags");

@@ -187,20 +187,24 @@ struct Tab<true> {
 __device__ __forceinline__ double dose_of(int c) { return c == 3 ? 2.0 : (c == 2 ? 1.0 : 0.0); }
 __device__ __forceinline__ double miss_of(int c) { return c == 1 ? 1.0 : 0.0; }
 
-// Builder thread (group gb, byte values low7 and low7 + 128): T(v) = sum_k dose(c_k(v)) r_k and
-// M(v) = sum_k [c_k(v) missing] r_k over the group's 4 subjects, summed in subject order.
-template <bool F32>
-__device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int low7, const double (&r)[4]) {
-  const int c0 = low7 & 3, c1 = (low7 >> 2) & 3, c2 = (low7 >> 4) & 3;
+// Builder thread: group gb = tid % 8 and byte values v = tid / 8 + (threads / 8) m. Entries are
+// T(v) = sum_k dose(c_k(v)) r_k and M(v) = sum_k [c_k(v) missing] r_k over the group's 4 subjects,
+// summed in subject order. 512 threads: 4 values per thread (the 4th subject's code varies);
+// 1024 threads: 2 values (the high bit of the 4th subject's code varies).
+template <bool F32, int THREADS>
+__device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int vb, const double (&r)[4]) {
+  static_assert(THREADS == 512 || THREADS == 1024, "builder mapping");
+  constexpr int EPT = 2048 / THREADS;
+  const int c0 = vb & 3, c1 = (vb >> 2) & 3, c2 = (vb >> 4) & 3;
   const double T6 = (dose_of(c0) * r[0] + dose_of(c1) * r[1]) + dose_of(c2) * r[2];
   const double M6 = (miss_of(c0) * r[0] + miss_of(c1) * r[1]) + miss_of(c2) * r[2];
-  const int b6 = low7 >> 6;  // low bit of the fourth subject's code
 #pragma unroll
-  for (int m = 0; m < 2; ++m) {
-    const int c3 = b6 | (m << 1);
-    const double T = T6 + dose_of(c3) * r[3];
-    const double M = M6 + miss_of(c3) * r[3];
-    char* row = lds + ((low7 + 128 * m) << 8) + buf * 128;
+  for (int m = 0; m < EPT; ++m) {
+    const int v = vb + (THREADS / 8) * m;
+    const int c3 = v >> 6;
+    const double T = (c3 == 0 || c3 == 1) ? T6 : T6 + dose_of(c3) * r[3];
+    const double M = (c3 == 1) ? M6 + r[3] : M6;
+    char* row = lds + (v << 8) + buf * 128;
     if constexpr (F32) {
       const float2 e = make_float2((float)T, (float)M);
       *reinterpret_cast<float2*>(row + (gb << 3)) = e;
@@ -215,7 +219,7 @@ __device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int lo
 // The pairings {b, b+4}, {b, b+2}, {0, 1} of byte positions map to the same pairings of subject
 // groups for every rotation, and + is commutative, so the tile sum depends only on the column's
 // bytes: identical columns give bitwise identical gradients.
-template <bool F32, int BUF>
+template <bool F32>
 __device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)[2], const uint2 d, double& accT,
                                          double& accM) {
   using acc_t = typename std::conditional<F32, float, double>::type;
@@ -229,7 +233,7 @@ __device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)
       const uint32_t dw = h ? d.y : d.x;
       // byte0 = slot offset of step b, byte1 = packed value, bytes 2-3 = 0
       const uint32_t sel = (4u + (uint32_t)c) | ((uint32_t)c << 8) | (0x0Cu << 16) | (0x0Cu << 24);
-      const uint32_t addr = __builtin_amdgcn_perm(offs[h], dw, sel) + BUF * 128;
+      const uint32_t addr = __builtin_amdgcn_perm(offs[h], dw, sel);
       if constexpr (F32) {
         const float2 e = *reinterpret_cast<const float2*>(lds + addr);
         vt[h] = e.x;
@@ -248,30 +252,56 @@ __device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)
   accM += (double)((PM[0] + PM[2]) + (PM[1] + PM[3]));
 }
 
-// Residual of the 4 subjects of group gb in tile t, centred on the subject-set mean, 0 outside it.
-__device__ __forceinline__ void group_residual(const double* __restrict__ r, const double* __restrict__ mask, int64_t n,
-                                               int t, int gb, double mean, double (&out)[4]) {
-  const int64_t i0 = (int64_t)t * kTileSubjects + gb * 4;
-  const double4 m4 = *reinterpret_cast<const double4*>(mask + i0);
-  const double mk[4] = {m4.x, m4.y, m4.z, m4.w};
+constexpr int kRing = 4;               // tiles of packed data held in registers (prefetch distance 3)
+constexpr int kMaxTilesPerBlock = 376;  // residual staged in LDS: 376 * 32 * 8 B next to the 64 KB table
+
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+// Packed bytes of tile t for the lane's NS SNPs: one buffer resource per tile (scalar base), one
+// 32-bit lane offset. Tiles past the block's range get a zero-size resource: the loads return zeros
+// without touching memory (and those tiles have all-zero tables).
+template <int NS>
+__device__ __forceinline__ void load_tile(uint2 (&d)[NS], const uint2* __restrict__ tiled, int64_t p_pad, uint32_t voff,
+                                          int t, int t1) {
+  const bool real = t < t1;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint2*>(tiled + (int64_t)(real ? t : 0) * p_pad), 0, real ? 0x7FFFFFFF : 0, 0x00020000);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) out[k] = (i0 + k < n && mk[k] != 0.0) ? r[i0 + k] - mean : 0.0;
+  for (int s = 0; s < NS; ++s) {
+    const v2u x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + (uint32_t)(s * kPassThreads * 8), 0, 2 /* nt */);
+    d[s] = make_uint2(x.x, x.y);
+  }
 }
 
 template <int NS, bool F32>
-__global__ __launch_bounds__(1024, 1) void k_pass(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
+__global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
                                                   int32_t tps, int64_t n, const double* __restrict__ r,
                                                   const double* __restrict__ mask, int64_t nT, const double* __restrict__ u,
                                                   const double* __restrict__ v, FitState* __restrict__ fs,
                                                   double* __restrict__ g, double2* __restrict__ partial) {
-  __shared__ __attribute__((aligned(16))) uint4 lds_raw[4096];  // 256 rows x 256 B
-  __shared__ double red[40];
-  char* lds = reinterpret_cast<char*>(lds_raw);
+  // The table sits at LDS address 0 (this kernel has no static LDS), so a v_perm result is the
+  // full lookup address; the residual of the block's subjects and the reduction scratch follow it.
+  extern __shared__ __attribute__((aligned(16))) uint4 dyn_lds[];
+  char* lds = reinterpret_cast<char*>(dyn_lds);               // 256 rows x 256 B table
+  double* red = reinterpret_cast<double*>(lds + 65536);      // 40 doubles of reduction scratch
+  double* rl = red + 40;                                      // centred residual of this block's subjects
   constexpr uint32_t GS = Tab<F32>::kGroupShift;
 
   const int tid = threadIdx.x;
-  // Centre the residual over the subject set: X_st^T 1_T = 0, so the gradient is unchanged and
-  // the table entries stay small. R = sum of the centred residual (~0) enters the epilogue.
+  const int t0 = blockIdx.y * tps;
+  const int t1 = min(ntiles, t0 + tps);
+  const int64_t i0 = (int64_t)t0 * kTileSubjects;
+  const int64_t nsub = (int64_t)(t1 - t0) * kTileSubjects;
+
+  const int64_t jb = (int64_t)blockIdx.x * (kPassThreads * NS) + tid;
+  const uint32_t voff = (uint32_t)(jb * 8);
+  // first tiles in flight before anything else
+  uint2 d[kRing][NS];
+#pragma unroll
+  for (int q = 0; q < kRing - 1; ++q) load_tile<NS>(d[q], tiled, p_pad, voff, t0 + q, t1);
+
+  // Centre the residual over the subject set: X_st^T 1_T = 0, so the gradient is unchanged and the
+  // table entries stay small. R = sum of the centred residual (~0) enters the epilogue.
   double mean, R;
   {
     double s1 = 0.0;
@@ -284,78 +314,77 @@ __global__ __launch_bounds__(1024, 1) void k_pass(const uint2* __restrict__ tile
       fs->mean = mean;
       fs->Rsum = R;
     }
+    for (int64_t q = tid; q < nsub; q += kPassThreads) {
+      const int64_t i = i0 + q;
+      rl[q] = (i < n && mask[i] != 0.0) ? r[i] - mean : 0.0;
+    }
   }
-  const int64_t jb = (int64_t)blockIdx.x * (kPassThreads * NS) + tid;
-  const int t0 = blockIdx.y * tps;
-  const int t1 = min(ntiles, t0 + tps);
-  const uint32_t rot = (uint32_t)tid & 7u;  // == j & 7 for every SNP slot of this lane
 
-  // offs[h] byte c = slot offset of step b = c + 4h: group (b + rot) mod 8.
-  uint32_t offs[2];
+  const uint32_t rot = (uint32_t)tid & 7u;  // == j & 7 for every SNP slot of this lane
+  // offs[B][h] byte c = offset inside a table row of step b = c + 4h in LDS buffer B:
+  // B * 128 + copy base + (group (b + rot) mod 8) * entry size.
+  uint32_t offs[2][2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    uint32_t o = 0;
+  for (int B = 0; B < 2; ++B)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) o |= (Tab<F32>::slot_base(tid) + ((((uint32_t)(c + 4 * h) + rot) & 7u) << GS)) << (8 * c);
-    offs[h] = o;
-  }
-  const int gb = tid & 7, low7 = tid >> 3;
-  const uint2* src = tiled + jb;
+    for (int h = 0; h < 2; ++h) {
+      uint32_t o = 0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        o |= ((uint32_t)B * 128u + Tab<F32>::slot_base(tid) + ((((uint32_t)(c + 4 * h) + rot) & 7u) << GS)) << (8 * c);
+      offs[B][h] = o;
+    }
+  const int gb = tid & 7, vb = tid >> 3;
+
+  // residuals of builder group gb in tile t (zero past the block's range -> all-zero table)
+  auto group_r = [&](int t, double (&rr)[4]) {
+    const bool live = t < t1;
+    const int q = live ? (t - t0) * kTileSubjects + gb * 4 : 0;
+    const double4 x = *reinterpret_cast<const double4*>(rl + q);
+    rr[0] = live ? x.x : 0.0;
+    rr[1] = live ? x.y : 0.0;
+    rr[2] = live ? x.z : 0.0;
+    rr[3] = live ? x.w : 0.0;
+  };
 
   double accT[NS], accM[NS];
-  uint2 dA[NS], dB[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     accT[s] = 0.0;
     accM[s] = 0.0;
-    dA[s] = stream_load2(src + (int64_t)t0 * p_pad + s * kPassThreads);
   }
+  __syncthreads();  // residual staged
   {
     double rr[4];
-    group_residual(r, mask, n, t0, gb, mean, rr);
-    build_entries<F32>(lds, 0, gb, low7, rr);
+    group_r(t0, rr);
+    build_entries<F32, kPassThreads>(lds, 0, gb, vb, rr);
   }
   __syncthreads();
 
-  // Two tiles per trip with explicit register sets A (even tiles, buffer 0) and B (odd tiles,
-  // buffer 1): each half prefetches the next tile and builds its table while the current tile is
-  // consumed. A prefetch past the last tile reads one shared 8-byte word instead (no branch).
-  const int npairs = (t1 - t0) >> 1;
-  for (int pr = 0; pr < npairs; ++pr) {
-    const int t = t0 + 2 * pr;
-    {
-      double rr[4];
-      group_residual(r, mask, n, t + 1, gb, mean, rr);
+  // Tile t uses ring slot (t - t0) % 4 and LDS buffer (t - t0) % 2, both compile-time in the
+  // unrolled body. Each step prefetches tile t+3, builds the table of tile t+1 and consumes tile t.
+  // Tiles past t1 (at most 3 in the last trip) have all-zero tables and add exact zeros.
+  const int trips = (t1 - t0 + kRing - 1) / kRing;
+  for (int trip = 0; trip < trips; ++trip) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) dB[s] = stream_load2(src + (int64_t)(t + 1) * p_pad + s * kPassThreads);
-      build_entries<F32>(lds, 1, gb, low7, rr);
+    for (int uu = 0; uu < kRing; ++uu) {
+      const int t = t0 + trip * kRing + uu;
+      load_tile<NS>(d[(uu + kRing - 1) % kRing], tiled, p_pad, voff, t + kRing - 1, t1);
+      {
+        double rr[4];
+        group_r(t + 1, rr);
+        build_entries<F32, kPassThreads>(lds, (uu + 1) & 1, gb, vb, rr);
+      }
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        tile_sum<F32, 0>(lds, offs, dA[s], accT[s], accM[s]);
+        tile_sum<F32>(lds, offs[uu & 1], d[uu][s], accT[s], accM[s]);
+#if IHT_PASS_SNP_BARRIER
         __builtin_amdgcn_sched_barrier(0);
+#endif
       }
       __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
     }
-    {
-      const bool real = t + 2 < t1;
-      const int tc = real ? t + 2 : t1 - 1;
-      double rr[4];
-      group_residual(r, mask, n, tc, gb, mean, rr);
-      const uint2* nx = real ? src + (int64_t)tc * p_pad : tiled;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) dA[s] = stream_load2(real ? nx + s * kPassThreads : nx);
-      build_entries<F32>(lds, 0, gb, low7, rr);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        tile_sum<F32, 1>(lds, offs, dB[s], accT[s], accM[s]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      __syncthreads();
-    }
-  }
-  if ((t1 - t0) & 1) {  // last tile of an odd count: already in A / buffer 0
-#pragma unroll
-    for (int s = 0; s < NS; ++s) tile_sum<F32, 0>(lds, offs, dA[s], accT[s], accM[s]);
   }
 
 #pragma unroll
@@ -859,25 +888,28 @@ struct PassGeom {
 };
 
 PassGeom pass_geometry(const Layout& L, int precision) {
-  // 2 SNPs per lane: 4 would spill registers.
-  const int cand64[2] = {2, 1}, cand32[3] = {2, 1, 1};
+  const int cand64[3] = {4, 2, 1}, cand32[3] = {4, 2, 1};
   const int* cand = precision == 1 ? cand32 : cand64;
-  const int ncand = precision == 1 ? 3 : 2;
+  const int ncand = 3;
+  const int64_t min_split = (L.ntiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock;
   PassGeom G{1, 1, (int)L.ntiles, 0};
   for (int ci = 0; ci < ncand; ++ci) {
     const int ns = cand[ci];
     const int64_t groups = (L.p + (int64_t)kPassThreads * ns - 1) / ((int64_t)kPassThreads * ns);
     if (groups * 2 >= 256 || ns == 1 || (groups >= 64 && L.ntiles >= 8)) {
-      int split = (int)std::max<int64_t>(1, 256 / groups);
-      split = (int)std::min<int64_t>(split, L.ntiles);
+      int64_t split = std::max<int64_t>(1, 256 / groups);
+      split = std::min<int64_t>(split, L.ntiles);
+      split = std::max<int64_t>(split, min_split);
       const int tps = (int)((L.ntiles + split - 1) / split);
-      split = (int)((L.ntiles + tps - 1) / tps);
-      G = PassGeom{ns, split, tps, groups};
+      split = (L.ntiles + tps - 1) / tps;
+      G = PassGeom{ns, (int)split, tps, groups};
       break;
     }
   }
   return G;
 }
+
+size_t pass_lds_bytes(const PassGeom& G) { return 65536 + 40 * sizeof(double) + (size_t)G.tps * kTileSubjects * sizeof(double); }
 
 }  // namespace
 
@@ -908,19 +940,29 @@ size_t gradient_partial_bytes(const Layout& L) {
   return b;
 }
 
-template <int NS>
-static void launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* r,
-                           const double* mask, int64_t nT, const double* u, const double* v, FitState* fs, double* g,
-                           double2* partial) {
-  if constexpr (NS <= 2) {
-    if (!f32) {
-      hipLaunchKernelGGL((k_pass<NS, false>), grid, dim3(kPassThreads), 0, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n,
-                         r, mask, nT, u, v, fs, g, partial);
-      return;
-    }
+template <int NS, bool F32>
+static void launch_pass_one(dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* r,
+                            const double* mask, int64_t nT, const double* u, const double* v, FitState* fs, double* g,
+                            double2* partial) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<NS, F32>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              65536 + 40 * (int)sizeof(double) + kMaxTilesPerBlock * kTileSubjects * (int)sizeof(double));
+    attr_set = true;
   }
-  hipLaunchKernelGGL((k_pass<NS, true>), grid, dim3(kPassThreads), 0, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n, r,
+  hipLaunchKernelGGL((k_pass<NS, F32>), grid, dim3(kPassThreads), lds, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n, r,
                      mask, nT, u, v, fs, g, partial);
+}
+
+template <int NS>
+static void launch_pass_ns(bool f32, dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps,
+                           const double* r, const double* mask, int64_t nT, const double* u, const double* v, FitState* fs,
+                           double* g, double2* partial) {
+  if (!f32) {
+    launch_pass_one<NS, false>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial);
+    return;
+  }
+  launch_pass_one<NS, true>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial);
 }
 
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
@@ -931,12 +973,13 @@ hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* 
   double2* part = (G.split > 1) ? reinterpret_cast<double2*>(partial) : nullptr;
   const bool f32 = precision == 1;
   const uint2* t4 = reinterpret_cast<const uint2*>(tiled);
-  if (G.ns == 4 && f32)
-    launch_pass_ns<4>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+  const size_t lds = pass_lds_bytes(G);
+  if (G.ns == 4)
+    launch_pass_ns<4>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
   else if (G.ns == 2)
-    launch_pass_ns<2>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+    launch_pass_ns<2>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
   else
-    launch_pass_ns<1>(f32, grid, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+    launch_pass_ns<1>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (part) {

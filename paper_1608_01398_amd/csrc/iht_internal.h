@@ -14,7 +14,13 @@ namespace iht {
 constexpr int kTileSubjects = 32;
 constexpr int kSegBytes = 8;
 constexpr int64_t kSnpAlign = 8192;  // p is padded to this (covers 1024 lanes x 8 SNPs per lane)
-constexpr int kPassThreads = 1024;
+#ifndef IHT_PASS_THREADS
+#define IHT_PASS_THREADS 512
+#endif
+#ifndef IHT_PASS_SNP_BARRIER
+#define IHT_PASS_SNP_BARRIER 1
+#endif
+constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (64 KB table + residual in LDS)
 constexpr int kSmallThreads = 1024;
 constexpr int kMaxUnpenalized = 64;  // dense covariates + intercept
 constexpr int kTopkBins0 = 8192;     // first-level histogram: key bits 62..50
