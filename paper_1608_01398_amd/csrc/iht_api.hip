@@ -284,7 +284,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
   if (pb) HIPCHK(G->partial.ensure(pb));
   FitState* fs = G->state.as<FitState>();
   HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask.as<double>(), s->nT, s->u.as<double>(), s->v.as<double>(), fs,
-                         precision, grad, G->partial.as<double>(), st));
+                         precision, grad, G->partial.as<double>(), nullptr, st));
   return IHT_OK;
 }
 
@@ -391,14 +391,19 @@ int iht_fit(const iht_geno* g, const iht_stats* s, const double* y, const float*
   HIPCHK(launch_fill(bc, kMaxUnpenalized, 0.0, st));
   HIPCHK(launch_zero_u32(W.topk.tw.state + 3, 1, st));
   HIPCHK(launch_check_finite(y, Z, L.n, cz, mask, fs, st));
-  HIPCHK(launch_residual(y, Xs, W.betap.as<double>(), 0, U, bc, mask, L, W.r.as<double>(), gc, loss_trace, 0, fs, st));
-  HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), st));
+  HIPCHK(launch_residual(y, Xs, W.betap.as<double>(), 0, U, bc, mask, L, W.r.as<double>(), gc, loss_trace, 0, fs, nullptr, st));
+  HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), nullptr, st));
   HIPCHK(launch_fill(&fs->mu, 1, 1.0, st));  // top-k of |0 + 1*g| = |g|
   HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, S, nullptr, st));
   HIPCHK(launch_decode_cols(tiled, L, S, k, u, v, mask, Xs, st));
   if (int rc = read_state()) return rc;
   if (h.nonfinite) return fail(IHT_ENONFINITE, "iht_fit: non-finite y or Z inside the subject set");
 
+  // One iteration is enqueued speculatively: step size, proposal, backtracking test, and then the
+  // residual/loss, gradient and commit kernels gated on the device flag fs->go (proposal accepted
+  // or support unchanged). One host synchronisation per iteration reads the flags; only when the
+  // proposal needed backtracking does the host run the halving loop and re-enqueue the gated tail.
+  const int32_t* go = &fs->go;
   int status = IHT_NOT_CONVERGED;
   int32_t m = 0;
   uint32_t terr = 0;
@@ -408,35 +413,43 @@ int iht_fit(const iht_geno* g, const iht_stats* s, const double* y, const float*
     HIPCHK(launch_decode_cols(tiled, L, Sp, k, u, v, mask, Xp, st));
     HIPCHK(launch_bt_check(S, Xs, Sp, Xp, W.betap.as<double>(), k, beta, U, bc, gc, bcp, o.c, mask, L, fs, W.bt.as<double>(),
                            st));
+    HIPCHK(launch_residual(y, Xp, W.betap.as<double>(), k, U, bcp, mask, L, W.r.as<double>(), gc, loss_trace, m + 1, fs, go,
+                           st));
+    HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), go, st));
+    HIPCHK(launch_commit(S, Sp, W.betap.as<double>(), k, beta, bc, bcp, nc, o.tol, fs, go, st));
     if (int rc = read_state()) return rc;
     if (h.den_zero) {
       status = IHT_OK;
       break;
     }
-    int nbt = 0;
-    bool stalled = false;
-    while (!h.same && !h.accept) {
-      if (nbt == o.max_backtrack) {
-        stalled = true;
+    if (!h.go) {
+      int nbt = 0;
+      bool stalled = false;
+      while (!h.same && !h.accept) {
+        if (nbt == o.max_backtrack) {
+          stalled = true;
+          break;
+        }
+        HIPCHK(launch_shrink(fs, o.shrink, st));
+        ++nbt;
+        HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, Sp, W.betap.as<double>(), st));
+        HIPCHK(launch_decode_cols(tiled, L, Sp, k, u, v, mask, Xp, st));
+        HIPCHK(launch_bt_check(S, Xs, Sp, Xp, W.betap.as<double>(), k, beta, U, bc, gc, bcp, o.c, mask, L, fs,
+                               W.bt.as<double>(), st));
+        if (int rc = read_state()) return rc;
+      }
+      if (stalled) {
+        status = IHT_STALLED;
         break;
       }
-      HIPCHK(launch_shrink(fs, o.shrink, st));
-      ++nbt;
-      HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, Sp, W.betap.as<double>(), st));
-      HIPCHK(launch_decode_cols(tiled, L, Sp, k, u, v, mask, Xp, st));
-      HIPCHK(launch_bt_check(S, Xs, Sp, Xp, W.betap.as<double>(), k, beta, U, bc, gc, bcp, o.c, mask, L, fs,
-                             W.bt.as<double>(), st));
+      HIPCHK(launch_residual(y, Xp, W.betap.as<double>(), k, U, bcp, mask, L, W.r.as<double>(), gc, loss_trace, m + 1, fs, go,
+                             st));
+      HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), go,
+                             st));
+      HIPCHK(launch_commit(S, Sp, W.betap.as<double>(), k, beta, bc, bcp, nc, o.tol, fs, go, st));
       if (int rc = read_state()) return rc;
     }
-    if (stalled) {
-      status = IHT_STALLED;
-      break;
-    }
-    HIPCHK(launch_residual(y, Xp, W.betap.as<double>(), k, U, bcp, mask, L, W.r.as<double>(), gc, loss_trace, m + 1, fs, st));
-    HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), st));
-    HIPCHK(launch_commit(S, Sp, W.betap.as<double>(), k, beta, bc, bcp, nc, o.tol, fs, st));
     std::swap(Xs, Xp);
-    if (int rc = read_state()) return rc;
     if (h.conv) {
       status = IHT_OK;
       ++m;

@@ -71,22 +71,6 @@ __device__ double block_max(double x, double* sh) {
   return sh[32];
 }
 
-// Exclusive suffix sum over the threads of a 1024-thread block: returns sum of `x` over threads > tid.
-__device__ uint32_t block_excl_suffix(uint32_t x, uint32_t* sc /* [1024] */) {
-  const int t = threadIdx.x;
-  const int pos = 1023 - t;
-  __syncthreads();
-  sc[pos] = x;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t add = (pos >= off) ? sc[pos - off] : 0u;
-    __syncthreads();
-    sc[pos] += add;
-    __syncthreads();
-  }
-  return sc[pos] - x;
-}
-
 // ------------------------------------------------------------------------------------------------
 // Re-tile PLINK SNP-major rows into [tile][p_pad][8 B] with a per-SNP byte rotation.
 
@@ -114,7 +98,7 @@ __global__ __launch_bounds__(256) void k_retile(const uint8_t* __restrict__ raw,
 }
 
 // ------------------------------------------------------------------------------------------------
-// a2: exact genotype class counts over the subject set -> u, v (Methods, "Bandwidth optimization").
+// Exact genotype class counts over the subject set -> u, v (Methods, "Bandwidth optimization of IHT").
 
 __device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {  // bit q -> bit 2q
   return (m & 1u) | ((m & 2u) << 1) | ((m & 4u) << 2) | ((m & 8u) << 3);
@@ -164,7 +148,7 @@ __global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, 
 }
 
 // ------------------------------------------------------------------------------------------------
-// a4: the gradient pass.
+// The gradient pass.
 
 // LDS table: one 256-byte row per packed byte value v (0..255), 64 KB in all. FP64 rows hold
 // [buffer 0: 8 groups x (T, M) 16 B][buffer 1: same]; FP32 rows hold [buffer 0 copy 0: 8 x 8 B]
@@ -278,7 +262,9 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
                                                   int32_t tps, int64_t n, const double* __restrict__ r,
                                                   const double* __restrict__ mask, int64_t nT, const double* __restrict__ u,
                                                   const double* __restrict__ v, FitState* __restrict__ fs,
-                                                  double* __restrict__ g, double2* __restrict__ partial) {
+                                                  double* __restrict__ g, double2* __restrict__ partial,
+                                                  const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   // The table sits at LDS address 0 (this kernel has no static LDS), so a v_perm result is the
   // full lookup address; the residual of the block's subjects and the reduction scratch follow it.
   extern __shared__ __attribute__((aligned(16))) uint4 dyn_lds[];
@@ -403,7 +389,8 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
 __global__ __launch_bounds__(256) void k_pass_finalize(const double2* __restrict__ partial, int32_t split, int64_t p,
                                                        int64_t p_pad, const double* __restrict__ u,
                                                        const double* __restrict__ v, const FitState* __restrict__ fs,
-                                                       double* __restrict__ g) {
+                                                       double* __restrict__ g, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= p) return;
   double D = 0.0, M = 0.0;
@@ -416,7 +403,8 @@ __global__ __launch_bounds__(256) void k_pass_finalize(const double2* __restrict
 }
 
 // ------------------------------------------------------------------------------------------------
-// a9: decode + standardise support columns into a [kc][n_pad] FP64 cache.
+// Decode + standardise support columns into a [kc][n_pad] FP64 cache (Methods, "Bandwidth optimization
+// of IHT": decompress only the columns of the current support for X_k beta_k).
 
 __global__ __launch_bounds__(256) void k_decode_cols(const uint8_t* __restrict__ tiled, int64_t p_pad, int64_t n_pad,
                                                      const int64_t* __restrict__ cols, int32_t kc,
@@ -440,7 +428,7 @@ __global__ __launch_bounds__(256) void k_decode_cols(const uint8_t* __restrict__
 }
 
 // ------------------------------------------------------------------------------------------------
-// a6: top-k of |w| with ties to the lower index.
+// Top-k of |w| with ties to the lower index (the projection of eq. ihta).
 // Level 0: 8192-bin histogram of key bits 62..50 (key = IEEE bits of |w|) -> threshold bucket.
 // Collect: keys above the bucket are selected; keys in it are candidates. The last block finds the
 // exact remainder among the candidates by radix select on the unique 96-bit key (|w| bits, ~index),
@@ -459,31 +447,47 @@ struct SrcStep {
 
 __device__ __forceinline__ uint64_t abs_key(double w) { return (uint64_t)__double_as_longlong(fabs(w)); }
 
-// Returns (bucket, count above) for the need-th largest over nb bins held in LDS h; the owning
-// thread writes them to out[0], out[1]; all threads see them after the final barrier.
-__device__ void find_bucket(const uint32_t* h, int nb, uint32_t need, uint32_t* sc, uint32_t* out) {
-  const int per = nb / 1024;
-  const int t = threadIdx.x;
-  uint32_t local = 0;
-  for (int q = 0; q < per; ++q) local += h[t * per + q];
-  uint32_t cum = block_excl_suffix(local, sc);
-  for (int q = per - 1; q >= 0; --q) {
-    const uint32_t c = h[t * per + q];
-    if (cum < need && cum + c >= need) {
-      out[0] = (uint32_t)(t * per + q);
-      out[1] = cum;
-      out[2] = c;
+// (bucket, count above, count in bucket) of the need-th largest over nb bins held in LDS h,
+// found by the first wave (per-lane bin sums, then a shuffle suffix scan); out[] is visible to the
+// whole block after the closing barrier.
+__device__ void find_bucket(const uint32_t* h, int nb, uint32_t need, uint32_t* out) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int per = nb / 64;
+    uint32_t local = 0;
+    for (int q = 0; q < per; ++q) local += h[lane * per + q];
+    uint32_t incl = local;  // sum over lanes >= lane
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t t = __shfl_down(incl, off, 64);
+      if (lane + off < 64) incl += t;
     }
-    cum += c;
+    uint32_t cum = incl - local;  // sum over lanes > lane (higher bins)
+    if (cum < need && cum + local >= need) {
+      for (int q = per - 1; q >= 0; --q) {
+        const uint32_t c = h[lane * per + q];
+        if (cum + c >= need) {
+          out[0] = (uint32_t)(lane * per + q);
+          out[1] = cum;
+          out[2] = c;
+          break;
+        }
+        cum += c;
+      }
+    }
   }
   __syncthreads();
+}
+
+// Total order of the projection: |w| descending, then index ascending ("a before b").
+__device__ __forceinline__ bool key_before(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
+  return ka > kb || (ka == kb && ia < ib);
 }
 
 template <class Src>
 __global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
                                                     int32_t k, TopkWork tw) {
   __shared__ uint32_t h[kTopkBins0];
-  __shared__ uint32_t sc[1024];
   __shared__ uint32_t res[4];
   __shared__ uint32_t ticket;
   if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __res
     tw.hist[i] = 0u;
   }
   __syncthreads();
-  find_bucket(h, kTopkBins0, (uint32_t)k, sc, res);
+  find_bucket(h, kTopkBins0, (uint32_t)k, res);
   if (threadIdx.x == 0) {
     tw.state[0] = res[0];
     tw.state[1] = res[1];
@@ -520,13 +524,16 @@ __global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __res
   }
 }
 
+constexpr int kCandLds = 2048;  // candidates ranked directly in LDS when there are at most this many
+
 template <class Src>
 __global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
                                                        int32_t k, TopkWork tw, int64_t* __restrict__ support,
                                                        double* __restrict__ vals) {
-  __shared__ uint32_t h[4096];
-  __shared__ uint32_t sc[1024];
   __shared__ int32_t sel[kTopkMaxK];
+  __shared__ uint64_t ck[kCandLds];
+  __shared__ int32_t ci[kCandLds];
+  __shared__ uint32_t h[4096];
   __shared__ uint32_t res[4];
   __shared__ uint32_t ticket, nsel_l;
   if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
@@ -551,68 +558,97 @@ __global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __
   if (ticket != gridDim.x - 1) return;
   __threadfence();
 
+  // ---- last block: the `need` best candidates of the threshold bucket, then sort k indices ----
   const uint32_t n_above = atomic_load_u32(&tw.counters[2]);
   const uint32_t n_cand = atomic_load_u32(&tw.counters[3]);
-  for (uint32_t q = threadIdx.x; q < n_above; q += blockDim.x) sel[q] = __hip_atomic_load(&tw.sel[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  uint32_t need = (uint32_t)k - n_above;
-
-  // Radix select of the need-th largest 96-bit key c = (|w| bits << 32) | ~index over candidates.
-  typedef unsigned __int128 u128;
-  u128 prefix = 0;
-  uint32_t need_c = need;
-  for (int L = 0; L < 8; ++L) {
-    const int shift = 84 - 12 * L;
-    for (int i = threadIdx.x; i < 4096; i += blockDim.x) h[i] = 0;
-    __syncthreads();
+  for (uint32_t q = threadIdx.x; q < n_above; q += blockDim.x)
+    sel[q] = __hip_atomic_load(&tw.sel[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t need = (uint32_t)k - n_above;
+  if (n_cand <= (uint32_t)kCandLds) {
     for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
-      const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
-                     (u128)(0xFFFFFFFFu - (uint32_t)__hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if ((c >> (shift + 12)) == prefix) atomicAdd(&h[(uint32_t)(c >> shift) & 0xFFFu], 1u);
+      ck[q] = __hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ci[q] = __hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    find_bucket(h, 4096, need_c, sc, res);
-    prefix = (prefix << 12) | (u128)res[0];
-    need_c -= res[1];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) nsel_l = n_above;
-  __syncthreads();
-  for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
-    const int32_t idx = __hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
-                   (u128)(0xFFFFFFFFu - (uint32_t)idx);
-    if (c >= prefix) {
-      const uint32_t pos = atomicAdd(&nsel_l, 1u);
-      if (pos < (uint32_t)kTopkMaxK) sel[pos] = idx;
+    // rank of each candidate in the total order; ranks are distinct, so the best `need` land in
+    // sel[n_above + rank] without atomics
+    for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
+      const uint64_t kq = ck[q];
+      const int32_t iq = ci[q];
+      uint32_t rank = 0;
+      for (uint32_t q2 = 0; q2 < n_cand; ++q2) rank += key_before(ck[q2], ci[q2], kq, iq) ? 1u : 0u;
+      if (rank < need) sel[n_above + rank] = iq;
     }
-  }
-  __syncthreads();
-  const uint32_t nsel = nsel_l;
-  if (nsel != (uint32_t)k && threadIdx.x == 0) atomicOr(&tw.state[3], 2u);
-  // bitonic sort of the k selected indices, ascending
-  int N = 1;
-  while (N < k) N <<= 1;
-  for (int q = threadIdx.x; q < N; q += blockDim.x)
-    if (q >= k) sel[q] = 0x7FFFFFFF;
-  __syncthreads();
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < N / 2; i += blockDim.x) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool asc = (lo & size) == 0;
-        const int32_t a = sel[lo], c2 = sel[hi];
-        if ((a > c2) == asc) {
-          sel[lo] = c2;
-          sel[hi] = a;
-        }
+  } else {
+    // Radix select of the need-th best 96-bit key c = (|w| bits << 32) | ~index over candidates.
+    typedef unsigned __int128 u128;
+    u128 prefix = 0;
+    uint32_t need_c = need;
+    for (int L = 0; L < 8; ++L) {
+      const int shift = 84 - 12 * L;
+      for (int i = threadIdx.x; i < 4096; i += blockDim.x) h[i] = 0;
+      __syncthreads();
+      for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
+        const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
+                       (u128)(0xFFFFFFFFu - (uint32_t)__hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED,
+                                                                       __HIP_MEMORY_SCOPE_AGENT));
+        if ((c >> (shift + 12)) == prefix) atomicAdd(&h[(uint32_t)(c >> shift) & 0xFFFu], 1u);
       }
       __syncthreads();
+      find_bucket(h, 4096, need_c, res);
+      prefix = (prefix << 12) | (u128)res[0];
+      need_c -= res[1];
+      __syncthreads();
     }
+    if (threadIdx.x == 0) nsel_l = n_above;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < n_cand; q += blockDim.x) {
+      const int32_t idx = __hip_atomic_load(&tw.cand_idx[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const u128 c = ((u128)__hip_atomic_load(&tw.cand_key[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32) |
+                     (u128)(0xFFFFFFFFu - (uint32_t)idx);
+      if (c >= prefix) {
+        const uint32_t pos = atomicAdd(&nsel_l, 1u);
+        if (pos < (uint32_t)kTopkMaxK) sel[pos] = idx;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && nsel_l != (uint32_t)k) atomicOr(&tw.state[3], 2u);
   }
-  for (int q = threadIdx.x; q < k; q += blockDim.x) {
-    support[q] = sel[q];
-    if (vals) vals[q] = src.at(sel[q]);
+  __syncthreads();
+  // the k selected indices, ascending
+  if (k <= 1024) {
+    for (int q = threadIdx.x; q < k; q += blockDim.x) {
+      const int32_t x = sel[q];
+      int rank = 0;
+      for (int q2 = 0; q2 < k; ++q2) rank += (sel[q2] < x) ? 1 : 0;
+      support[rank] = x;
+      if (vals) vals[rank] = src.at(x);
+    }
+  } else {
+    int N = 1;
+    while (N < k) N <<= 1;
+    for (int q = threadIdx.x; q < N; q += blockDim.x)
+      if (q >= k) sel[q] = 0x7FFFFFFF;
+    __syncthreads();
+    for (int size = 2; size <= N; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < N / 2; i += blockDim.x) {
+          const int lo = 2 * i - (i & (stride - 1));
+          const int hi = lo + stride;
+          const bool asc = (lo & size) == 0;
+          const int32_t a = sel[lo], c2 = sel[hi];
+          if ((a > c2) == asc) {
+            sel[lo] = c2;
+            sel[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int q = threadIdx.x; q < k; q += blockDim.x) {
+      support[q] = sel[q];
+      if (vals) vals[q] = src.at(sel[q]);
+    }
   }
   if (threadIdx.x == 0) {
     tw.counters[1] = 0u;
@@ -641,12 +677,17 @@ __global__ __launch_bounds__(1024) void k_check_finite(const double* __restrict_
   if (threadIdx.x == 0) fs->nonfinite = bad;
 }
 
+constexpr int kSubjUnroll = 4;  // subjects per thread in flight in the single-block step kernels
+
 // r = mask (y - A_{cols,C} b); loss = 1/2 ||r||^2 (eq. leastsquaresloss); covariate gradient gc = A_C^T r.
+// Skipped entirely when the gate flag is 0 (a proposal that still needs backtracking).
 __global__ __launch_bounds__(1024) void k_residual(const double* __restrict__ y, const double* __restrict__ X,
                                                    const double* __restrict__ bvals, int32_t kc, Unpen U,
                                                    const double* __restrict__ bc, const double* __restrict__ mask,
                                                    int64_t n, int64_t n_pad, double* __restrict__ r, double* __restrict__ gc,
-                                                   double* __restrict__ trace, int32_t trace_idx, FitState* fs) {
+                                                   double* __restrict__ trace, int32_t trace_idx, FitState* fs,
+                                                   const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double sh[40];
   __shared__ double bl[kTopkMaxK];
   __shared__ double bcl[kMaxUnpenalized];
@@ -655,17 +696,36 @@ __global__ __launch_bounds__(1024) void k_residual(const double* __restrict__ y,
   for (int q = threadIdx.x; q < nc; q += blockDim.x) bcl[q] = bc[q];
   __syncthreads();
   double rr = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    double ri = 0.0;
-    if (mask[i] != 0.0) {
-      double s = 0.0;
-      for (int q = 0; q < kc; ++q) s += X[(int64_t)q * n_pad + i] * bl[q];
-      for (int c = 0; c < U.cz; ++c) s += (double)U.Z[(int64_t)c * n + i] * bcl[c];
-      if (U.icpt) s += 1.0 * bcl[U.cz];
-      ri = y[i] - s;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
+    int64_t ii[kSubjUnroll];
+    bool ok[kSubjUnroll];
+    double sm[kSubjUnroll];
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      ii[w] = i0 + (int64_t)w * blockDim.x;
+      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
+      if (ii[w] >= n) ii[w] = 0;
+      sm[w] = 0.0;
     }
-    r[i] = ri;
-    rr += ri * ri;
+    for (int q = 0; q < kc; ++q) {
+      const double bq = bl[q];
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += X[(int64_t)q * n_pad + ii[w]] * bq;
+    }
+    for (int c = 0; c < U.cz; ++c) {
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)c * n + ii[w]] * bcl[c];
+    }
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      if (U.icpt) sm[w] += 1.0 * bcl[U.cz];
+      const int64_t i = i0 + (int64_t)w * blockDim.x;
+      if (i < n) {
+        const double ri = ok[w] ? y[i] - sm[w] : 0.0;
+        r[i] = ri;
+        rr += ri * ri;
+      }
+    }
   }
   const double loss = 0.5 * block_sum(rr, sh);
   for (int c = 0; c < nc; ++c) {
@@ -683,7 +743,7 @@ __global__ __launch_bounds__(1024) void k_residual(const double* __restrict__ y,
   }
 }
 
-// a5: mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2.
+// Normalised step mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2.
 __global__ __launch_bounds__(1024) void k_mu(const double* __restrict__ Xs, const int64_t* __restrict__ S, int32_t k,
                                              const double* __restrict__ g, Unpen U, const double* __restrict__ gc,
                                              const double* __restrict__ mask, int64_t n, int64_t n_pad, FitState* fs) {
@@ -700,13 +760,31 @@ __global__ __launch_bounds__(1024) void k_mu(const double* __restrict__ Xs, cons
     for (int q = 0; q < nc; ++q) num += gcl[q] * gcl[q];
   }
   double dd = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    if (mask[i] == 0.0) continue;
-    double s = 0.0;
-    for (int q = 0; q < k; ++q) s += Xs[(int64_t)q * n_pad + i] * gl[q];
-    for (int c = 0; c < U.cz; ++c) s += (double)U.Z[(int64_t)c * n + i] * gcl[c];
-    if (U.icpt) s += 1.0 * gcl[U.cz];
-    dd += s * s;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
+    int64_t ii[kSubjUnroll];
+    bool ok[kSubjUnroll];
+    double sm[kSubjUnroll];
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      ii[w] = i0 + (int64_t)w * blockDim.x;
+      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
+      if (ii[w] >= n) ii[w] = 0;
+      sm[w] = 0.0;
+    }
+    for (int q = 0; q < k; ++q) {
+      const double gq = gl[q];
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += Xs[(int64_t)q * n_pad + ii[w]] * gq;
+    }
+    for (int c = 0; c < U.cz; ++c) {
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)c * n + ii[w]] * gcl[c];
+    }
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      if (U.icpt) sm[w] += 1.0 * gcl[U.cz];
+      if (ok[w]) dd += sm[w] * sm[w];
+    }
   }
   const double den = block_sum(dd, sh);
   if (threadIdx.x == 0) {
@@ -717,7 +795,7 @@ __global__ __launch_bounds__(1024) void k_mu(const double* __restrict__ Xs, cons
   }
 }
 
-// a7: support comparison, unpenalised proposal bcp = bc + mu gc, and (if the support moved)
+// Support comparison, unpenalised proposal bcp = bc + mu gc, and (if the support moved)
 // omega = (1-c)||Delta||^2 / ||A Delta||^2 over S u S+ u C with accept = mu < omega.
 __global__ __launch_bounds__(1024) void k_bt_check(const int64_t* __restrict__ S, const double* __restrict__ Xs,
                                                    const int64_t* __restrict__ Sp, const double* __restrict__ Xp,
@@ -781,22 +859,39 @@ __global__ __launch_bounds__(1024) void k_bt_check(const int64_t* __restrict__ S
       fs->same = 1;
       fs->accept = 1;
       fs->omega = 0.0;
+      fs->go = fs->den_zero ? 0 : 1;
     }
     return;
   }
   const int nu = nu_s;
   double sa = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    if (mask[i] == 0.0) continue;
-    double s = 0.0;
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
+    int64_t ii[kSubjUnroll];
+    bool ok[kSubjUnroll];
+    double sm[kSubjUnroll];
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      ii[w] = i0 + (int64_t)w * blockDim.x;
+      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
+      if (ii[w] >= n) ii[w] = 0;
+      sm[w] = 0.0;
+    }
     for (int q = 0; q < nu; ++q) {
       const int src = uidx[q];
-      const double x = (src >= 0) ? Xs[(int64_t)src * n_pad + i] : Xp[(int64_t)(-src - 1) * n_pad + i];
-      s += x * udel[q];
+      const double* col = (src >= 0) ? Xs + (int64_t)src * n_pad : Xp + (int64_t)(-src - 1) * n_pad;
+      const double dq = udel[q];
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += col[ii[w]] * dq;
     }
-    for (int cc = 0; cc < U.cz; ++cc) s += (double)U.Z[(int64_t)cc * n + i] * dcl[cc];
-    if (U.icpt) s += 1.0 * dcl[U.cz];
-    sa += s * s;
+    for (int cc = 0; cc < U.cz; ++cc) {
+#pragma unroll
+      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)cc * n + ii[w]] * dcl[cc];
+    }
+#pragma unroll
+    for (int w = 0; w < kSubjUnroll; ++w) {
+      if (U.icpt) sm[w] += 1.0 * dcl[U.cz];
+      if (ok[w]) sa += sm[w] * sm[w];
+    }
   }
   const double dA = block_sum(sa, sh);
   if (threadIdx.x == 0) {
@@ -804,6 +899,7 @@ __global__ __launch_bounds__(1024) void k_bt_check(const int64_t* __restrict__ S
     fs->same = 0;
     fs->omega = omega;
     fs->accept = (mu < omega);
+    fs->go = (!fs->den_zero && mu < omega) ? 1 : 0;
   }
 }
 
@@ -816,7 +912,8 @@ __global__ void k_shrink(FitState* fs, double shrink) {
 __global__ __launch_bounds__(1024) void k_commit(int64_t* __restrict__ S, const int64_t* __restrict__ Sp,
                                                  const double* __restrict__ betap, int32_t k, double* __restrict__ beta,
                                                  double* __restrict__ bc, const double* __restrict__ bcp, int32_t nc,
-                                                 double tol, FitState* fs) {
+                                                 double tol, FitState* fs, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ double sh[40];
   __shared__ int same_s;
   if (threadIdx.x == 0) same_s = 1;
@@ -943,7 +1040,7 @@ size_t gradient_partial_bytes(const Layout& L) {
 template <int NS, bool F32>
 static void launch_pass_one(dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* r,
                             const double* mask, int64_t nT, const double* u, const double* v, FitState* fs, double* g,
-                            double2* partial) {
+                            double2* partial, const int32_t* gate) {
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<NS, F32>), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -951,23 +1048,23 @@ static void launch_pass_one(dim3 grid, size_t lds, hipStream_t st, const uint2* 
     attr_set = true;
   }
   hipLaunchKernelGGL((k_pass<NS, F32>), grid, dim3(kPassThreads), lds, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n, r,
-                     mask, nT, u, v, fs, g, partial);
+                     mask, nT, u, v, fs, g, partial, gate);
 }
 
 template <int NS>
 static void launch_pass_ns(bool f32, dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps,
                            const double* r, const double* mask, int64_t nT, const double* u, const double* v, FitState* fs,
-                           double* g, double2* partial) {
+                           double* g, double2* partial, const int32_t* gate) {
   if (!f32) {
-    launch_pass_one<NS, false>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial);
+    launch_pass_one<NS, false>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial, gate);
     return;
   }
-  launch_pass_one<NS, true>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial);
+  launch_pass_one<NS, true>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial, gate);
 }
 
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
                            const double* u, const double* v, FitState* fs, int precision, double* g, double* partial,
-                           hipStream_t st) {
+                           const int32_t* gate, hipStream_t st) {
   const PassGeom G = pass_geometry(L, precision);
   const dim3 grid((unsigned)G.groups, (unsigned)G.split);
   double2* part = (G.split > 1) ? reinterpret_cast<double2*>(partial) : nullptr;
@@ -975,16 +1072,16 @@ hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* 
   const uint2* t4 = reinterpret_cast<const uint2*>(tiled);
   const size_t lds = pass_lds_bytes(G);
   if (G.ns == 4)
-    launch_pass_ns<4>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+    launch_pass_ns<4>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
   else if (G.ns == 2)
-    launch_pass_ns<2>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+    launch_pass_ns<2>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
   else
-    launch_pass_ns<1>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part);
+    launch_pass_ns<1>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (part) {
     hipLaunchKernelGGL(k_pass_finalize, dim3((unsigned)((L.p + 255) / 256)), dim3(256), 0, st, part, G.split, L.p, L.p_pad, u,
-                       v, fs, g);
+                       v, fs, g, gate);
     e = hipGetLastError();
   }
   return e;
@@ -1032,9 +1129,9 @@ hipError_t launch_check_finite(const double* y, const float* Z, int64_t n, int32
 
 hipError_t launch_residual(const double* y, const double* X, const double* bvals, int32_t kc, Unpen U, const double* bc,
                            const double* mask, const Layout& L, double* r, double* gc, double* trace, int32_t trace_idx,
-                           FitState* fs, hipStream_t st) {
+                           FitState* fs, const int32_t* gate, hipStream_t st) {
   hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, st, y, X, bvals, kc, U, bc, mask, L.n, L.n_pad, r, gc, trace,
-                     trace_idx, fs);
+                     trace_idx, fs, gate);
   return hipGetLastError();
 }
 
@@ -1060,8 +1157,8 @@ hipError_t launch_shrink(FitState* fs, double shrink, hipStream_t st) {
 }
 
 hipError_t launch_commit(int64_t* S, const int64_t* Sp, const double* betap_vals, int32_t k, double* beta, double* bc,
-                         const double* bcp, int32_t nc, double tol, FitState* fs, hipStream_t st) {
-  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1024), 0, st, S, Sp, betap_vals, k, beta, bc, bcp, nc, tol, fs);
+                         const double* bcp, int32_t nc, double tol, FitState* fs, const int32_t* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1024), 0, st, S, Sp, betap_vals, k, beta, bc, bcp, nc, tol, fs, gate);
   return hipGetLastError();
 }
 

@@ -39,7 +39,9 @@ struct FitState {
   double loss, mean, Rsum;
   double dmax, bmax;
   int32_t same, accept, den_zero, conv;
-  int32_t nonfinite, topk_error, pad0, pad1;
+  int32_t nonfinite, topk_error;
+  int32_t go;  // proposal accepted (or support unchanged) and mu defined: the gated kernels run
+  int32_t pad1;
 };
 
 // Top-k work area (counters are self-resetting: the last block of each kernel clears them).
@@ -64,7 +66,7 @@ hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* m
 // writes the subject-set mean of r and R = sum of the centred residual to fs.
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
                            const double* u, const double* v, FitState* fs, int precision, double* g, double* partial,
-                           hipStream_t st);
+                           const int32_t* gate, hipStream_t st);
 size_t gradient_partial_bytes(const Layout& L);
 
 hipError_t launch_decode_cols(const uint8_t* tiled, const Layout& L, const int64_t* cols, int32_t kc, const double* u,
@@ -87,9 +89,10 @@ struct Unpen {
 hipError_t launch_check_finite(const double* y, const float* Z, int64_t n, int32_t cz, const double* mask, FitState* fs,
                                hipStream_t st);
 // r = mask*(y - X_cols b - Z bc), loss and covariate gradient gc; trace[idx] = loss.
+// Gated launches (residual, gradient, commit) do nothing when *gate == 0; gate may be NULL.
 hipError_t launch_residual(const double* y, const double* X, const double* bvals, int32_t kc, Unpen U, const double* bc,
                            const double* mask, const Layout& L, double* r, double* gc, double* trace, int32_t trace_idx,
-                           FitState* fs, hipStream_t st);
+                           FitState* fs, const int32_t* gate, hipStream_t st);
 hipError_t launch_mu(const double* Xs, const int64_t* S, int32_t k, const double* g, Unpen U, const double* gc,
                      const double* mask, const Layout& L, FitState* fs, hipStream_t st);
 hipError_t launch_bt_check(const int64_t* S, const double* Xs, const int64_t* Sp, const double* Xp, const double* betap_vals,
@@ -97,7 +100,7 @@ hipError_t launch_bt_check(const int64_t* S, const double* Xs, const int64_t* Sp
                            double c, const double* mask, const Layout& L, FitState* fs, double* work, hipStream_t st);
 hipError_t launch_shrink(FitState* fs, double shrink, hipStream_t st);
 hipError_t launch_commit(int64_t* S, const int64_t* Sp, const double* betap_vals, int32_t k, double* beta, double* bc,
-                         const double* bcp, int32_t nc, double tol, FitState* fs, hipStream_t st);
+                         const double* bcp, int32_t nc, double tol, FitState* fs, const int32_t* gate, hipStream_t st);
 hipError_t launch_output(const int64_t* S, int32_t k, const double* beta, const double* bc, int32_t nc, int64_t* support,
                          double* beta_S, double* beta_cov, hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double val, hipStream_t st);
