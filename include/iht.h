@@ -113,6 +113,19 @@ int iht_stats_read(const iht_stats *s, double *u, double *v, void *stream);
 int iht_gradient(const iht_geno *g, const iht_stats *s, const double *r, double *grad, int32_t precision, void *stream);
 
 /*
+ * Batched gradient pass G_t = X_st^T r_t for T solves sharing the genotype matrix (the many traits,
+ * cross-validation folds and model sizes of Methods, "Model selection"), each over its own subject
+ * set and standardisation. Runs on the matrix cores: dosages and missing flags as int8 against the
+ * residual split into three int8 digits under a power-of-two scale, with exact int32 sums combined
+ * in FP64; the only approximation is that quantisation (relative error ~1e-7 of max|r_t|).
+ *   stats  host array of T stats handles of this matrix (handles may repeat).
+ *   R      device [T][n] FP64 residuals (row t for solve t); entries outside a solve's set ignored.
+ *   G      device [T][p] FP64 output (row t = gradient of solve t).
+ *   1 <= T <= 65536. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. Synchronises the stream.
+ */
+int iht_gradient_batch(const iht_geno *g, const iht_stats *const *stats, int32_t T, const double *R, double *G, void *stream);
+
+/*
  * Hard-threshold projection P_Sk (Methods, eq. ihta and the text after it): keep the k entries of
  * largest |w|, ties broken towards the lower index, zero the rest.
  *   w        device [p] FP64, finite.

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "iht.h"
+#include "iht_batch.h"
 #include "iht_internal.h"
 
 using namespace iht;
@@ -114,6 +115,7 @@ struct iht_geno {
   // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
   DevBuf partial, state;
   FitWork fit;
+  DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
 };
 
 struct iht_stats {
@@ -289,6 +291,31 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
 }
 
 // Work area of iht_project: one per (thread, device), kept for the life of the process.
+int iht_gradient_batch(const iht_geno* g, const iht_stats* const* stats, int32_t T, const double* R, double* G, void* stream) {
+  if (!g || !stats || !R || !G) return fail(IHT_EINVAL, "iht_gradient_batch: NULL argument");
+  if (T < 1 || T > 65536) return fail(IHT_EINVAL, "iht_gradient_batch: T out of range");
+  std::vector<BatchSolve> sv((size_t)T);
+  for (int32_t t = 0; t < T; ++t) {
+    if (!stats[t]) return fail(IHT_EINVAL, "iht_gradient_batch: NULL stats handle");
+    if (stats[t]->geno != g) return fail(IHT_EINVAL, "iht_gradient_batch: stats belong to another genotype handle");
+    sv[t] = BatchSolve{stats[t]->u.as<double>(), stats[t]->v.as<double>(), stats[t]->mask.as<double>(), stats[t]->nT};
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  iht_geno* Gh = const_cast<iht_geno*>(g);
+  const Layout& L = g->L;
+  const int32_t Tp = batch_t_pad(T);
+  HIPCHK(Gh->batch_r8.ensure(batch_r8_bytes(L, T)));
+  HIPCHK(Gh->batch_scale.ensure((size_t)Tp * 8));
+  HIPCHK(Gh->batch_rsum.ensure((size_t)Tp * 8));
+  HIPCHK(Gh->batch_sv.ensure((size_t)T * sizeof(BatchSolve)));
+  HIPCHK(hipMemcpyAsync(Gh->batch_sv.p, sv.data(), (size_t)T * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_gradient_batch(g->tiled.as<uint8_t>(), L, R, T, Gh->batch_sv.as<BatchSolve>(), Gh->batch_r8.as<int8_t>(),
+                               Gh->batch_scale.as<double>(), Gh->batch_rsum.as<double>(), G, L.p, st));
+  // the host copy of the per-solve table must outlive the copy
+  HIPCHK(hipStreamSynchronize(st));
+  return IHT_OK;
+}
+
 static TopkArea* project_area() {
   static thread_local std::vector<TopkArea*> areas;
   int dev = 0;

@@ -1,0 +1,255 @@
+// iht_batch.hip -- batched gradient G = X_st^T R for T solves sharing one packed genotype matrix.
+//
+// For solve t on subject set T_t (Methods, eq. normal_grad; "Bandwidth optimization of IHT"):
+//   G_jt = v_jt (A_jt - u_jt (R_t - B_jt)),  A = X0^T R~, B = M^T R~, R_t = sum_i R~_it,
+// with X0 the dosages (missing -> 0), M the missing indicator and R~ the residual centred over T_t
+// and quantised to three balanced int8 digits under a power-of-two scale s_t:
+//   R~_it = s_t (q0 + q1 / 254 + q2 / 254^2),  q in [-127, 127].
+// A and B are exact int32 sums computed on the matrix cores (v_mfma_i32_32x32x32_i8): dosages 0/1/2
+// and flags 0/1 times the digits; the digit sums are combined in FP64. The only approximation is
+// the quantisation of the residual (|R - R~| <= s_t / (2 * 254^2), s_t < max|R| / 63.5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "iht_batch.h"
+
+namespace iht {
+namespace {
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+typedef uint32_t v2u_b __attribute__((ext_vector_type(2)));
+
+constexpr int kDigits = 3;
+constexpr double kBase = 254.0;
+
+__device__ double bsum(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    sh[32] = t;
+  }
+  __syncthreads();
+  return sh[32];
+}
+
+__device__ double bmax(double x, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = sh[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, sh[i]);
+    sh[32] = t;
+  }
+  __syncthreads();
+  return sh[32];
+}
+
+// One block per (padded) solve: centre, choose the scale, write the digits and the exact digit sums.
+// R8 layout: [tile][digit][T_pad][32 subjects] int8.
+__global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, int64_t n, int64_t n_pad, int32_t T,
+                                                int32_t T_pad, const BatchSolve* __restrict__ sv, int8_t* __restrict__ R8,
+                                                double* __restrict__ scale, double* __restrict__ rsum) {
+  __shared__ double sh[40];
+  const int t = blockIdx.x;
+  const int64_t ntiles = n_pad / 32;
+  if (t >= T) {  // padding columns: zero digits
+    for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x)
+      for (int d = 0; d < kDigits; ++d) R8[(((i >> 5) * kDigits + d) * T_pad + t) * 32 + (i & 31)] = 0;
+    return;
+  }
+  const double* r = R + (int64_t)t * n;
+  const double* mask = sv[t].mask;
+  double s1 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s1 += (mask[i] != 0.0) ? r[i] : 0.0;
+  const double mean = bsum(s1, sh) / (double)sv[t].nT;
+  double mx = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    if (mask[i] != 0.0) mx = fmax(mx, fabs(r[i] - mean));
+  mx = bmax(mx, sh);
+  // smallest power of two s with 127 s >= max|r - mean| (exact scaling, no overflow of q0)
+  double s = 1.0;
+  if (mx > 0.0) {
+    int e;
+    (void)frexp(mx / 127.0, &e);
+    s = ldexp(1.0, e);
+    if (127.0 * ldexp(1.0, e - 1) >= mx) s = ldexp(1.0, e - 1);
+  }
+  double sq[kDigits] = {0.0, 0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x) {
+    int q[kDigits] = {0, 0, 0};
+    if (i < n && mask[i] != 0.0 && mx > 0.0) {
+      double x = (r[i] - mean) / s;  // |x| <= 127, exact division by a power of two
+      const double q0 = rint(x);
+      const double e0 = (x - q0) * kBase;  // |e0| <= 127
+      const double q1 = rint(e0);
+      const double e1 = (e0 - q1) * kBase;
+      const double q2 = rint(e1);
+      q[0] = (int)q0;
+      q[1] = (int)q1;
+      q[2] = (int)q2;
+    }
+#pragma unroll
+    for (int d = 0; d < kDigits; ++d) {
+      R8[(((i >> 5) * kDigits + d) * T_pad + t) * 32 + (i & 31)] = (int8_t)q[d];
+      sq[d] += (double)q[d];  // integer-valued, exact
+    }
+  }
+  (void)ntiles;
+  double tot[kDigits];
+#pragma unroll
+  for (int d = 0; d < kDigits; ++d) tot[d] = bsum(sq[d], sh);
+  if (threadIdx.x == 0) {
+    scale[t] = s;
+    rsum[t] = s * ((tot[0] + tot[1] * (1.0 / kBase)) + tot[2] * (1.0 / (kBase * kBase)));
+  }
+}
+
+// byte of 4 two-bit codes -> (4 dosage bytes, 4 missing-flag bytes)
+__device__ __forceinline__ uint2 code_lut_entry(uint32_t b) {
+  uint32_t d = 0, m = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t c = (b >> (2 * e)) & 3u;
+    const uint32_t dose = c == 3u ? 2u : (c == 2u ? 1u : 0u);
+    d |= dose << (8 * e);
+    m |= (c == 1u ? 1u : 0u) << (8 * e);
+  }
+  return make_uint2(d, m);
+}
+
+constexpr int kBlockSnps = 256;  // 4 waves x 64 SNPs
+constexpr int kBlockSolves = 32;
+
+// Block (bx, by): SNPs [256 bx, 256 bx + 256) x solves [32 by, 32 by + 32). Wave w: SNPs
+// [256 bx + 64 w, +64) as two groups of 32 rows, each with a dosage and a missing-flag operand,
+// times the 3 digit column tiles: 12 accumulator tiles of 32x32 int32.
+__global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
+                                                  const int8_t* __restrict__ R8, int32_t T, int32_t T_pad,
+                                                  const BatchSolve* __restrict__ sv, const double* __restrict__ scale,
+                                                  const double* __restrict__ rsum, double* __restrict__ G, int64_t ldg) {
+  __shared__ uint2 lut[256];
+  __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * 32];  // 2 x 3 KB
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int kh = lane >> 5;  // k-half: subjects 16 kh .. 16 kh + 15 of the tile
+  const int col = lane & 31;
+  lut[tid] = code_lut_entry((uint32_t)tid);
+
+  const int64_t j0 = (int64_t)blockIdx.x * kBlockSnps + 64 * w;
+  const int64_t jA = j0 + col, jB = j0 + 32 + col;  // this lane's SNP in group 0 / group 1
+  const int tb = blockIdx.y * kBlockSolves;
+  // un-rotation selector: group g of the tile sits in segment byte (g - j) mod 8; this lane needs
+  // groups 4 kh .. 4 kh + 3 in order (v_perm over the segment {hi dword, lo dword}).
+  const uint32_t rot = (uint32_t)(jA & 7);
+  uint32_t sel = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) sel |= ((4u * kh + e - rot) & 7u) << (8 * e);
+
+  // R digit chunk of this block for tile t: 3 x 1 KB at [(t*3 + d)*T_pad + tb][32]
+  auto stage_r = [&](int t, int buf) {
+    if (tid < 192) {
+      const int d = tid >> 6, part = tid & 63;
+      const int4 x = *reinterpret_cast<const int4*>(R8 + (((int64_t)t * kDigits + d) * T_pad + tb) * 32 + part * 16);
+      *reinterpret_cast<int4*>(&rb[buf][d * 1024 + part * 16]) = x;
+    }
+  };
+  auto load_seg = [&](int t, int64_t j) -> uint2 {
+    const int64_t jj = j < p_pad ? j : 0;
+    return tiled[(int64_t)t * p_pad + jj];
+  };
+
+  v16i acc[2][2][kDigits];  // [snp group][dose|miss][digit]
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int d = 0; d < kDigits; ++d) acc[h][o][d] = v16i{};
+
+  uint2 segA = load_seg(0, jA), segB = load_seg(0, jB);
+  stage_r(0, 0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    const int buf = t & 1;
+    uint2 nA = segA, nB = segB;
+    if (t + 1 < ntiles) {
+      nA = load_seg(t + 1, jA);
+      nB = load_seg(t + 1, jB);
+      stage_r(t + 1, buf ^ 1);
+    }
+    // A operands: 4 packed bytes (16 subjects) of each SNP -> dosage and flag dwords
+    v4i op[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint2 sg = h ? segB : segA;
+      const uint32_t g4 = __builtin_amdgcn_perm(sg.y, sg.x, sel);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint2 L = lut[(g4 >> (8 * e)) & 0xFFu];
+        op[h][0][e] = (int32_t)L.x;
+        op[h][1][e] = (int32_t)L.y;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < kDigits; ++d) {
+      const v4i bop = *reinterpret_cast<const v4i*>(&rb[buf][d * 1024 + col * 32 + kh * 16]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int o = 0; o < 2; ++o) acc[h][o][d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(op[h][o], bop, acc[h][o][d], 0, 0, 0);
+    }
+    __syncthreads();
+    segA = nA;
+    segB = nB;
+  }
+
+  // Epilogue: column col = solve tb + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
+  const int t = tb + col;
+  if (t >= T) return;
+  const double s = scale[t], Rt = rsum[t];
+  const double* u = sv[t].u;
+  const double* v = sv[t].v;
+  const double i1 = 1.0 / kBase, i2 = 1.0 / (kBase * kBase);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t j = j0 + 32 * h + 8 * (r / 4) + 4 * kh + (r % 4);
+      if (j >= p) continue;
+      const double A = s * (((double)acc[h][0][0][r] + (double)acc[h][0][1][r] * i1) + (double)acc[h][0][2][r] * i2);
+      const double B = s * (((double)acc[h][1][0][r] + (double)acc[h][1][1][r] * i1) + (double)acc[h][1][2][r] * i2);
+      G[(int64_t)t * ldg + j] = v[j] * (A - u[j] * (Rt - B));
+    }
+}
+
+}  // namespace
+
+int32_t batch_t_pad(int32_t T) { return (T + kBlockSolves - 1) / kBlockSolves * kBlockSolves; }
+
+size_t batch_r8_bytes(const Layout& L, int32_t T) { return (size_t)L.ntiles * kDigits * batch_t_pad(T) * 32; }
+
+hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int32_t T, const BatchSolve* sv,
+                                 int8_t* R8, double* scale, double* rsum, double* G, int64_t ldg, hipStream_t st) {
+  const int32_t T_pad = batch_t_pad(T);
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)T_pad), dim3(1024), 0, st, R, L.n, L.n_pad, T, T_pad, sv, R8, scale, rsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((L.p + kBlockSnps - 1) / kBlockSnps), (unsigned)(T_pad / kBlockSolves));
+  hipLaunchKernelGGL(k_gradB, grid, dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad, (int32_t)L.ntiles,
+                     R8, T, T_pad, sv, scale, rsum, G, ldg);
+  return hipGetLastError();
+}
+
+}  // namespace iht

@@ -21,8 +21,8 @@ HOST_PTR, DEVICE_PTR = 0, 1
 MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
-           "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_project", "iht_fit", "iht_status_str",
-           "iht_last_error")
+           "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit",
+           "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -58,10 +58,11 @@ def load():
     L.iht_stats_destroy.argtypes = [P]
     L.iht_stats_read.argtypes = [P, P, P, P]
     L.iht_gradient.argtypes = [P, P, P, P, I32, P]
+    L.iht_gradient_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, P, P]
     L.iht_project.argtypes = [P, I64, I32, P, P, P]
     L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
-              "iht_stats_read", "iht_gradient", "iht_project", "iht_fit"):
+              "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -192,6 +193,19 @@ def gradient(geno: Geno, stats: Stats, r, precision: int = FP64, out=None):
         out = torch.empty(geno.p, dtype=torch.float64, device=r.device)
     gp = _dev(out, torch.float64, (geno.p,), "out")
     _check(load().iht_gradient(geno._h, stats._h, rp, gp, precision, _stream()))
+    return out
+
+
+def gradient_batch(geno: Geno, stats, R, out=None):
+    """G[t] = X_st^T R[t] for T solves (iht_gradient_batch). stats: one Stats per solve; R: float64 CUDA [T, n]."""
+    torch = _torch()
+    T = len(stats)
+    rp = _dev(R, torch.float64, (T, geno.n), "R")
+    if out is None:
+        out = torch.empty((T, geno.p), dtype=torch.float64, device=R.device)
+    gp = _dev(out, torch.float64, (T, geno.p), "out")
+    arr = (ctypes.c_void_p * T)(*[s._h.value for s in stats])
+    _check(load().iht_gradient_batch(geno._h, arr, T, rp, gp, _stream()))
     return out
 
 

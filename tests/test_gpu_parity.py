@@ -253,3 +253,52 @@ def test_fit_deterministic():
     b = iht.fit(g, s, y, 10)
     for key in ("support", "beta_S", "loss_trace"):
         assert torch.equal(a[key], b[key])
+
+
+# ------------------------------------------------------------------ batched gradient (matrix cores)
+
+def fold_masks(n, q, seed):
+    """q training masks (subjects outside fold f) of a seeded fold partition, plus the full set."""
+    rng = np.random.default_rng(seed)
+    fold = rng.permutation(np.arange(n) % q)
+    return [(fold != f).astype(np.uint8) for f in range(q)] + [np.ones(n, dtype=np.uint8)]
+
+
+@pytest.mark.parametrize("n,p,T", [(1001, 3000, 1), (1001, 3000, 7), (2500, 9000, 33), (5000, 40_000, 108)])
+def test_gradient_batch_parity(n, p, T):
+    say(f"gradient_batch n={n} p={p} T={T}")
+    bed, _ = synth.make_genotypes(n, p, seed=11 * n + p)
+    g = iht.Geno(bed, n)
+    masks = fold_masks(n, 5, 3)
+    stats_by_mask = [iht.Stats(g, m) for m in masks]
+    assign = [t % len(masks) for t in range(T)]
+    stats = [stats_by_mask[a] for a in assign]
+    rng = np.random.default_rng(T)
+    R = rng.standard_normal((T, n)) * rng.uniform(0.2, 5.0, size=(T, 1)) + rng.uniform(-2, 2, size=(T, 1))
+    got = iht.gradient_batch(g, stats, dev(R)).cpu().numpy()
+    again = iht.gradient_batch(g, stats, dev(R)).cpu().numpy()
+    assert np.array_equal(got, again)
+    uv = [oracle.stats(bed, n, m) for m in masks]
+    worst = 0.0
+    for t in range(T):
+        u, v = uv[assign[t]]
+        ref = oracle.gradient(bed, n, u, v, R[t], masks[assign[t]])
+        e = rel(got[t], ref)
+        worst = max(worst, e)
+        assert e <= 2e-6, (t, e)
+    say(f"  worst relative error {worst:.2e}")
+
+
+def test_gradient_batch_rows_match_single_solve_inputs():
+    n, p = 700, 2500
+    bed, _ = synth.make_genotypes(n, p, seed=4)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    rng = np.random.default_rng(9)
+    R = rng.standard_normal((3, n))
+    R[1] = 0.0  # an all-zero residual gives an exactly zero gradient row
+    got = iht.gradient_batch(g, [s, s, s], dev(R)).cpu().numpy()
+    assert np.all(got[1] == 0.0)
+    u, v = oracle.stats(bed, n)
+    for t in (0, 2):
+        assert rel(got[t], oracle.gradient(bed, n, u, v, R[t])) <= 2e-6
