@@ -6,13 +6,15 @@ from the packed genotypes already resident (re-tiled once) in HBM. The reported 
 gradient passes' algorithmic bytes (ceil(n/4) * p per pass) divided by the whole-solve wall time.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32] [--seed S]
-                       [--no-cpu-baseline] [--pass-reps R] [--small]
+                       [--no-cpu-baseline] [--pass-reps R] [--small] [--copy-calibration]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +31,23 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def pass_traffic():
+    """HBM bytes per FP64 pass launch at n=5000, p=500,000 from the committed counter summary, or None when
+    the pass source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_pass_c2_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_1608_01398_amd", "csrc", "iht_device.hip")
+    try:
+        txt = open(path).read()
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"iht_device\.hip sha256 ([0-9a-f]{64})", txt)
+    t = re.search(r"traffic_bytes_per_launch_fp64: (\d+)", txt)
+    if not m or not t or m.group(1) != cur:
+        return None
+    return int(t.group(1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,6 +58,9 @@ def main():
     ap.add_argument("--pass-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--small", action="store_true", help="n=1000, p=10,000 workload (the oracle-sized case)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also launch one fill and one device-to-device copy of the packed matrix's size, "
+                         "the known-size kernels that scale the HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -67,6 +89,15 @@ def main():
     torch.cuda.synchronize()
     log(f"upload + re-tile: {time.time() - t:.2f}s (host bytes {prob['bed'].nbytes / 1e6:.0f} MB)")
     y = torch.from_numpy(prob["y"]).cuda()
+
+    if args.copy_calibration:
+        src = torch.empty(pass_bytes, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: fill + copy of {pass_bytes} bytes")
+        del src, dst
 
     def solve():
         stats = iht.Stats(geno)
@@ -138,7 +169,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": pass_traffic() if (prec == iht.FP64 and cfg == "c2") else None,
             "launch_us": round(pass_ms * 1e3, 2),
             "algorithmic_bytes_per_launch": pass_bytes,
         },
