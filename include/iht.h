@@ -48,8 +48,10 @@ extern "C" {
 #define IHT_EUNSUPPORTED (-5)
 
 /* arithmetic of the gradient pass */
-#define IHT_FP64 0 /* table entries and accumulation in FP64 (default)                     */
-#define IHT_FP32 1 /* table entries in FP32, per-tile FP32 sums accumulated in FP64         */
+#define IHT_FP64 0     /* table entries and accumulation in FP64 (default)                          */
+#define IHT_FP32 1     /* table entries in FP32, per-tile FP32 sums accumulated in FP64              */
+#define IHT_MIXED_I8 2 /* fits only: one matrix-core pass per iteration for all solves (int8 genotype */
+                       /* and residual-digit operands, exact int32 sums, FP64 combination)           */
 
 /* iht_geno_create flags: where `bed` lives */
 #define IHT_HOST_PTR 0
@@ -61,14 +63,22 @@ extern "C" {
 typedef struct iht_geno iht_geno;   /* resident, re-tiled genotype matrix on one device */
 typedef struct iht_stats iht_stats; /* u, v [p] FP64 and the subject set T they were computed on */
 
-/* Options of iht_fit. The paper fixes none of them (Methods, "IHT step sizes" only asks 0<c<<1). */
+/*
+ * Options of iht_fit and iht_fit_batch. The paper fixes none of them (Methods, "IHT step sizes"
+ * only asks 0 < c << 1). With a reduced-precision gradient (IHT_FP32, IHT_MIXED_I8) the iteration
+ * stops at max(tol, mixed_tol); each converged solve is then refined in FP64 on its final support
+ * to the least-squares fit on S and the unpenalised columns (the fixed point of the IHT map on a
+ * fixed support), with at most polish_iter conjugate-gradient steps and the stopping rule at tol.
+ */
 typedef struct iht_opts {
     double tol;            /* stop when S+ = S and ||beta+ - beta||_inf <= tol*max(1,||beta+||_inf); default 1e-10 */
     int32_t max_iter;      /* default 200                                                   */
     int32_t max_backtrack; /* step halvings allowed per iteration; default 50               */
     double c;              /* omega = (1-c)||d||^2/||A d||^2, 0 < c < 1; default 0.01        */
     double shrink;         /* mu <- shrink*mu on each backtrack, 0 < shrink < 1; default 0.5 */
-    int32_t precision;     /* IHT_FP64 or IHT_FP32 for the gradient pass; default IHT_FP64   */
+    int32_t precision;     /* IHT_FP64, IHT_FP32 or IHT_MIXED_I8; default IHT_FP64          */
+    double mixed_tol;      /* iteration tolerance of the reduced precisions; default 1e-6   */
+    int32_t polish_iter;   /* FP64 refinement steps after a reduced-precision solve; default 200 */
 } iht_opts;
 
 /* Fill *o with the defaults above. */
@@ -121,7 +131,7 @@ int iht_gradient(const iht_geno *g, const iht_stats *s, const double *r, double 
  *   stats  host array of T stats handles of this matrix (handles may repeat).
  *   R      device [T][n] FP64 residuals (row t for solve t); entries outside a solve's set ignored.
  *   G      device [T][p] FP64 output (row t = gradient of solve t).
- *   1 <= T <= 65536. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. Synchronises the stream.
+ *   1 <= T <= 65535. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. Synchronises the stream.
  */
 int iht_gradient_batch(const iht_geno *g, const iht_stats *const *stats, int32_t T, const double *R, double *G, void *stream);
 
@@ -152,11 +162,39 @@ int iht_project(const double *w, int64_t p, int32_t k, int64_t *support, double 
  *   loss_trace device [max_iter + 1] FP64 output: f at beta^0 .. beta^{n_iter}.
  *   n_iter     host int32 output: iterations performed.
  * Returns IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED, or an error (IHT_EINVAL, IHT_ENONFINITE,
- * IHT_ENOMEM, IHT_EDEVICE). Synchronises the stream.
+ * IHT_ENOMEM, IHT_EDEVICE). Synchronises the stream. Same as iht_fit_batch with T = 1.
  */
 int iht_fit(const iht_geno *g, const iht_stats *s, const double *y, const float *Z, int32_t cz, int32_t intercept, int32_t k,
             const iht_opts *opts, int64_t *support, double *beta_S, double *beta_cov, double *loss_trace, int32_t *n_iter,
             void *stream);
+
+/*
+ * Many IHT solves sharing one genotype matrix, advanced in lock-step on the device (the traits,
+ * cross-validation folds and model sizes of Methods, "Model selection"). Solve t is exactly the
+ * iht_fit of (stats[t], Y + t*ldy, ks[t]) with the shared covariates and options; its result does
+ * not depend on the other solves of the call (each one's residual digits, scale and sums are its
+ * own), so it is the same alone and in any mix.
+ *   stats      host array of T stats handles of this matrix (handles may repeat).
+ *   Y          device FP64 traits, row t at Y + t*ldy (ldy >= n).
+ *   Z, cz, intercept   as in iht_fit, shared by all solves.
+ *   ks         host int32 [T], 1 <= ks[t] <= min(p, IHT_MAX_K); kmax = max ks[t].
+ *   support    device int64 [T][kmax]: row t ascending, entries past ks[t] set to -1.
+ *   beta_S     device FP64 [T][kmax]: effects on the support, entries past ks[t] set to 0.
+ *   beta_cov   device FP64 [T][cz + intercept], or NULL if cz + intercept = 0.
+ *   loss_trace device FP64 [T][max_iter + 1]: f at beta^0 .. beta^{n_iter[t]} of each solve (with a
+ *              reduced precision the last entry is the loss after the FP64 refinement).
+ *   n_iter     host int32 [T]: iterations performed by each solve.
+ *   status     host int32 [T]: IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED or IHT_ENONFINITE per solve.
+ *   precision  IHT_FP64 / IHT_FP32 run one gradient pass per solve and iteration; IHT_MIXED_I8 runs
+ *              one matrix-core pass per iteration over the solves that need a new gradient.
+ *   1 <= T <= 65535. Returns the most severe per-solve status (an error if any solve had
+ *   non-finite input, else the largest warning), or a call-level error (IHT_EINVAL, IHT_ENOMEM,
+ *   IHT_EDEVICE). Device memory grows with T (p doubles of beta and gradient per solve, plus the
+ *   top-k candidate area of 12 p bytes per solve). Synchronises the stream.
+ */
+int iht_fit_batch(const iht_geno *g, const iht_stats *const *stats, int32_t T, const double *Y, int64_t ldy, const float *Z,
+                  int32_t cz, int32_t intercept, const int32_t *ks, const iht_opts *opts, int64_t *support, double *beta_S,
+                  double *beta_cov, double *loss_trace, int32_t *n_iter, int32_t *status, void *stream);
 
 const char *iht_status_str(int status);
 const char *iht_last_error(void);

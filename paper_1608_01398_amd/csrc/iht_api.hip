@@ -16,6 +16,7 @@
 #include "iht.h"
 #include "iht_batch.h"
 #include "iht_internal.h"
+#include "iht_solve.h"
 
 using namespace iht;
 
@@ -48,11 +49,16 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
-  hipError_t ensure(size_t b) {
+  // grows to at least b bytes (contents are lost when it grows); *fresh tells whether it did
+  hipError_t ensure(size_t b, bool* fresh = nullptr) {
+    if (fresh) *fresh = false;
     if (b <= bytes && p) return hipSuccess;
     release();
     hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
-    if (e == hipSuccess) bytes = b;
+    if (e == hipSuccess) {
+      bytes = b;
+      if (fresh) *fresh = true;
+    }
     return e;
   }
   template <class T>
@@ -71,40 +77,45 @@ Layout make_layout(int64_t n, int64_t p) {
   return L;
 }
 
-// Device work area for top-k; counters and histogram start zeroed and are self-resetting.
+// Device work area for `rows` top-k problems over p entries. The per-row counters and histogram
+// start zeroed and are self-resetting; the error words are cleared before each use.
 struct TopkArea {
-  DevBuf small;  // hist | counters | state | sel
-  DevBuf cand;
+  DevBuf small;  // rows x kTopkRowWords
+  DevBuf cand;   // rows x cap x (8 + 4) bytes
   int64_t cap = 0;
-  TopkWork tw{};
-  int ensure(int64_t p, hipStream_t st) {
-    const size_t small_bytes = kTopkBins0 * 4 + 8 * 4 + 8 * 4 + kTopkMaxK * 4;
-    if (!small.p) {
-      HIPCHK(small.ensure(small_bytes));
-      HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int32_t)(small_bytes / 4), st));
+  int32_t rows = 0;
+  int ensure(int64_t p, int32_t nrows, hipStream_t st) {
+    if (nrows > rows || !small.p) {
+      bool fresh = false;
+      const size_t words = (size_t)nrows * kTopkRowWords;
+      HIPCHK(small.ensure(words * 4, &fresh));
+      if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)words, st));
+      rows = nrows;
     }
-    if (p > cap) {
-      HIPCHK(cand.ensure(topk_cand_capacity_bytes(p)));
-      cap = p;
+    if (p > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
+      cap = std::max(cap, p);
+      HIPCHK(cand.ensure((size_t)rows * (size_t)cap * (sizeof(uint64_t) + sizeof(int32_t))));
     }
-    uint32_t* b = small.as<uint32_t>();
-    tw.hist = b;
-    tw.counters = b + kTopkBins0;
-    tw.state = b + kTopkBins0 + 8;
-    tw.sel = reinterpret_cast<int32_t*>(b + kTopkBins0 + 16);
-    tw.cand_key = cand.as<uint64_t>();
-    tw.cand_idx = reinterpret_cast<int32_t*>(cand.as<char>() + (size_t)cap * sizeof(uint64_t));
     return IHT_OK;
   }
+  uint64_t* cand_key() const { return cand.as<uint64_t>(); }
+  int32_t* cand_idx() const { return reinterpret_cast<int32_t*>(cand.as<char>() + (size_t)rows * (size_t)cap * sizeof(uint64_t)); }
 };
 
 }  // namespace
 
-// One solve's device state (grown on demand, reused by later solves on the same genotype handle).
+// Device state of a set of solves (grown on demand, reused by later fits on the same genotype
+// handle), plus the pinned host copy of their FitStates.
 namespace {
-struct FitWork {
-  DevBuf beta, g, partial, r, S, Sp, betap, Xs, Xp, bc, bcp, gc, fs, bt;
+struct SolveWork {
+  DevBuf beta, g, partial, r, S, Sp, betap, X, bc, bcp, gc, fs, uidx, udel, pw, ks, sv;
+  DevBuf r8, scale, rsum, slots, count;
   TopkArea topk;
+  FitState* host = nullptr;
+  int32_t host_cap = 0;
+  ~SolveWork() {
+    if (host) (void)hipHostFree(host);
+  }
 };
 }  // namespace
 
@@ -114,7 +125,7 @@ struct iht_geno {
   DevBuf tiled;
   // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
   DevBuf partial, state;
-  FitWork fit;
+  SolveWork fit;
   DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
 };
 
@@ -134,6 +145,8 @@ void iht_opts_default(iht_opts* o) {
   o->c = 0.01;
   o->shrink = 0.5;
   o->precision = IHT_FP64;
+  o->mixed_tol = 1e-6;
+  o->polish_iter = 200;
 }
 
 const char* iht_last_error(void) { return g_last_error.c_str(); }
@@ -293,7 +306,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
 // Work area of iht_project: one per (thread, device), kept for the life of the process.
 int iht_gradient_batch(const iht_geno* g, const iht_stats* const* stats, int32_t T, const double* R, double* G, void* stream) {
   if (!g || !stats || !R || !G) return fail(IHT_EINVAL, "iht_gradient_batch: NULL argument");
-  if (T < 1 || T > 65536) return fail(IHT_EINVAL, "iht_gradient_batch: T out of range");
+  if (T < 1 || T > 65535) return fail(IHT_EINVAL, "iht_gradient_batch: T out of range");
   std::vector<BatchSolve> sv((size_t)T);
   for (int32_t t = 0; t < T; ++t) {
     if (!stats[t]) return fail(IHT_EINVAL, "iht_gradient_batch: NULL stats handle");
@@ -309,8 +322,9 @@ int iht_gradient_batch(const iht_geno* g, const iht_stats* const* stats, int32_t
   HIPCHK(Gh->batch_rsum.ensure((size_t)Tp * 8));
   HIPCHK(Gh->batch_sv.ensure((size_t)T * sizeof(BatchSolve)));
   HIPCHK(hipMemcpyAsync(Gh->batch_sv.p, sv.data(), (size_t)T * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
-  HIPCHK(launch_gradient_batch(g->tiled.as<uint8_t>(), L, R, T, Gh->batch_sv.as<BatchSolve>(), Gh->batch_r8.as<int8_t>(),
-                               Gh->batch_scale.as<double>(), Gh->batch_rsum.as<double>(), G, L.p, st));
+  HIPCHK(launch_gradient_batch(g->tiled.as<uint8_t>(), L, R, L.n, T, Gh->batch_sv.as<BatchSolve>(), nullptr, nullptr,
+                               Gh->batch_r8.as<int8_t>(), Gh->batch_scale.as<double>(), Gh->batch_rsum.as<double>(), G, L.p,
+                               st));
   // the host copy of the per-solve table must outlive the copy
   HIPCHK(hipStreamSynchronize(st));
   return IHT_OK;
@@ -333,23 +347,256 @@ int iht_project(const double* w, int64_t p, int32_t k, int64_t* support, double*
   TopkArea* Ap = project_area();
   if (!Ap) return fail(IHT_ENOMEM, "iht_project: work area");
   TopkArea& A = *Ap;
-  int rc = A.ensure(p, st);
-  if (rc) return rc;
-  HIPCHK(launch_zero_u32(A.tw.state + 3, 1, st));
+  if (int rc = A.ensure(p, 1, st)) return rc;
+  HIPCHK(launch_topk_clear_errors(A.small.as<uint32_t>(), 1, st));
   DevBuf vals;
   HIPCHK(vals.ensure((size_t)k * 8));
-  HIPCHK(launch_topk_w(w, p, k, A.tw, support, vals.as<double>(), st));
+  TopkJob J{};
+  J.g = w;
+  J.ld = p;
+  J.k0 = k;
+  J.out = support;
+  J.ldo = k;
+  J.vals = vals.as<double>();
+  J.small = A.small.as<uint32_t>();
+  J.cand_key = A.cand_key();
+  J.cand_idx = A.cand_idx();
+  J.cap = A.cap;
+  HIPCHK(launch_topk(J, p, 1, st));
   if (w_out) {
     HIPCHK(launch_fill(w_out, p, 0.0, st));
     HIPCHK(launch_scatter(support, vals.as<double>(), k, w_out, st));
   }
   uint32_t err = 0;
-  HIPCHK(hipMemcpyAsync(&err, A.tw.state + 3, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&err, A.small.as<uint32_t>() + kTopkErrorWord, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (err & 1u) return fail(IHT_ENONFINITE, "iht_project: non-finite entry in w");
   if (err & 2u) return fail(IHT_EDEVICE, "iht_project: internal top-k count mismatch");
   return IHT_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// The solve driver behind iht_fit and iht_fit_batch. The loop follows Methods, eq. (ihta) with the
+// normalised step and the omega rule of "IHT step sizes" for every solve of the set at once; all
+// arithmetic runs in the device kernels. Each iteration is enqueued speculatively (step size,
+// proposal, backtracking test, then residual, gradient and commit for the solves whose proposal was
+// accepted) and the host reads the solves' flags once; only when some solve needs a halving does it
+// run further rounds for those solves.
+namespace {
+
+struct FitArgs {
+  const iht_geno* g;
+  const iht_stats* const* stats;
+  int32_t T;
+  const double* Y;
+  int64_t ldy;
+  Unpen U;
+  const int32_t* ks;  // host
+  iht_opts o;
+  int64_t* support;
+  double* beta_S;
+  double* beta_cov;
+  double* trace;
+  int32_t* n_iter;  // host
+  int32_t* status;  // host
+  hipStream_t st;
+};
+
+int check_opts(const iht_opts& o, const char* who) {
+  if (o.max_iter < 0 || o.max_backtrack < 0 || !(o.c > 0.0 && o.c < 1.0) || !(o.shrink > 0.0 && o.shrink < 1.0) ||
+      !(o.tol >= 0.0) || !(o.mixed_tol >= 0.0) || o.polish_iter < 0 ||
+      (o.precision != IHT_FP64 && o.precision != IHT_FP32 && o.precision != IHT_MIXED_I8))
+    return fail(IHT_EINVAL, std::string(who) + ": bad options");
+  return IHT_OK;
+}
+
+int run_fit(const FitArgs& A) {
+  const iht_geno* g = A.g;
+  const Layout& L = g->L;
+  const int32_t T = A.T;
+  const iht_opts& o = A.o;
+  hipStream_t st = A.st;
+  SolveWork& W = const_cast<iht_geno*>(g)->fit;
+  int32_t kmax = 0;
+  for (int32_t t = 0; t < T; ++t) kmax = std::max(kmax, A.ks[t]);
+  const int32_t nc = A.U.cz + A.U.icpt;
+  const size_t Tz = (size_t)T, kz = (size_t)kmax;
+
+  std::vector<BatchSolve> sv(Tz);
+  for (int32_t t = 0; t < T; ++t)
+    sv[t] = BatchSolve{A.stats[t]->u.as<double>(), A.stats[t]->v.as<double>(), A.stats[t]->mask.as<double>(), A.stats[t]->nT};
+
+  HIPCHK(W.beta.ensure(Tz * L.p * 8));
+  HIPCHK(W.g.ensure(Tz * L.p * 8));
+  const size_t pb = gradient_partial_bytes(L);
+  if (pb) HIPCHK(W.partial.ensure(pb));
+  HIPCHK(W.r.ensure(Tz * L.n_pad * 8));
+  HIPCHK(W.S.ensure(Tz * kz * 8));
+  HIPCHK(W.Sp.ensure(Tz * kz * 8));
+  HIPCHK(W.betap.ensure(Tz * kz * 8));
+  HIPCHK(W.X.ensure(Tz * 2 * kz * L.n_pad * 8));
+  HIPCHK(W.bc.ensure(Tz * kMaxUnpenalized * 8));
+  HIPCHK(W.bcp.ensure(Tz * kMaxUnpenalized * 8));
+  HIPCHK(W.gc.ensure(Tz * kMaxUnpenalized * 8));
+  HIPCHK(W.fs.ensure(Tz * sizeof(FitState)));
+  HIPCHK(W.uidx.ensure(Tz * 2 * kz * 4));
+  HIPCHK(W.udel.ensure(Tz * 2 * kz * 8));
+  HIPCHK(W.pw.ensure(Tz * 3 * (kz + kMaxUnpenalized) * 8));
+  HIPCHK(W.ks.ensure(Tz * 4));
+  HIPCHK(W.sv.ensure(Tz * sizeof(BatchSolve)));
+  if (int rc = W.topk.ensure(L.p, T, st)) return rc;
+  const bool mixed = o.precision == IHT_MIXED_I8;
+  if (mixed) {
+    HIPCHK(W.r8.ensure(batch_r8_bytes(L, T)));
+    HIPCHK(W.scale.ensure((size_t)batch_t_pad(T) * 8));
+    HIPCHK(W.rsum.ensure((size_t)batch_t_pad(T) * 8));
+    HIPCHK(W.slots.ensure(Tz * 4));
+    HIPCHK(W.count.ensure(4));
+  }
+  if (W.host_cap < T) {
+    if (W.host) (void)hipHostFree(W.host);
+    W.host = nullptr;
+    W.host_cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.host), Tz * sizeof(FitState), hipHostMallocDefault));
+    W.host_cap = T;
+  }
+  HIPCHK(hipMemcpyAsync(W.ks.p, A.ks, Tz * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.sv.p, sv.data(), Tz * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
+
+  SolveSet Q{};
+  Q.T = T;
+  Q.kmax = kmax;
+  Q.n = L.n;
+  Q.n_pad = L.n_pad;
+  Q.p = L.p;
+  Q.p_pad = L.p_pad;
+  Q.sv = W.sv.as<BatchSolve>();
+  Q.ks = W.ks.as<int32_t>();
+  Q.Y = A.Y;
+  Q.ldy = A.ldy;
+  Q.U = A.U;
+  Q.beta = W.beta.as<double>();
+  Q.g = W.g.as<double>();
+  Q.r = W.r.as<double>();
+  Q.S = W.S.as<int64_t>();
+  Q.Sp = W.Sp.as<int64_t>();
+  Q.betap = W.betap.as<double>();
+  Q.X = W.X.as<double>();
+  Q.bc = W.bc.as<double>();
+  Q.bcp = W.bcp.as<double>();
+  Q.gc = W.gc.as<double>();
+  Q.fs = W.fs.as<FitState>();
+  Q.trace = A.trace;
+  Q.ldt = (int64_t)o.max_iter + 1;
+  Q.uidx = W.uidx.as<int32_t>();
+  Q.udel = W.udel.as<double>();
+  Q.pw = W.pw.as<double>();
+
+  TopkJob J{};
+  J.beta = Q.beta;
+  J.g = Q.g;
+  J.ld = L.p;
+  J.fs = Q.fs;
+  J.ks = Q.ks;
+  J.ldo = kmax;
+  J.small = W.topk.small.as<uint32_t>();
+  J.cand_key = W.topk.cand_key();
+  J.cand_idx = W.topk.cand_idx();
+  J.cap = W.topk.cap;
+  const uint8_t* tiled = g->tiled.as<uint8_t>();
+  const double tol_main = o.precision == IHT_FP64 ? o.tol : std::max(o.tol, o.mixed_tol);
+  FitState* h = W.host;
+
+  // gradient of the solves in `phase` (kPhaseInit: every solve with finite inputs; kPhaseGo: those
+  // whose proposal was accepted)
+  auto gradient = [&](int32_t phase) -> int {
+    if (mixed) {
+      HIPCHK(solve_slots(Q.fs, T, phase, W.slots.as<int32_t>(), W.count.as<int32_t>(), st));
+      HIPCHK(launch_gradient_batch(tiled, L, Q.r, L.n_pad, T, Q.sv, W.slots.as<int32_t>(), W.count.as<int32_t>(),
+                                   W.r8.as<int8_t>(), W.scale.as<double>(), W.rsum.as<double>(), Q.g, L.p, st));
+      return IHT_OK;
+    }
+    for (int32_t t = 0; t < T; ++t)
+      HIPCHK(launch_gradient(tiled, L, Q.r + (size_t)t * L.n_pad, sv[t].mask, sv[t].nT, sv[t].u, sv[t].v, Q.fs + t,
+                             o.precision, Q.g + (size_t)t * L.p, W.partial.as<double>(),
+                             phase == kPhaseInit ? nullptr : &Q.fs[t].go, st));
+    return IHT_OK;
+  };
+  auto propose = [&](int32_t phase) -> int {
+    J.phase = phase;
+    J.out = Q.Sp;
+    J.vals = Q.betap;
+    HIPCHK(launch_topk(J, L.p, T, st));
+    HIPCHK(solve_decode(tiled, Q, 1, phase, st));
+    return IHT_OK;
+  };
+  auto tail = [&]() -> int {
+    HIPCHK(solve_residual(Q, kPhaseGo, 0, st));
+    if (int rc = gradient(kPhaseGo)) return rc;
+    HIPCHK(solve_commit(Q, tol_main, o.max_iter, st));
+    return IHT_OK;
+  };
+  auto read_states = [&]() -> int {
+    HIPCHK(hipMemcpyAsync(h, Q.fs, Tz * sizeof(FitState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return IHT_OK;
+  };
+  auto count_if = [&](auto pred) {
+    int32_t c = 0;
+    for (int32_t t = 0; t < T; ++t) c += pred(h[t]) ? 1 : 0;
+    return c;
+  };
+
+  // initial state: beta = 0, r = y on each subject set, g = A^T r, S = top-k |g| (mu = 1, beta = 0)
+  HIPCHK(launch_topk_clear_errors(J.small, T, st));
+  HIPCHK(solve_init(Q, o.max_iter, st));
+  HIPCHK(solve_residual(Q, kPhaseInit, 1, st));
+  if (int rc = gradient(kPhaseInit)) return rc;
+  J.phase = kPhaseInit;
+  J.out = Q.S;
+  J.vals = nullptr;
+  HIPCHK(launch_topk(J, L.p, T, st));
+  HIPCHK(solve_decode(tiled, Q, 0, kPhaseInit, st));
+  if (int rc = read_states()) return rc;
+
+  for (int32_t m = 0; m < o.max_iter && count_if([](const FitState& f) { return f.active != 0; }) > 0; ++m) {
+    HIPCHK(solve_mu(Q, st));
+    if (int rc = propose(kPhaseActive)) return rc;
+    HIPCHK(solve_bt_check(Q, kPhaseActive, o.c, o.max_backtrack, st));
+    if (int rc = tail()) return rc;
+    if (int rc = read_states()) return rc;
+    while (count_if([](const FitState& f) { return f.active != 0 && f.need_bt != 0; }) > 0) {
+      HIPCHK(solve_shrink(Q, o.shrink, st));
+      if (int rc = propose(kPhaseBacktrack)) return rc;
+      HIPCHK(solve_bt_check(Q, kPhaseBacktrack, o.c, o.max_backtrack, st));
+      if (int rc = tail()) return rc;
+      if (int rc = read_states()) return rc;
+    }
+  }
+  if (o.precision != IHT_FP64 && o.polish_iter > 0) HIPCHK(solve_polish(Q, o.tol, o.polish_iter, st));
+  HIPCHK(solve_output(Q, A.support, A.beta_S, A.beta_cov, kmax, nc, st));
+  std::vector<uint32_t> terr(Tz);
+  HIPCHK(hipMemcpy2DAsync(terr.data(), 4, J.small + kTopkErrorWord, (size_t)kTopkRowWords * 4, 4, Tz, hipMemcpyDeviceToHost,
+                          st));
+  if (int rc = read_states()) return rc;
+  int worst = IHT_OK;
+  for (int32_t t = 0; t < T; ++t) {
+    if (terr[t] && !h[t].nonfinite) return fail(IHT_EDEVICE, "internal top-k error");
+    A.n_iter[t] = h[t].iter;
+    A.status[t] = h[t].status;
+    if (h[t].status < 0)
+      worst = std::min(worst, h[t].status);
+    else if (worst >= 0)
+      worst = std::max(worst, h[t].status);
+  }
+  return worst;
+}
+
+}  // namespace
+
+extern "C" {
 
 int iht_fit(const iht_geno* g, const iht_stats* s, const double* y, const float* Z, int32_t cz, int32_t intercept, int32_t k,
             const iht_opts* opts, int64_t* support, double* beta_S, double* beta_cov, double* loss_trace, int32_t* n_iter,
@@ -365,130 +612,44 @@ int iht_fit(const iht_geno* g, const iht_stats* s, const double* y, const float*
   if (cz < 0 || (cz > 0 && !Z) || nc > kMaxUnpenalized) return fail(IHT_EINVAL, "iht_fit: bad covariates");
   if (nc > 0 && !beta_cov) return fail(IHT_EINVAL, "iht_fit: beta_cov is NULL");
   if (k < 1 || k > L.p || k > IHT_MAX_K) return fail(IHT_EINVAL, "iht_fit: k out of range");
-  if (o.max_iter < 0 || o.max_backtrack < 0 || !(o.c > 0.0 && o.c < 1.0) || !(o.shrink > 0.0 && o.shrink < 1.0) ||
-      !(o.tol >= 0.0) || (o.precision != IHT_FP64 && o.precision != IHT_FP32))
-    return fail(IHT_EINVAL, "iht_fit: bad options");
+  if (int rc = check_opts(o, "iht_fit")) return rc;
   *n_iter = 0;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int32_t status = IHT_OK;
+  const iht_stats* const stats[1] = {s};
+  FitArgs A{g, stats, 1, y, L.n, Unpen{Z, cz, icpt}, &k, o, support, beta_S, nc ? beta_cov : nullptr, loss_trace, n_iter,
+            &status, reinterpret_cast<hipStream_t>(stream)};
+  const int rc = run_fit(A);
+  if (rc == IHT_ENONFINITE) return fail(IHT_ENONFINITE, "iht_fit: non-finite y or Z inside the subject set");
+  return rc;
+}
 
-  FitWork& W = const_cast<iht_geno*>(g)->fit;
-  const size_t kb = (size_t)k;
-  HIPCHK(W.beta.ensure(L.p * 8));
-  HIPCHK(W.g.ensure(L.p * 8));
-  const size_t pb = gradient_partial_bytes(L);
-  if (pb) HIPCHK(W.partial.ensure(pb));
-  HIPCHK(W.r.ensure(L.n_pad * 8));
-  HIPCHK(W.S.ensure(kb * 8));
-  HIPCHK(W.Sp.ensure(kb * 8));
-  HIPCHK(W.betap.ensure(kb * 8));
-  HIPCHK(W.Xs.ensure(kb * L.n_pad * 8));
-  HIPCHK(W.Xp.ensure(kb * L.n_pad * 8));
-  HIPCHK(W.bc.ensure(kMaxUnpenalized * 8));
-  HIPCHK(W.bcp.ensure(kMaxUnpenalized * 8));
-  HIPCHK(W.gc.ensure(kMaxUnpenalized * 8));
-  HIPCHK(W.fs.ensure(sizeof(FitState)));
-  HIPCHK(W.bt.ensure(3 * kb * 8));
-  if (int rc = W.topk.ensure(L.p, st)) return rc;
-
-  double* beta = W.beta.as<double>();
-  double* gr = W.g.as<double>();
-  double* bc = W.bc.as<double>();
-  double* bcp = W.bcp.as<double>();
-  double* gc = W.gc.as<double>();
-  FitState* fs = W.fs.as<FitState>();
-  int64_t* S = W.S.as<int64_t>();
-  int64_t* Sp = W.Sp.as<int64_t>();
-  double* Xs = W.Xs.as<double>();
-  double* Xp = W.Xp.as<double>();
-  const double* mask = s->mask.as<double>();
-  const double* u = s->u.as<double>();
-  const double* v = s->v.as<double>();
-  const uint8_t* tiled = g->tiled.as<uint8_t>();
-  const Unpen U{Z, cz, icpt};
-  FitState h{};
-
-  auto read_state = [&]() -> int {
-    HIPCHK(hipMemcpyAsync(&h, fs, sizeof(FitState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return IHT_OK;
-  };
-
-  // Initialisation: beta = 0, r = y on T, g = A^T r, S = top-k |g|.
-  HIPCHK(launch_fill(beta, L.p, 0.0, st));
-  HIPCHK(launch_fill(bc, kMaxUnpenalized, 0.0, st));
-  HIPCHK(launch_zero_u32(W.topk.tw.state + 3, 1, st));
-  HIPCHK(launch_check_finite(y, Z, L.n, cz, mask, fs, st));
-  HIPCHK(launch_residual(y, Xs, W.betap.as<double>(), 0, U, bc, mask, L, W.r.as<double>(), gc, loss_trace, 0, fs, nullptr, st));
-  HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), nullptr, st));
-  HIPCHK(launch_fill(&fs->mu, 1, 1.0, st));  // top-k of |0 + 1*g| = |g|
-  HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, S, nullptr, st));
-  HIPCHK(launch_decode_cols(tiled, L, S, k, u, v, mask, Xs, st));
-  if (int rc = read_state()) return rc;
-  if (h.nonfinite) return fail(IHT_ENONFINITE, "iht_fit: non-finite y or Z inside the subject set");
-
-  // One iteration is enqueued speculatively: step size, proposal, backtracking test, and then the
-  // residual/loss, gradient and commit kernels gated on the device flag fs->go (proposal accepted
-  // or support unchanged). One host synchronisation per iteration reads the flags; only when the
-  // proposal needed backtracking does the host run the halving loop and re-enqueue the gated tail.
-  const int32_t* go = &fs->go;
-  int status = IHT_NOT_CONVERGED;
-  int32_t m = 0;
-  uint32_t terr = 0;
-  for (; m < o.max_iter; ++m) {
-    HIPCHK(launch_mu(Xs, S, k, gr, U, gc, mask, L, fs, st));
-    HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, Sp, W.betap.as<double>(), st));
-    HIPCHK(launch_decode_cols(tiled, L, Sp, k, u, v, mask, Xp, st));
-    HIPCHK(launch_bt_check(S, Xs, Sp, Xp, W.betap.as<double>(), k, beta, U, bc, gc, bcp, o.c, mask, L, fs, W.bt.as<double>(),
-                           st));
-    HIPCHK(launch_residual(y, Xp, W.betap.as<double>(), k, U, bcp, mask, L, W.r.as<double>(), gc, loss_trace, m + 1, fs, go,
-                           st));
-    HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), go, st));
-    HIPCHK(launch_commit(S, Sp, W.betap.as<double>(), k, beta, bc, bcp, nc, o.tol, fs, go, st));
-    if (int rc = read_state()) return rc;
-    if (h.den_zero) {
-      status = IHT_OK;
-      break;
-    }
-    if (!h.go) {
-      int nbt = 0;
-      bool stalled = false;
-      while (!h.same && !h.accept) {
-        if (nbt == o.max_backtrack) {
-          stalled = true;
-          break;
-        }
-        HIPCHK(launch_shrink(fs, o.shrink, st));
-        ++nbt;
-        HIPCHK(launch_topk_step(beta, gr, &fs->mu, L.p, k, W.topk.tw, Sp, W.betap.as<double>(), st));
-        HIPCHK(launch_decode_cols(tiled, L, Sp, k, u, v, mask, Xp, st));
-        HIPCHK(launch_bt_check(S, Xs, Sp, Xp, W.betap.as<double>(), k, beta, U, bc, gc, bcp, o.c, mask, L, fs,
-                               W.bt.as<double>(), st));
-        if (int rc = read_state()) return rc;
-      }
-      if (stalled) {
-        status = IHT_STALLED;
-        break;
-      }
-      HIPCHK(launch_residual(y, Xp, W.betap.as<double>(), k, U, bcp, mask, L, W.r.as<double>(), gc, loss_trace, m + 1, fs, go,
-                             st));
-      HIPCHK(launch_gradient(tiled, L, W.r.as<double>(), mask, s->nT, u, v, fs, o.precision, gr, W.partial.as<double>(), go,
-                             st));
-      HIPCHK(launch_commit(S, Sp, W.betap.as<double>(), k, beta, bc, bcp, nc, o.tol, fs, go, st));
-      if (int rc = read_state()) return rc;
-    }
-    std::swap(Xs, Xp);
-    if (h.conv) {
-      status = IHT_OK;
-      ++m;
-      break;
-    }
+int iht_fit_batch(const iht_geno* g, const iht_stats* const* stats, int32_t T, const double* Y, int64_t ldy, const float* Z,
+                  int32_t cz, int32_t intercept, const int32_t* ks, const iht_opts* opts, int64_t* support, double* beta_S,
+                  double* beta_cov, double* loss_trace, int32_t* n_iter, int32_t* status, void* stream) {
+  iht_opts o;
+  iht_opts_default(&o);
+  if (opts) o = *opts;
+  if (!g || !stats || !Y || !ks || !support || !beta_S || !loss_trace || !n_iter || !status)
+    return fail(IHT_EINVAL, "iht_fit_batch: NULL argument");
+  if (T < 1 || T > 65535) return fail(IHT_EINVAL, "iht_fit_batch: T out of range");
+  const Layout& L = g->L;
+  if (ldy < L.n) return fail(IHT_EINVAL, "iht_fit_batch: ldy < n");
+  const int32_t icpt = intercept ? 1 : 0;
+  const int32_t nc = cz + icpt;
+  if (cz < 0 || (cz > 0 && !Z) || nc > kMaxUnpenalized) return fail(IHT_EINVAL, "iht_fit_batch: bad covariates");
+  if (nc > 0 && !beta_cov) return fail(IHT_EINVAL, "iht_fit_batch: beta_cov is NULL");
+  for (int32_t t = 0; t < T; ++t) {
+    if (!stats[t]) return fail(IHT_EINVAL, "iht_fit_batch: NULL stats handle");
+    if (stats[t]->geno != g) return fail(IHT_EINVAL, "iht_fit_batch: stats belong to another genotype handle");
+    if (ks[t] < 1 || ks[t] > L.p || ks[t] > IHT_MAX_K) return fail(IHT_EINVAL, "iht_fit_batch: k out of range");
   }
-  HIPCHK(launch_output(S, k, beta, bc, nc, support, beta_S, beta_cov, st));
-  HIPCHK(hipMemcpyAsync(&terr, W.topk.tw.state + 3, 4, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (terr) return fail(IHT_EDEVICE, "iht_fit: internal top-k error");
-  *n_iter = m;
-  return status;
+  if (int rc = check_opts(o, "iht_fit_batch")) return rc;
+  for (int32_t t = 0; t < T; ++t) n_iter[t] = 0;
+  FitArgs A{g, stats, T, Y, ldy, Unpen{Z, cz, icpt}, ks, o, support, beta_S, nc ? beta_cov : nullptr, loss_trace, n_iter,
+            status, reinterpret_cast<hipStream_t>(stream)};
+  const int rc = run_fit(A);
+  if (rc == IHT_ENONFINITE) return fail(IHT_ENONFINITE, "iht_fit_batch: non-finite y or Z inside a solve's subject set");
+  return rc;
 }
 
 }  // extern "C"

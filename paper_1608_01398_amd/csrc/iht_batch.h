@@ -15,10 +15,13 @@ struct BatchSolve {
 int32_t batch_t_pad(int32_t T);
 size_t batch_r8_bytes(const Layout& L, int32_t T);
 
-// G[t * ldg + j] = (X_st^T R_t)_j for t < T, using R [T][n] (entries outside each solve's subject
-// set ignored). Work areas: R8 (batch_r8_bytes), scale and rsum (T_pad doubles each); sv is a
-// device array of T BatchSolve entries.
-hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int32_t T, const BatchSolve* sv,
-                                 int8_t* R8, double* scale, double* rsum, double* G, int64_t ldg, hipStream_t st);
+// G[t * ldg + j] = (X_st^T R_t)_j, with R_t = R + t * ldr (entries outside the solve's subject set
+// ignored). Slot s < *count computes solve t = slots[s]; with slots == NULL and count == NULL the
+// slots are the solves 0..T-1. Work areas: R8 (batch_r8_bytes), scale and rsum (T_pad doubles
+// each); sv is a device array of T BatchSolve entries. A solve's result does not depend on which
+// slot it occupies or on the other solves of the launch.
+hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
+                                 const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
+                                 double* rsum, double* G, int64_t ldg, hipStream_t st);
 
 }  // namespace iht

@@ -56,20 +56,21 @@ __device__ double bmax(double x, double* sh) {
   return sh[32];
 }
 
-// One block per (padded) solve: centre, choose the scale, write the digits and the exact digit sums.
+// One block per slot: centre the slot's residual over its subject set, choose the scale, write the
+// digits and the exact digit sums. Slots at or past the live count are skipped: a matrix-core
+// column only ever meets its own digits, so their contents never reach a live slot.
 // R8 layout: [tile][digit][T_pad][32 subjects] int8.
-__global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, int64_t n, int64_t n_pad, int32_t T,
-                                                int32_t T_pad, const BatchSolve* __restrict__ sv, int8_t* __restrict__ R8,
-                                                double* __restrict__ scale, double* __restrict__ rsum) {
+__global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, int64_t ldr, int64_t n, int64_t n_pad, int32_t T,
+                                                int32_t T_pad, const BatchSolve* __restrict__ sv,
+                                                const int32_t* __restrict__ slots, const int32_t* __restrict__ count,
+                                                int8_t* __restrict__ R8, double* __restrict__ scale,
+                                                double* __restrict__ rsum) {
   __shared__ double sh[40];
-  const int t = blockIdx.x;
-  const int64_t ntiles = n_pad / 32;
-  if (t >= T) {  // padding columns: zero digits
-    for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x)
-      for (int d = 0; d < kDigits; ++d) R8[(((i >> 5) * kDigits + d) * T_pad + t) * 32 + (i & 31)] = 0;
-    return;
-  }
-  const double* r = R + (int64_t)t * n;
+  const int slot = blockIdx.x;
+  const int live = count ? *count : T;
+  if (slot >= live) return;
+  const int t = slots ? slots[slot] : slot;
+  const double* r = R + (int64_t)t * ldr;
   const double* mask = sv[t].mask;
   double s1 = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s1 += (mask[i] != 0.0) ? r[i] : 0.0;
@@ -102,17 +103,16 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
     }
 #pragma unroll
     for (int d = 0; d < kDigits; ++d) {
-      R8[(((i >> 5) * kDigits + d) * T_pad + t) * 32 + (i & 31)] = (int8_t)q[d];
+      R8[(((i >> 5) * kDigits + d) * T_pad + slot) * 32 + (i & 31)] = (int8_t)q[d];
       sq[d] += (double)q[d];  // integer-valued, exact
     }
   }
-  (void)ntiles;
   double tot[kDigits];
 #pragma unroll
   for (int d = 0; d < kDigits; ++d) tot[d] = bsum(sq[d], sh);
   if (threadIdx.x == 0) {
-    scale[t] = s;
-    rsum[t] = s * ((tot[0] + tot[1] * (1.0 / kBase)) + tot[2] * (1.0 / (kBase * kBase)));
+    scale[slot] = s;
+    rsum[slot] = s * ((tot[0] + tot[1] * (1.0 / kBase)) + tot[2] * (1.0 / (kBase * kBase)));
   }
 }
 
@@ -132,13 +132,16 @@ __device__ __forceinline__ uint2 code_lut_entry(uint32_t b) {
 constexpr int kBlockSnps = 256;  // 4 waves x 64 SNPs
 constexpr int kBlockSolves = 32;
 
-// Block (bx, by): SNPs [256 bx, 256 bx + 256) x solves [32 by, 32 by + 32). Wave w: SNPs
+// Block (bx, by): SNPs [256 bx, 256 bx + 256) x slots [32 by, 32 by + 32). Wave w: SNPs
 // [256 bx + 64 w, +64) as two groups of 32 rows, each with a dosage and a missing-flag operand,
 // times the 3 digit column tiles: 12 accumulator tiles of 32x32 int32.
 __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
                                                   const int8_t* __restrict__ R8, int32_t T, int32_t T_pad,
-                                                  const BatchSolve* __restrict__ sv, const double* __restrict__ scale,
+                                                  const BatchSolve* __restrict__ sv, const int32_t* __restrict__ slots,
+                                                  const int32_t* __restrict__ count, const double* __restrict__ scale,
                                                   const double* __restrict__ rsum, double* __restrict__ G, int64_t ldg) {
+  const int live = count ? *count : T;
+  if ((int)blockIdx.y * kBlockSolves >= live) return;  // no live slot in this block (uniform)
   __shared__ uint2 lut[256];
   __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * 32];  // 2 x 3 KB
   const int tid = threadIdx.x;
@@ -215,10 +218,11 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
     segB = nB;
   }
 
-  // Epilogue: column col = solve tb + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
-  const int t = tb + col;
-  if (t >= T) return;
-  const double s = scale[t], Rt = rsum[t];
+  // Epilogue: column col = slot tb + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
+  const int sl = tb + col;
+  if (sl >= live) return;
+  const int t = slots ? slots[sl] : sl;
+  const double s = scale[sl], Rt = rsum[sl];
   const double* u = sv[t].u;
   const double* v = sv[t].v;
   const double i1 = 1.0 / kBase, i2 = 1.0 / (kBase * kBase);
@@ -240,15 +244,17 @@ int32_t batch_t_pad(int32_t T) { return (T + kBlockSolves - 1) / kBlockSolves * 
 
 size_t batch_r8_bytes(const Layout& L, int32_t T) { return (size_t)L.ntiles * kDigits * batch_t_pad(T) * 32; }
 
-hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int32_t T, const BatchSolve* sv,
-                                 int8_t* R8, double* scale, double* rsum, double* G, int64_t ldg, hipStream_t st) {
+hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
+                                 const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
+                                 double* rsum, double* G, int64_t ldg, hipStream_t st) {
   const int32_t T_pad = batch_t_pad(T);
-  hipLaunchKernelGGL(k_quant, dim3((unsigned)T_pad), dim3(1024), 0, st, R, L.n, L.n_pad, T, T_pad, sv, R8, scale, rsum);
+  hipLaunchKernelGGL(k_quant, dim3((unsigned)T_pad), dim3(1024), 0, st, R, ldr, L.n, L.n_pad, T, T_pad, sv, slots, count, R8,
+                     scale, rsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((L.p + kBlockSnps - 1) / kBlockSnps), (unsigned)(T_pad / kBlockSolves));
   hipLaunchKernelGGL(k_gradB, grid, dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad, (int32_t)L.ntiles,
-                     R8, T, T_pad, sv, scale, rsum, G, ldg);
+                     R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
   return hipGetLastError();
 }
 

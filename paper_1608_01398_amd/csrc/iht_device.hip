@@ -55,22 +55,6 @@ __device__ double block_sum(double x, double* sh) {
   return sh[32];
 }
 
-__device__ double block_max(double x, double* sh) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[w] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = sh[0];
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t = fmax(t, sh[i]);
-    sh[32] = t;
-  }
-  __syncthreads();
-  return sh[32];
-}
-
 // ------------------------------------------------------------------------------------------------
 // Re-tile PLINK SNP-major rows into [tile][p_pad][8 B] with a per-SNP byte rotation.
 
@@ -403,47 +387,42 @@ __global__ __launch_bounds__(256) void k_pass_finalize(const double2* __restrict
 }
 
 // ------------------------------------------------------------------------------------------------
-// Decode + standardise support columns into a [kc][n_pad] FP64 cache (Methods, "Bandwidth optimization
-// of IHT": decompress only the columns of the current support for X_k beta_k).
-
-__global__ __launch_bounds__(256) void k_decode_cols(const uint8_t* __restrict__ tiled, int64_t p_pad, int64_t n_pad,
-                                                     const int64_t* __restrict__ cols, int32_t kc,
-                                                     const double* __restrict__ u, const double* __restrict__ v,
-                                                     const double* __restrict__ mask, double* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int q = blockIdx.y;
-  if (i >= n_pad || q >= kc) return;
-  const int64_t j = cols[q];
-  const int64_t t = i / kTileSubjects;
-  const int grp = (int)((i % kTileSubjects) >> 2);
-  const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
-  const uint8_t byte = tiled[(t * p_pad + j) * kSegBytes + b];
-  const int code = (byte >> (2 * (i & 3))) & 3;
-  double x = 0.0;
-  if (mask[i] != 0.0 && code != 1) {
-    const double d = (code == 0) ? 0.0 : (double)(code - 1);
-    x = v[j] * (d - u[j]);
-  }
-  out[(int64_t)q * n_pad + i] = x;
-}
-
-// ------------------------------------------------------------------------------------------------
 // Top-k of |w| with ties to the lower index (the projection of eq. ihta).
 // Level 0: 8192-bin histogram of key bits 62..50 (key = IEEE bits of |w|) -> threshold bucket.
 // Collect: keys above the bucket are selected; keys in it are candidates. The last block finds the
 // exact remainder among the candidates by radix select on the unique 96-bit key (|w| bits, ~index),
 // then sorts the k indices ascending.
 
-struct SrcW {
-  const double* w;
-  __device__ double at(int64_t j) const { return w[j]; }
-};
-struct SrcStep {
-  const double* beta;
+// Row t of a TopkJob: the values it ranks, its k and its work area.
+struct TopkRow {
+  const double* beta;  // NULL: w = g
   const double* g;
   double mu;
-  __device__ double at(int64_t j) const { return __dadd_rn(beta[j], __dmul_rn(mu, g[j])); }
+  int32_t k;
+  TopkWork tw;
+  int64_t* out;
+  double* vals;
+  __device__ double at(int64_t j) const { return beta ? __dadd_rn(beta[j], __dmul_rn(mu, g[j])) : g[j]; }
 };
+
+// false when row t is outside the job's phase (the whole block then returns).
+__device__ __forceinline__ bool topk_row(const TopkJob& J, int t, TopkRow& R) {
+  if (J.fs && !fs_selected(J.fs + t, J.phase)) return false;
+  R.beta = J.beta ? J.beta + (int64_t)t * J.ld : nullptr;
+  R.g = J.g + (int64_t)t * J.ld;
+  R.mu = J.beta ? J.fs[t].mu : 0.0;
+  R.k = J.ks ? J.ks[t] : J.k0;
+  uint32_t* b = J.small + (int64_t)t * kTopkRowWords;
+  R.tw.hist = b;
+  R.tw.counters = b + kTopkBins0;
+  R.tw.state = b + kTopkBins0 + 8;
+  R.tw.sel = reinterpret_cast<int32_t*>(b + kTopkBins0 + 16);
+  R.tw.cand_key = J.cand_key + (int64_t)t * J.cap;
+  R.tw.cand_idx = J.cand_idx + (int64_t)t * J.cap;
+  R.out = J.out + (int64_t)t * J.ldo;
+  R.vals = J.vals ? J.vals + (int64_t)t * J.ldo : nullptr;
+  return true;
+}
 
 __device__ __forceinline__ uint64_t abs_key(double w) { return (uint64_t)__double_as_longlong(fabs(w)); }
 
@@ -484,13 +463,14 @@ __device__ __forceinline__ bool key_before(uint64_t ka, int32_t ia, uint64_t kb,
   return ka > kb || (ka == kb && ia < ib);
 }
 
-template <class Src>
-__global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
-                                                    int32_t k, TopkWork tw) {
+__global__ __launch_bounds__(1024) void k_topk_hist(TopkJob J, int64_t p, int64_t chunk) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.y, src)) return;
+  const TopkWork& tw = src.tw;
+  const int32_t k = src.k;
   __shared__ uint32_t h[kTopkBins0];
   __shared__ uint32_t res[4];
   __shared__ uint32_t ticket;
-  if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
   for (int i = threadIdx.x; i < kTopkBins0; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const int64_t b = (int64_t)blockIdx.x * chunk, e = min(p, b + chunk);
@@ -526,17 +506,19 @@ __global__ __launch_bounds__(1024) void k_topk_hist(Src src, const double* __res
 
 constexpr int kCandLds = 2048;  // candidates ranked directly in LDS when there are at most this many
 
-template <class Src>
-__global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __restrict__ mu_ptr, int64_t p, int64_t chunk,
-                                                       int32_t k, TopkWork tw, int64_t* __restrict__ support,
-                                                       double* __restrict__ vals) {
+__global__ __launch_bounds__(1024) void k_topk_collect(TopkJob J, int64_t p, int64_t chunk) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.y, src)) return;
+  const TopkWork& tw = src.tw;
+  const int32_t k = src.k;
+  int64_t* __restrict__ support = src.out;
+  double* __restrict__ vals = src.vals;
   __shared__ int32_t sel[kTopkMaxK];
   __shared__ uint64_t ck[kCandLds];
   __shared__ int32_t ci[kCandLds];
   __shared__ uint32_t h[4096];
   __shared__ uint32_t res[4];
   __shared__ uint32_t ticket, nsel_l;
-  if constexpr (std::is_same<Src, SrcStep>::value) src.mu = *mu_ptr;
   const uint32_t bucket = tw.state[0];
   const int64_t b = (int64_t)blockIdx.x * chunk, e = min(p, b + chunk);
   for (int64_t j = b + threadIdx.x; j < e; j += blockDim.x) {
@@ -621,8 +603,12 @@ __global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __
       const int32_t x = sel[q];
       int rank = 0;
       for (int q2 = 0; q2 < k; ++q2) rank += (sel[q2] < x) ? 1 : 0;
-      support[rank] = x;
-      if (vals) vals[rank] = src.at(x);
+      const bool ok = x >= 0 && x < p && rank < k;  // always true when the counts agree
+      if (!ok) atomicOr(&tw.state[3], 2u);
+      if (rank < k) {
+        support[rank] = ok ? x : 0;
+        if (vals) vals[rank] = ok ? src.at(x) : 0.0;
+      }
     }
   } else {
     int N = 1;
@@ -646,8 +632,11 @@ __global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __
       }
     }
     for (int q = threadIdx.x; q < k; q += blockDim.x) {
-      support[q] = sel[q];
-      if (vals) vals[q] = src.at(sel[q]);
+      const int32_t x = sel[q];
+      const bool ok = x >= 0 && x < p;  // always true when the counts agree
+      if (!ok) atomicOr(&tw.state[3], 2u);
+      support[q] = ok ? x : 0;
+      if (vals) vals[q] = ok ? src.at(x) : 0.0;
     }
   }
   if (threadIdx.x == 0) {
@@ -657,310 +646,14 @@ __global__ __launch_bounds__(1024) void k_topk_collect(Src src, const double* __
   }
 }
 
-// ------------------------------------------------------------------------------------------------
-// Solve steps (one workgroup each; n and k are small next to the pass).
-
-__global__ __launch_bounds__(1024) void k_check_finite(const double* __restrict__ y, const float* __restrict__ Z, int64_t n,
-                                                       int32_t cz, const double* __restrict__ mask, FitState* fs) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  int b = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    if (mask[i] == 0.0) continue;
-    if (!isfinite(y[i])) b = 1;
-    for (int c = 0; c < cz; ++c)
-      if (!isfinite(Z[(int64_t)c * n + i])) b = 1;
-  }
-  if (b) atomicOr(&bad, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) fs->nonfinite = bad;
-}
-
-constexpr int kSubjUnroll = 4;  // subjects per thread in flight in the single-block step kernels
-
-// r = mask (y - A_{cols,C} b); loss = 1/2 ||r||^2 (eq. leastsquaresloss); covariate gradient gc = A_C^T r.
-// Skipped entirely when the gate flag is 0 (a proposal that still needs backtracking).
-__global__ __launch_bounds__(1024) void k_residual(const double* __restrict__ y, const double* __restrict__ X,
-                                                   const double* __restrict__ bvals, int32_t kc, Unpen U,
-                                                   const double* __restrict__ bc, const double* __restrict__ mask,
-                                                   int64_t n, int64_t n_pad, double* __restrict__ r, double* __restrict__ gc,
-                                                   double* __restrict__ trace, int32_t trace_idx, FitState* fs,
-                                                   const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  __shared__ double sh[40];
-  __shared__ double bl[kTopkMaxK];
-  __shared__ double bcl[kMaxUnpenalized];
-  const int nc = U.cz + U.icpt;
-  for (int q = threadIdx.x; q < kc; q += blockDim.x) bl[q] = bvals[q];
-  for (int q = threadIdx.x; q < nc; q += blockDim.x) bcl[q] = bc[q];
-  __syncthreads();
-  double rr = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
-    int64_t ii[kSubjUnroll];
-    bool ok[kSubjUnroll];
-    double sm[kSubjUnroll];
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      ii[w] = i0 + (int64_t)w * blockDim.x;
-      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
-      if (ii[w] >= n) ii[w] = 0;
-      sm[w] = 0.0;
-    }
-    for (int q = 0; q < kc; ++q) {
-      const double bq = bl[q];
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += X[(int64_t)q * n_pad + ii[w]] * bq;
-    }
-    for (int c = 0; c < U.cz; ++c) {
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)c * n + ii[w]] * bcl[c];
-    }
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      if (U.icpt) sm[w] += 1.0 * bcl[U.cz];
-      const int64_t i = i0 + (int64_t)w * blockDim.x;
-      if (i < n) {
-        const double ri = ok[w] ? y[i] - sm[w] : 0.0;
-        r[i] = ri;
-        rr += ri * ri;
-      }
-    }
-  }
-  const double loss = 0.5 * block_sum(rr, sh);
-  for (int c = 0; c < nc; ++c) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-      const double a = (c < U.cz) ? (double)U.Z[(int64_t)c * n + i] : 1.0;
-      s += (mask[i] != 0.0) ? a * r[i] : 0.0;
-    }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) gc[c] = s;
-  }
-  if (threadIdx.x == 0) {
-    trace[trace_idx] = loss;
-    fs->loss = loss;
-  }
-}
-
-// Normalised step mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2.
-__global__ __launch_bounds__(1024) void k_mu(const double* __restrict__ Xs, const int64_t* __restrict__ S, int32_t k,
-                                             const double* __restrict__ g, Unpen U, const double* __restrict__ gc,
-                                             const double* __restrict__ mask, int64_t n, int64_t n_pad, FitState* fs) {
-  __shared__ double sh[40];
-  __shared__ double gl[kTopkMaxK];
-  __shared__ double gcl[kMaxUnpenalized];
-  const int nc = U.cz + U.icpt;
-  for (int q = threadIdx.x; q < k; q += blockDim.x) gl[q] = g[S[q]];
-  for (int q = threadIdx.x; q < nc; q += blockDim.x) gcl[q] = gc[q];
-  __syncthreads();
-  double num = 0.0;
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < k; ++q) num += gl[q] * gl[q];
-    for (int q = 0; q < nc; ++q) num += gcl[q] * gcl[q];
-  }
-  double dd = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
-    int64_t ii[kSubjUnroll];
-    bool ok[kSubjUnroll];
-    double sm[kSubjUnroll];
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      ii[w] = i0 + (int64_t)w * blockDim.x;
-      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
-      if (ii[w] >= n) ii[w] = 0;
-      sm[w] = 0.0;
-    }
-    for (int q = 0; q < k; ++q) {
-      const double gq = gl[q];
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += Xs[(int64_t)q * n_pad + ii[w]] * gq;
-    }
-    for (int c = 0; c < U.cz; ++c) {
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)c * n + ii[w]] * gcl[c];
-    }
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      if (U.icpt) sm[w] += 1.0 * gcl[U.cz];
-      if (ok[w]) dd += sm[w] * sm[w];
-    }
-  }
-  const double den = block_sum(dd, sh);
-  if (threadIdx.x == 0) {
-    fs->num = num;
-    fs->den = den;
-    fs->den_zero = (den == 0.0);
-    fs->mu = (den == 0.0) ? 0.0 : num / den;
-  }
-}
-
-// Support comparison, unpenalised proposal bcp = bc + mu gc, and (if the support moved)
-// omega = (1-c)||Delta||^2 / ||A Delta||^2 over S u S+ u C with accept = mu < omega.
-__global__ __launch_bounds__(1024) void k_bt_check(const int64_t* __restrict__ S, const double* __restrict__ Xs,
-                                                   const int64_t* __restrict__ Sp, const double* __restrict__ Xp,
-                                                   const double* __restrict__ betap, int32_t k,
-                                                   const double* __restrict__ beta, Unpen U, const double* __restrict__ bc,
-                                                   const double* __restrict__ gc, double* __restrict__ bcp, double c,
-                                                   const double* __restrict__ mask, int64_t n, int64_t n_pad, FitState* fs,
-                                                   int32_t* __restrict__ uidx /* [2k] */, double* __restrict__ udel /* [2k] */) {
-  __shared__ double sh[40];
-  __shared__ double dcl[kMaxUnpenalized];
-  __shared__ int same_s, nu_s;
-  __shared__ double dd_s;
-  const int nc = U.cz + U.icpt;
-  const double mu = fs->mu;
-  if (threadIdx.x == 0) {
-    int same = 1;
-    for (int q = 0; q < k; ++q)
-      if (S[q] != Sp[q]) same = 0;
-    same_s = same;
-    double dd = 0.0;
-    int nu = 0;
-    if (!same) {
-      // merge S and S+ ascending; uidx encodes the column source: q (from Xs) or -(q+1) (from Xp)
-      int a = 0, b = 0;
-      while (a < k || b < k) {
-        if (b >= k || (a < k && S[a] < Sp[b])) {
-          const double d = 0.0 - beta[S[a]];
-          uidx[nu] = a;
-          udel[nu++] = d;
-          dd += d * d;
-          ++a;
-        } else if (a >= k || Sp[b] < S[a]) {
-          const double d = betap[b] - 0.0;
-          uidx[nu] = -(b + 1);
-          udel[nu++] = d;
-          dd += d * d;
-          ++b;
-        } else {
-          const double d = betap[b] - beta[S[a]];
-          uidx[nu] = -(b + 1);
-          udel[nu++] = d;
-          dd += d * d;
-          ++a;
-          ++b;
-        }
-      }
-    }
-    for (int q = 0; q < nc; ++q) {
-      const double np = bc[q] + mu * gc[q];
-      bcp[q] = np;
-      const double d = np - bc[q];
-      dcl[q] = d;
-      dd += d * d;
-    }
-    nu_s = nu;
-    dd_s = dd;
-  }
-  __syncthreads();
-  if (same_s) {
-    if (threadIdx.x == 0) {
-      fs->same = 1;
-      fs->accept = 1;
-      fs->omega = 0.0;
-      fs->go = fs->den_zero ? 0 : 1;
-    }
-    return;
-  }
-  const int nu = nu_s;
-  double sa = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kSubjUnroll * blockDim.x) {
-    int64_t ii[kSubjUnroll];
-    bool ok[kSubjUnroll];
-    double sm[kSubjUnroll];
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      ii[w] = i0 + (int64_t)w * blockDim.x;
-      ok[w] = ii[w] < n && mask[ii[w] < n ? ii[w] : 0] != 0.0;
-      if (ii[w] >= n) ii[w] = 0;
-      sm[w] = 0.0;
-    }
-    for (int q = 0; q < nu; ++q) {
-      const int src = uidx[q];
-      const double* col = (src >= 0) ? Xs + (int64_t)src * n_pad : Xp + (int64_t)(-src - 1) * n_pad;
-      const double dq = udel[q];
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += col[ii[w]] * dq;
-    }
-    for (int cc = 0; cc < U.cz; ++cc) {
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)U.Z[(int64_t)cc * n + ii[w]] * dcl[cc];
-    }
-#pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      if (U.icpt) sm[w] += 1.0 * dcl[U.cz];
-      if (ok[w]) sa += sm[w] * sm[w];
-    }
-  }
-  const double dA = block_sum(sa, sh);
-  if (threadIdx.x == 0) {
-    const double omega = (1.0 - c) * dd_s / dA;
-    fs->same = 0;
-    fs->omega = omega;
-    fs->accept = (mu < omega);
-    fs->go = (!fs->den_zero && mu < omega) ? 1 : 0;
-  }
-}
-
-__global__ void k_shrink(FitState* fs, double shrink) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) fs->mu = fs->mu * shrink;
-}
-
-// Convergence test (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf)), then beta <- beta+.
-// When S+ = S the union of the supports is S itself, so the infinity norms run over S+ and C.
-__global__ __launch_bounds__(1024) void k_commit(int64_t* __restrict__ S, const int64_t* __restrict__ Sp,
-                                                 const double* __restrict__ betap, int32_t k, double* __restrict__ beta,
-                                                 double* __restrict__ bc, const double* __restrict__ bcp, int32_t nc,
-                                                 double tol, FitState* fs, const int32_t* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  __shared__ double sh[40];
-  __shared__ int same_s;
-  if (threadIdx.x == 0) same_s = 1;
-  __syncthreads();
-  double dmax = 0.0, bmax = 0.0;
-  for (int q = threadIdx.x; q < k; q += blockDim.x) {
-    if (S[q] != Sp[q]) atomicAnd(&same_s, 0);
-    dmax = fmax(dmax, fabs(betap[q] - beta[Sp[q]]));
-    bmax = fmax(bmax, fabs(betap[q]));
-  }
-  for (int q = threadIdx.x; q < nc; q += blockDim.x) {
-    dmax = fmax(dmax, fabs(bcp[q] - bc[q]));
-    bmax = fmax(bmax, fabs(bcp[q]));
-  }
-  dmax = block_max(dmax, sh);
-  bmax = block_max(bmax, sh);
-  const int same = same_s;
-  const int conv = same && dmax <= tol * fmax(1.0, bmax);
-  __syncthreads();
-  for (int q = threadIdx.x; q < k; q += blockDim.x) beta[S[q]] = 0.0;
-  __syncthreads();
-  for (int q = threadIdx.x; q < k; q += blockDim.x) {
-    beta[Sp[q]] = betap[q];
-    S[q] = Sp[q];
-  }
-  for (int q = threadIdx.x; q < nc; q += blockDim.x) bc[q] = bcp[q];
-  if (threadIdx.x == 0) {
-    fs->conv = conv;
-    fs->same = same;
-    fs->dmax = dmax;
-    fs->bmax = bmax;
-  }
-}
-
-__global__ void k_output(const int64_t* __restrict__ S, int32_t k, const double* __restrict__ beta,
-                         const double* __restrict__ bc, int32_t nc, int64_t* __restrict__ support,
-                         double* __restrict__ beta_S, double* __restrict__ beta_cov) {
-  for (int q = threadIdx.x; q < k; q += blockDim.x) {
-    support[q] = S[q];
-    beta_S[q] = beta[S[q]];
-  }
-  for (int q = threadIdx.x; q < nc; q += blockDim.x) beta_cov[q] = bc[q];
-}
-
-__global__ void k_zero_u32(uint32_t* __restrict__ x, int32_t n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_u32(uint32_t* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0u;
+}
+
+__global__ void k_topk_clear_errors(uint32_t* __restrict__ small, int32_t rows) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < rows) small[t * kTopkRowWords + kTopkErrorWord] = 0u;
 }
 
 __global__ void k_fill(double* __restrict__ x, int64_t n, double val) {
@@ -1087,90 +780,26 @@ hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* 
   return e;
 }
 
-hipError_t launch_decode_cols(const uint8_t* tiled, const Layout& L, const int64_t* cols, int32_t kc, const double* u,
-                              const double* v, const double* mask, double* out, hipStream_t st) {
-  if (kc <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((L.n_pad + 255) / 256), (unsigned)kc);
-  hipLaunchKernelGGL(k_decode_cols, grid, dim3(256), 0, st, tiled, L.p_pad, L.n_pad, cols, kc, u, v, mask, out);
-  return hipGetLastError();
-}
-
-size_t topk_cand_capacity_bytes(int64_t p) { return (size_t)p * (sizeof(uint64_t) + sizeof(int32_t)); }
-
-static const int64_t kTopkChunk = 4096;
-
-template <class Src>
-static hipError_t launch_topk(Src src, const double* mu_ptr, int64_t p, int32_t k, const TopkWork& tw, int64_t* support,
-                              double* vals, hipStream_t st) {
-  const int64_t blocks = (p + kTopkChunk - 1) / kTopkChunk;
-  hipLaunchKernelGGL((k_topk_hist<Src>), dim3((unsigned)blocks), dim3(1024), 0, st, src, mu_ptr, p, kTopkChunk, k, tw);
+hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st) {
+  // chunk per block: about 2048 blocks over all rows, between 4096 and 65536 entries
+  int64_t chunk = 4096;
+  while (chunk < 65536 && (p + chunk - 1) / chunk * rows > 2048) chunk <<= 1;
+  const dim3 grid((unsigned)((p + chunk - 1) / chunk), (unsigned)rows);
+  hipLaunchKernelGGL(k_topk_hist, grid, dim3(1024), 0, st, J, p, chunk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_topk_collect<Src>), dim3((unsigned)blocks), dim3(1024), 0, st, src, mu_ptr, p, kTopkChunk, k, tw,
-                     support, vals);
+  hipLaunchKernelGGL(k_topk_collect, grid, dim3(1024), 0, st, J, p, chunk);
   return hipGetLastError();
 }
 
-hipError_t launch_topk_w(const double* w, int64_t p, int32_t k, const TopkWork& tw, int64_t* support, double* vals,
-                         hipStream_t st) {
-  return launch_topk(SrcW{w}, nullptr, p, k, tw, support, vals, st);
-}
-
-hipError_t launch_topk_step(const double* beta, const double* g, const double* mu, int64_t p, int32_t k, const TopkWork& tw,
-                            int64_t* support, double* vals, hipStream_t st) {
-  return launch_topk(SrcStep{beta, g, 0.0}, mu, p, k, tw, support, vals, st);
-}
-
-hipError_t launch_check_finite(const double* y, const float* Z, int64_t n, int32_t cz, const double* mask, FitState* fs,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(1024), 0, st, y, Z, n, cz, mask, fs);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual(const double* y, const double* X, const double* bvals, int32_t kc, Unpen U, const double* bc,
-                           const double* mask, const Layout& L, double* r, double* gc, double* trace, int32_t trace_idx,
-                           FitState* fs, const int32_t* gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3(1), dim3(1024), 0, st, y, X, bvals, kc, U, bc, mask, L.n, L.n_pad, r, gc, trace,
-                     trace_idx, fs, gate);
-  return hipGetLastError();
-}
-
-hipError_t launch_mu(const double* Xs, const int64_t* S, int32_t k, const double* g, Unpen U, const double* gc,
-                     const double* mask, const Layout& L, FitState* fs, hipStream_t st) {
-  hipLaunchKernelGGL(k_mu, dim3(1), dim3(1024), 0, st, Xs, S, k, g, U, gc, mask, L.n, L.n_pad, fs);
-  return hipGetLastError();
-}
-
-hipError_t launch_bt_check(const int64_t* S, const double* Xs, const int64_t* Sp, const double* Xp, const double* betap_vals,
-                           int32_t k, const double* beta, Unpen U, const double* bc, const double* gc, double* bcp, double c,
-                           const double* mask, const Layout& L, FitState* fs, double* work, hipStream_t st) {
-  int32_t* uidx = reinterpret_cast<int32_t*>(work);
-  double* udel = work + k;  // work holds >= 3k doubles: [2k int32 | 2k doubles]
-  hipLaunchKernelGGL(k_bt_check, dim3(1), dim3(1024), 0, st, S, Xs, Sp, Xp, betap_vals, k, beta, U, bc, gc, bcp, c, mask, L.n,
-                     L.n_pad, fs, uidx, udel);
-  return hipGetLastError();
-}
-
-hipError_t launch_shrink(FitState* fs, double shrink, hipStream_t st) {
-  hipLaunchKernelGGL(k_shrink, dim3(1), dim3(64), 0, st, fs, shrink);
-  return hipGetLastError();
-}
-
-hipError_t launch_commit(int64_t* S, const int64_t* Sp, const double* betap_vals, int32_t k, double* beta, double* bc,
-                         const double* bcp, int32_t nc, double tol, FitState* fs, const int32_t* gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_commit, dim3(1), dim3(1024), 0, st, S, Sp, betap_vals, k, beta, bc, bcp, nc, tol, fs, gate);
-  return hipGetLastError();
-}
-
-hipError_t launch_output(const int64_t* S, int32_t k, const double* beta, const double* bc, int32_t nc, int64_t* support,
-                         double* beta_S, double* beta_cov, hipStream_t st) {
-  hipLaunchKernelGGL(k_output, dim3(1), dim3(1024), 0, st, S, k, beta, bc, nc, support, beta_S, beta_cov);
-  return hipGetLastError();
-}
-
-hipError_t launch_zero_u32(uint32_t* x, int32_t n, hipStream_t st) {
+hipError_t launch_zero_u32(uint32_t* x, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, hipStream_t st) {
+  hipLaunchKernelGGL(k_topk_clear_errors, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, small, rows);
   return hipGetLastError();
 }
 

@@ -33,25 +33,69 @@ struct Layout {
   int64_t p_pad;   // p rounded up to kSnpAlign
 };
 
-// Scalars of one solve, resident on the device; the host reads the flags once per decision.
+// Scalars and control state of one solve, resident on the device. Every per-solve kernel checks
+// its phase against these flags, so a launch over many solves touches only the ones concerned.
 struct FitState {
   double mu, omega, num, den;
   double loss, mean, Rsum;
   double dmax, bmax;
   int32_t same, accept, den_zero, conv;
   int32_t nonfinite, topk_error;
-  int32_t go;  // proposal accepted (or support unchanged) and mu defined: the gated kernels run
-  int32_t pad1;
+  int32_t go;       // proposal accepted (or support unchanged): residual, gradient and commit run
+  int32_t active;   // still iterating
+  int32_t need_bt;  // proposal rejected: halve mu and propose again
+  int32_t nbt;      // halvings in this iteration
+  int32_t iter;     // committed iterations
+  int32_t status;   // IHT_OK / IHT_NOT_CONVERGED / IHT_STALLED / IHT_ENONFINITE
+  int32_t xcur;     // which of the solve's two column caches holds the columns of S
+  int32_t polish_steps;
 };
 
-// Top-k work area (counters are self-resetting: the last block of each kernel clears them).
+// Launch phases of the per-solve kernels: every solve; solves with finite inputs (the initial
+// gradient and support); solves still iterating; those whose proposal needs a halving; those whose
+// proposal was accepted.
+enum : int32_t { kPhaseAll = 0, kPhaseActive = 1, kPhaseBacktrack = 2, kPhaseGo = 3, kPhaseInit = 4 };
+
+__device__ __forceinline__ bool fs_selected(const FitState* fs, int32_t phase) {
+  if (phase == kPhaseAll) return true;
+  if (phase == kPhaseInit) return fs->nonfinite == 0;
+  if (phase == kPhaseActive) return fs->active != 0;
+  if (phase == kPhaseBacktrack) return fs->active != 0 && fs->need_bt != 0;
+  return fs->active != 0 && fs->go != 0;
+}
+
+// Top-k work area of one row (counters are self-resetting: the last block of each kernel clears
+// them). Rows are laid out kTopkRowWords apart in one small buffer; candidates `cap` apart.
 struct TopkWork {
   uint32_t* hist;      // [kTopkBins0]
   uint32_t* counters;  // [8]: 0 hist ticket, 1 collect ticket, 2 n_sel, 3 n_cand
-  uint32_t* state;     // [4]: bucket, n_above, n_eq, error
+  uint32_t* state;     // [8]: bucket, n_above, n_eq, error (bit 0 non-finite, bit 1 count mismatch)
   int32_t* sel;        // [kTopkMaxK]
-  uint64_t* cand_key;  // [p]
-  int32_t* cand_idx;   // [p]
+  uint64_t* cand_key;  // [cap]
+  int32_t* cand_idx;   // [cap]
+};
+constexpr int64_t kTopkRowWords = kTopkBins0 + 8 + 8 + kTopkMaxK;
+constexpr int64_t kTopkErrorWord = kTopkBins0 + 8 + 3;  // state[3] of a row
+
+// Many top-k problems in one launch (grid row t = problem t). Row t projects
+//   w = g_t                     (beta == NULL), or
+//   w = beta_t + mu_t g_t       (mu_t = fs[t].mu),
+// keeping k_t = ks ? ks[t] : k0 entries; rows whose FitState is outside `phase` are skipped.
+struct TopkJob {
+  const double* beta;
+  const double* g;
+  int64_t ld;  // row stride of beta and g
+  const FitState* fs;
+  int32_t phase;
+  int32_t k0;
+  const int32_t* ks;
+  int64_t* out;  // support rows (ascending), stride ldo
+  int64_t ldo;
+  double* vals;  // w at the support, stride ldo (may be NULL)
+  uint32_t* small;  // row t at small + t * kTopkRowWords
+  uint64_t* cand_key;
+  int32_t* cand_idx;
+  int64_t cap;  // candidate slots per row (>= p)
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
@@ -72,39 +116,20 @@ size_t gradient_partial_bytes(const Layout& L);
 hipError_t launch_decode_cols(const uint8_t* tiled, const Layout& L, const int64_t* cols, int32_t kc, const double* u,
                               const double* v, const double* mask, double* out, hipStream_t st);
 
-// Top-k of |w_j| (w given) or of |beta_j + mu g_j|; writes support (ascending) and the w values there.
-hipError_t launch_topk_w(const double* w, int64_t p, int32_t k, const TopkWork& tw, int64_t* support, double* vals,
-                         hipStream_t st);
-hipError_t launch_topk_step(const double* beta, const double* g, const double* mu, int64_t p, int32_t k, const TopkWork& tw,
-                            int64_t* support, double* vals, hipStream_t st);
-size_t topk_cand_capacity_bytes(int64_t p);
+// Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.
+hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st);
+// Zero the error word of rows 0 .. rows-1 of a top-k work area.
+hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, hipStream_t st);
 
-// ---- single-workgroup solve steps ----
+// Unpenalised columns: dense covariates and the intercept.
 struct Unpen {
   const float* Z;  // [cz][n] column-major covariates
   int32_t cz;
   int32_t icpt;
 };
 
-hipError_t launch_check_finite(const double* y, const float* Z, int64_t n, int32_t cz, const double* mask, FitState* fs,
-                               hipStream_t st);
-// r = mask*(y - X_cols b - Z bc), loss and covariate gradient gc; trace[idx] = loss.
-// Gated launches (residual, gradient, commit) do nothing when *gate == 0; gate may be NULL.
-hipError_t launch_residual(const double* y, const double* X, const double* bvals, int32_t kc, Unpen U, const double* bc,
-                           const double* mask, const Layout& L, double* r, double* gc, double* trace, int32_t trace_idx,
-                           FitState* fs, const int32_t* gate, hipStream_t st);
-hipError_t launch_mu(const double* Xs, const int64_t* S, int32_t k, const double* g, Unpen U, const double* gc,
-                     const double* mask, const Layout& L, FitState* fs, hipStream_t st);
-hipError_t launch_bt_check(const int64_t* S, const double* Xs, const int64_t* Sp, const double* Xp, const double* betap_vals,
-                           int32_t k, const double* beta, Unpen U, const double* bc, const double* gc, double* bcp,
-                           double c, const double* mask, const Layout& L, FitState* fs, double* work, hipStream_t st);
-hipError_t launch_shrink(FitState* fs, double shrink, hipStream_t st);
-hipError_t launch_commit(int64_t* S, const int64_t* Sp, const double* betap_vals, int32_t k, double* beta, double* bc,
-                         const double* bcp, int32_t nc, double tol, FitState* fs, const int32_t* gate, hipStream_t st);
-hipError_t launch_output(const int64_t* S, int32_t k, const double* beta, const double* bc, int32_t nc, int64_t* support,
-                         double* beta_S, double* beta_cov, hipStream_t st);
 hipError_t launch_fill(double* x, int64_t n, double val, hipStream_t st);
-hipError_t launch_zero_u32(uint32_t* x, int32_t n, hipStream_t st);
+hipError_t launch_zero_u32(uint32_t* x, int64_t n, hipStream_t st);
 hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, double* out, hipStream_t st);
 
 }  // namespace iht

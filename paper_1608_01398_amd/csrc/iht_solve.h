@@ -1,0 +1,50 @@
+// iht_solve.h -- device state of a set of IHT solves and the per-solve step launchers.
+#pragma once
+#include "iht_batch.h"
+#include "iht_internal.h"
+
+namespace iht {
+
+// T solves sharing one genotype matrix; solve t works on its subject set sv[t], its trait
+// Y + t * ldy and its model size ks[t] <= kmax. All arrays are device memory.
+struct SolveSet {
+  int32_t T, kmax;
+  int64_t n, n_pad, p, p_pad;
+  const BatchSolve* sv;  // [T]
+  const int32_t* ks;     // [T]
+  const double* Y;       // [T][ldy]
+  int64_t ldy;
+  Unpen U;
+  double* beta;  // [T][p] dense coefficients (zero off the support)
+  double* g;     // [T][p] gradient X_st^T r
+  double* r;     // [T][n_pad] residual (zero outside the subject set)
+  int64_t* S;    // [T][kmax] support, ascending
+  int64_t* Sp;   // [T][kmax] proposed support
+  double* betap;  // [T][kmax] proposal on Sp
+  double* X;      // [T][2][kmax][n_pad] two caches of decoded support columns (FitState::xcur)
+  double* bc;     // [T][kMaxUnpenalized] unpenalised coefficients
+  double* bcp;    // [T][kMaxUnpenalized] their proposal
+  double* gc;     // [T][kMaxUnpenalized] A_C^T r
+  FitState* fs;   // [T]
+  double* trace;  // [T][ldt] loss trace
+  int64_t ldt;
+  int32_t* uidx;  // [T][2 kmax] backtracking work: column sources of S u S+
+  double* udel;   // [T][2 kmax] and beta+ - beta there
+  double* pw;     // [T][3][kmax + kMaxUnpenalized] polish vectors
+};
+
+hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st);
+hipError_t solve_residual(const SolveSet& Q, int32_t phase, int32_t initial, hipStream_t st);
+hipError_t solve_mu(const SolveSet& Q, hipStream_t st);
+hipError_t solve_bt_check(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st);
+hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
+hipError_t solve_commit(const SolveSet& Q, double tol, int32_t max_iter, hipStream_t st);
+// which = 0: columns of S into the current cache; 1: columns of S+ into the other one.
+hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, int32_t phase, hipStream_t st);
+hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStream_t st);
+hipError_t solve_output(const SolveSet& Q, int64_t* support, double* beta_S, double* beta_cov, int64_t ldk, int64_t ldc,
+                        hipStream_t st);
+// slots[0 .. *count) = the solves in `phase`, ascending.
+hipError_t solve_slots(const FitState* fs, int32_t T, int32_t phase, int32_t* slots, int32_t* count, hipStream_t st);
+
+}  // namespace iht

@@ -16,13 +16,13 @@ LIB_PATH = os.path.join(_HERE, "libiht.so")
 
 OK, NOT_CONVERGED, STALLED = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = -1, -2, -3, -4, -5
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED_I8 = 0, 1, 2
 HOST_PTR, DEVICE_PTR = 0, 1
 MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit",
-           "iht_status_str", "iht_last_error")
+           "iht_fit_batch", "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -33,7 +33,8 @@ class IHTError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
-                ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32)]
 
 
 _lib = None
@@ -61,8 +62,10 @@ def load():
     L.iht_gradient_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, P, P]
     L.iht_project.argtypes = [P, I64, I32, P, P, P]
     L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
+    L.iht_fit_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, I64, P, I32, I32, P, ctypes.POINTER(Opts),
+                                P, P, P, P, P, P, P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
-              "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit"):
+              "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit", "iht_fit_batch"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -136,13 +139,16 @@ class Geno:
             flags = HOST_PTR
             ptr = keep.ctypes.data_as(ctypes.c_void_p)
         _check(L.iht_geno_create(ptr, n, p, rb, flags, _stream(), ctypes.byref(self._h)))
+        self._pid = os.getpid()
         del keep
         self.n, self.p = int(n), int(p)
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
+        # only the creating process may free the device memory: a forked child (a worker pool
+        # started after the handle existed) holds a copy of the object but no usable device state
+        if getattr(self, "_h", None) and self._h.value and getattr(self, "_pid", None) == os.getpid():
             load().iht_geno_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -165,6 +171,7 @@ class Stats:
                 raise ValueError("subset must have n entries")
         _check(L.iht_stats_create(geno._h, None if m is None else m.ctypes.data_as(ctypes.c_void_p), _stream(),
                                   ctypes.byref(self._h)))
+        self._pid = os.getpid()
 
     def read(self):
         torch = _torch()
@@ -174,9 +181,9 @@ class Stats:
         return u, v
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
+        if getattr(self, "_h", None) and self._h.value and getattr(self, "_pid", None) == os.getpid():
             load().iht_stats_destroy(self._h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -247,3 +254,42 @@ def fit(geno: Geno, stats: Stats, y, k: int, Z=None, intercept: bool = True, **o
     _check(rc, allow_warnings=True)
     it = nit.value
     return dict(status=rc, support=sup, beta_S=bS, beta_cov=bc[:nc], loss_trace=trace[:it + 1], n_iter=it)
+
+
+def fit_batch(geno: Geno, stats, Y, ks, Z=None, intercept: bool = True, **opts):
+    """T lock-step IHT solves sharing the genotypes (iht_fit_batch).
+
+    stats: T Stats handles; Y: float64 CUDA [T, n] (row t = trait of solve t); ks: T model sizes;
+    Z: float32 CUDA [c, n] shared covariates or None. Returns dict(status (call), statuses [T], support
+    [T, kmax] (-1 past k_t), beta_S [T, kmax], beta_cov [T, nc], loss_trace [T, max_iter+1], n_iter [T]).
+    """
+    torch = _torch()
+    o = default_opts(**opts)
+    T = len(stats)
+    if len(ks) != T:
+        raise ValueError("ks must have one entry per solve")
+    yp = _dev(Y, torch.float64, (T, geno.n), "Y")
+    cz = 0
+    zp = None
+    if Z is not None:
+        cz = Z.shape[0]
+        zp = _dev(Z, torch.float32, (cz, geno.n), "Z")
+    nc = cz + (1 if intercept else 0)
+    kmax = int(max(ks))
+    dev = Y.device
+    sup = torch.empty((T, kmax), dtype=torch.int64, device=dev)
+    bS = torch.empty((T, kmax), dtype=torch.float64, device=dev)
+    bc = torch.empty((T, max(nc, 1)), dtype=torch.float64, device=dev)
+    trace = torch.full((T, o.max_iter + 1), float("nan"), dtype=torch.float64, device=dev)
+    ks_arr = np.ascontiguousarray(ks, dtype=np.int32)
+    nit = np.zeros(T, dtype=np.int32)
+    st = np.zeros(T, dtype=np.int32)
+    arr = (ctypes.c_void_p * T)(*[s._h.value for s in stats])
+    rc = load().iht_fit_batch(geno._h, arr, T, yp, geno.n, zp, cz, 1 if intercept else 0,
+                              ks_arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o),
+                              ctypes.c_void_p(sup.data_ptr()), ctypes.c_void_p(bS.data_ptr()),
+                              ctypes.c_void_p(bc.data_ptr()) if nc else None, ctypes.c_void_p(trace.data_ptr()),
+                              nit.ctypes.data_as(ctypes.c_void_p), st.ctypes.data_as(ctypes.c_void_p), _stream())
+    if rc < 0 and rc != ENONFINITE:
+        _check(rc)
+    return dict(status=rc, statuses=st, support=sup, beta_S=bS, beta_cov=bc[:, :nc], loss_trace=trace, n_iter=nit)

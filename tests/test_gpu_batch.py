@@ -1,0 +1,224 @@
+"""Batched solves (iht_fit_batch) through the C ABI against the FP64 oracle.
+
+Bars: FP64 batch: every solve as in the single-fit parity tests (same status, support, iteration
+count; beta within 1e-6 relative; loss trace within 1e-9 relative) and bitwise equal to the same
+solve run alone. Reduced precisions (FP32 pass, int8 matrix-core pass) with the FP64 polish: same
+status and support as the oracle, beta within 1e-6 relative; each solve bitwise the same alone and
+in any mix.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_1608_01398_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1608_01398_amd import iht  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def fold_masks(n, q, seed):
+    """q training masks (subjects outside fold f) of a seeded fold partition, plus the full set."""
+    rng = np.random.default_rng(seed)
+    fold = rng.permutation(np.arange(n) % q)
+    return [(fold != f).astype(np.uint8) for f in range(q)] + [np.ones(n, dtype=np.uint8)]
+
+
+def cv_solves(prob, ks, n_traits, seed):
+    """(mask index, trait row, k) of a CV grid over folds x ks on trait 0, plus extra traits at max k."""
+    n = prob["n"]
+    masks = fold_masks(n, 5, seed)
+    traits = [prob["y"]]
+    for e in range(n_traits):
+        y, *_ = synth.make_trait(prob["bed"], n, prob["q"], prob["k"], (0.2, 0.5), seed=100 + e)
+        traits.append(y)
+    solves = [(f, 0, k) for f in range(5) for k in ks]
+    solves += [(5, 1 + e, max(ks)) for e in range(n_traits)]
+    return masks, traits, solves
+
+
+def run_batch(g, masks, traits, solves, precision, Z=None, **opts):
+    stats_by_mask = {}
+    for f, _, _ in solves:
+        if f not in stats_by_mask:
+            stats_by_mask[f] = iht.Stats(g, masks[f])
+    stats = [stats_by_mask[f] for f, _, _ in solves]
+    Y = np.stack([traits[tr] for _, tr, _ in solves])
+    res = iht.fit_batch(g, stats, dev(Y), [k for _, _, k in solves],
+                        Z=None if Z is None else dev(Z, torch.float32), precision=precision, **opts)
+    out = {key: (val.cpu().numpy() if hasattr(val, "cpu") else val) for key, val in res.items()}
+    return out
+
+
+def check_solve(out, t, k, ref, exact_path):
+    st = int(out["statuses"][t])
+    assert st == ref["status"], (t, st, ref["status"])
+    sup = out["support"][t]
+    assert np.array_equal(sup[:k], ref["support"]), (t, sup[:k], ref["support"])
+    assert np.all(sup[k:] == -1)
+    scale = np.abs(ref["beta_S"]).max()
+    err = np.abs(out["beta_S"][t, :k] - ref["beta_S"]).max()
+    assert err <= 1e-6 * scale, (t, err / scale)
+    if len(ref["beta_cov"]):
+        np.testing.assert_allclose(out["beta_cov"][t], ref["beta_cov"], rtol=1e-6, atol=1e-6 * scale)
+    if exact_path:
+        it = int(out["n_iter"][t])
+        assert it == ref["n_iter"], (t, it, ref["n_iter"])
+        np.testing.assert_allclose(out["loss_trace"][t, :it + 1], ref["loss_trace"], rtol=1e-9)
+    return err / scale
+
+
+@pytest.fixture(scope="module")
+def c1_grid():
+    prob = synth.make_problem("c1", seed=7)
+    masks, traits, solves = cv_solves(prob, ks=[1, 4, 10], n_traits=2, seed=3)
+    say(f"c1 grid: {len(solves)} solves; oracle fits ...")
+    refs = [oracle.fit(prob["bed"], prob["n"], traits[tr], k, intercept=True, subset=masks[f]) for f, tr, k in solves]
+    g = iht.Geno(prob["bed"], prob["n"])
+    return prob, g, masks, traits, solves, refs
+
+
+def test_fit_batch_fp64_matches_oracle(c1_grid):
+    prob, g, masks, traits, solves, refs = c1_grid
+    out = run_batch(g, masks, traits, solves, iht.FP64)
+    assert out["status"] == max(int(s) for s in out["statuses"])
+    for t, (f, tr, k) in enumerate(solves):
+        check_solve(out, t, k, refs[t], exact_path=True)
+
+
+def test_fit_batch_fp64_solve_equals_single_fit(c1_grid):
+    prob, g, masks, traits, solves, refs = c1_grid
+    out = run_batch(g, masks, traits, solves, iht.FP64)
+    for t in (0, 7, len(solves) - 1):
+        f, tr, k = solves[t]
+        single = iht.fit(g, iht.Stats(g, masks[f]), dev(traits[tr]), k)
+        it = single["n_iter"]
+        assert it == out["n_iter"][t]
+        assert np.array_equal(single["support"].cpu().numpy(), out["support"][t, :k])
+        assert np.array_equal(single["beta_S"].cpu().numpy(), out["beta_S"][t, :k])
+        assert np.array_equal(single["loss_trace"].cpu().numpy(), out["loss_trace"][t, :it + 1])
+
+
+@pytest.mark.parametrize("precision", [iht.MIXED_I8, iht.FP32])
+def test_fit_batch_reduced_precision_matches_oracle(c1_grid, precision):
+    prob, g, masks, traits, solves, refs = c1_grid
+    out = run_batch(g, masks, traits, solves, precision)
+    worst = max(check_solve(out, t, k, refs[t], exact_path=False) for t, (_, _, k) in enumerate(solves))
+    say(f"  precision {precision}: worst beta rel err {worst:.2e}; iterations {list(out['n_iter'])}")
+
+
+def test_fit_batch_mixed_same_alone_and_in_mix(c1_grid):
+    prob, g, masks, traits, solves, refs = c1_grid
+    out = run_batch(g, masks, traits, solves, iht.MIXED_I8)
+    # a solve alone, and inside a different, reordered mix, gives bitwise the same result
+    for t in (2, 9):
+        alone = run_batch(g, masks, traits, [solves[t]], iht.MIXED_I8)
+        other = [solves[t]] + solves[::-3]
+        mix = run_batch(g, masks, traits, other, iht.MIXED_I8)
+        for res, row in ((alone, 0), (mix, 0)):
+            assert res["n_iter"][row] == out["n_iter"][t]
+            assert np.array_equal(res["support"][row], out["support"][t, :res["support"].shape[1]])
+            k = solves[t][2]
+            assert np.array_equal(res["beta_S"][row, :k], out["beta_S"][t, :k])
+
+
+def test_fit_fp32_single_converges_with_polish():
+    prob = synth.make_problem("c1", seed=2)
+    g = iht.Geno(prob["bed"], prob["n"])
+    res = iht.fit(g, iht.Stats(g), dev(prob["y"]), prob["k"], precision=iht.FP32)
+    ref = oracle.fit(prob["bed"], prob["n"], prob["y"], prob["k"], intercept=True)
+    assert res["status"] == iht.OK
+    assert np.array_equal(res["support"].cpu().numpy(), ref["support"])
+    scale = np.abs(ref["beta_S"]).max()
+    assert np.abs(res["beta_S"].cpu().numpy() - ref["beta_S"]).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("precision", [iht.FP64, iht.MIXED_I8])
+def test_fit_batch_covariates_subsets(precision):
+    prob = synth.make_problem("c5", seed=4, n=1200, p=6000)
+    n = prob["n"]
+    masks = fold_masks(n, 5, 8)
+    solves = [(0, 0, 12), (3, 0, 5), (5, 0, 12), (5, 0, 30)]
+    refs = [oracle.fit(prob["bed"], n, prob["y"], k, Z=prob["Z"], intercept=True, subset=masks[f])
+            for f, _, k in solves]
+    g = iht.Geno(prob["bed"], n)
+    out = run_batch(g, masks, [prob["y"]], solves, precision, Z=prob["Z"])
+    for t, (_, _, k) in enumerate(solves):
+        check_solve(out, t, k, refs[t], exact_path=precision == iht.FP64)
+
+
+@pytest.mark.parametrize("precision", [iht.FP64, iht.MIXED_I8])
+def test_fit_batch_statuses(precision):
+    """Mixed statuses in one call: a non-finite trait, max_iter reached, a stalled backtrack."""
+    rng = np.random.default_rng(5)
+    n, p = 600, 3000
+    bed, q = synth.make_genotypes(n, p, 5)
+    codes = synth.unpack_codes(bed, n)
+    for a in range(0, 40, 2):
+        flip = rng.random(n) < 0.03
+        codes[a + 1] = np.where(flip, codes[a + 7], codes[a])
+    bed = synth.pack_codes(codes)
+    y, *_ = synth.make_trait(bed, n, q, 10, (0.3, 0.8), 5)
+    ybad = y.copy()
+    ybad[17] = np.inf
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    Y = np.stack([y, ybad, y, y])
+    ks = [12, 12, 5, 12]
+    res = iht.fit_batch(g, [s] * 4, dev(Y), ks, precision=precision, max_backtrack=0)
+    st = list(res["statuses"])
+    assert st[1] == iht.ENONFINITE and res["status"] == iht.ENONFINITE
+    assert np.all(res["support"][1].cpu().numpy() == -1)
+    # the reduced-precision iteration stops at mixed_tol (1e-6): its reference is the oracle
+    # run to that tolerance (a late support change past it can stall the 1e-10 run only)
+    tol = 1e-10 if precision == iht.FP64 else 1e-6
+    for t in (0, 2, 3):
+        ref = oracle.fit(bed, n, Y[t], ks[t], intercept=True, max_backtrack=0, tol=tol)
+        say(f"  solve {t}: status {st[t]} iters {res['n_iter'][t]}; oracle {ref['status']} {ref['n_iter']}")
+        assert st[t] == ref["status"], (t, st[t], ref["status"])
+        assert np.array_equal(res["support"][t, :ks[t]].cpu().numpy(), ref["support"])
+    res1 = iht.fit_batch(g, [s, s], dev(np.stack([y, y])), [3, 7], precision=precision, max_iter=1)
+    assert list(res1["statuses"]) == [iht.NOT_CONVERGED, iht.NOT_CONVERGED]
+    assert list(res1["n_iter"]) == [1, 1]
+
+
+def test_fit_batch_rejects_bad_arguments():
+    prob = synth.make_problem("c1", seed=1, n=300, p=500)
+    g = iht.Geno(prob["bed"], prob["n"])
+    s = iht.Stats(g)
+    Y = dev(np.stack([prob["y"]] * 2))
+    for ks in ([0, 3], [3, 501], [3, iht.MAX_K + 1]):
+        with pytest.raises(iht.IHTError) as e:
+            iht.fit_batch(g, [s, s], Y, ks)
+        assert e.value.code == iht.EINVAL
+    with pytest.raises(iht.IHTError) as e:
+        iht.fit_batch(g, [s, s], Y, [3, 3], precision=7)
+    assert e.value.code == iht.EINVAL
+
+
+def test_fit_batch_c3_shape_sampled():
+    """The C3 layout (5 training folds x k = 1..20 on one trait, plus 8 traits at full n) on a
+    narrower matrix, mixed precision; a sample of the solves against the oracle."""
+    prob = synth.make_problem("c2", seed=1, n=5000, p=40_000)
+    masks, traits, solves = cv_solves(prob, ks=list(range(1, 21)), n_traits=8, seed=2)
+    assert len(solves) == 108
+    g = iht.Geno(prob["bed"], prob["n"])
+    out = run_batch(g, masks, traits, solves, iht.MIXED_I8)
+    assert out["status"] >= 0
+    for t in (0, 19, 57, 99, 100, 107):
+        f, tr, k = solves[t]
+        say(f"  oracle solve {t}: fold {f} trait {tr} k {k}")
+        ref = oracle.fit(prob["bed"], prob["n"], traits[tr], k, intercept=True, subset=masks[f])
+        check_solve(out, t, k, ref, exact_path=False)
