@@ -92,8 +92,9 @@ struct TopkArea {
       if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)words, st));
       rows = nrows;
     }
-    if (p > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
-      cap = std::max(cap, p);
+    const int64_t want = std::max<int64_t>(p, 16384);  // also holds the two-pass candidates
+    if (want > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
+      cap = std::max(cap, want);
       HIPCHK(cand.ensure((size_t)rows * (size_t)cap * (sizeof(uint64_t) + sizeof(int32_t))));
     }
     return IHT_OK;
@@ -355,6 +356,7 @@ int iht_project(const double* w, int64_t p, int32_t k, int64_t* support, double*
   J.g = w;
   J.ld = p;
   J.k0 = k;
+  J.kmax = k;
   J.out = support;
   J.ldo = k;
   J.vals = vals.as<double>();
@@ -500,6 +502,7 @@ int run_fit(const FitArgs& A) {
   J.ld = L.p;
   J.fs = Q.fs;
   J.ks = Q.ks;
+  J.kmax = kmax;
   J.ldo = kmax;
   J.small = W.topk.small.as<uint32_t>();
   J.cand_key = W.topk.cand_key();

@@ -58,27 +58,47 @@ __device__ double block_sum(double x, double* sh) {
 // ------------------------------------------------------------------------------------------------
 // Re-tile PLINK SNP-major rows into [tile][p_pad][8 B] with a per-SNP byte rotation.
 
+// Block (bx, by): SNPs [32 bx, 32 bx + 32) x tiles [32 by, 32 by + 32), i.e. PLINK bytes
+// [256 by, 256 by + 256) of 32 rows. The rows are staged in LDS with consecutive lanes reading
+// consecutive bytes of a row; the segments are written with consecutive lanes on consecutive SNPs
+// of one tile (256 contiguous bytes per tile). Pad SNPs (j >= p) and bits of subjects >= n are zero.
+constexpr int kRetileSnps = 32;
+constexpr int kRetileTiles = 32;
+constexpr int kRetileBytes = kRetileTiles * kSegBytes;  // 256 PLINK bytes per row and block
+
 __global__ __launch_bounds__(256) void k_retile(const uint8_t* __restrict__ raw, int64_t row, int64_t n, int64_t p,
                                                 int64_t p_pad, int64_t ntiles, uint8_t* __restrict__ tiled) {
-  const int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (seg >= ntiles * p_pad) return;
-  const int64_t t = seg / p_pad, j = seg - t * p_pad;
-  uint32_t w[2] = {0u, 0u};
-  if (j < p) {
-    const int rot = (int)(j & (kSegBytes - 1));
-#pragma unroll
-    for (int b = 0; b < kSegBytes; ++b) {
-      const int64_t src = t * kSegBytes + ((b + rot) & (kSegBytes - 1));  // byte of the PLINK row
-      uint32_t val = 0;
-      if (src < row && src * 4 < n) {
-        val = raw[j * row + src];
-        const int64_t keep = n - src * 4;  // subjects of this byte that exist
-        if (keep < 4) val &= (1u << (2 * keep)) - 1u;
-      }
-      w[b >> 2] |= val << (8 * (b & 3));
+  __shared__ uint8_t st[kRetileSnps][kRetileBytes];
+  const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kRetileSnps;
+  const int64_t c0 = (int64_t)blockIdx.y * kRetileBytes;  // first PLINK byte of the chunk
+  const int64_t nbytes = (n + 3) / 4;                       // PLINK bytes that hold subjects
+#pragma unroll 4
+  for (int q = tid; q < kRetileSnps * kRetileBytes; q += 256) {
+    const int r = q / kRetileBytes, o = q % kRetileBytes;
+    const int64_t j = j0 + r, src = c0 + o;
+    uint32_t val = 0;
+    if (j < p && src < nbytes) {
+      val = raw[j * row + src];
+      const int64_t keep = n - src * 4;  // subjects of this byte that exist
+      if (keep < 4) val &= (1u << (2 * keep)) - 1u;
     }
+    st[r][o] = (uint8_t)val;
   }
-  *reinterpret_cast<uint2*>(tiled + seg * kSegBytes) = make_uint2(w[0], w[1]);
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.y * kRetileTiles;
+#pragma unroll
+  for (int m = 0; m < (kRetileSnps * kRetileTiles) / 256; ++m) {
+    const int q = tid + 256 * m;
+    const int r = q % kRetileSnps, tl = q / kRetileSnps;
+    const int64_t t = t0 + tl, j = j0 + r;
+    if (t >= ntiles) continue;
+    const int rot = (int)(j & (kSegBytes - 1));
+    uint32_t w[2] = {0u, 0u};
+#pragma unroll
+    for (int b = 0; b < kSegBytes; ++b) w[b >> 2] |= (uint32_t)st[r][tl * kSegBytes + ((b + rot) & (kSegBytes - 1))] << (8 * (b & 3));
+    *reinterpret_cast<uint2*>(tiled + (t * p_pad + j) * kSegBytes) = make_uint2(w[0], w[1]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -183,6 +203,11 @@ __device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int vb
   }
 }
 
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) v2d_t lds_double2;
+typedef __attribute__((address_space(3))) v2f_t lds_float2;
+
 // Lookups and rotation-invariant tile sum of one SNP's 8-byte segment (buffer BUF).
 // The pairings {b, b+4}, {b, b+2}, {0, 1} of byte positions map to the same pairings of subject
 // groups for every rotation, and + is commutative, so the tile sum depends only on the column's
@@ -201,13 +226,14 @@ __device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)
       const uint32_t dw = h ? d.y : d.x;
       // byte0 = slot offset of step b, byte1 = packed value, bytes 2-3 = 0
       const uint32_t sel = (4u + (uint32_t)c) | ((uint32_t)c << 8) | (0x0Cu << 16) | (0x0Cu << 24);
+      // the table starts at LDS address 0, so the perm result is the LDS address itself
       const uint32_t addr = __builtin_amdgcn_perm(offs[h], dw, sel);
       if constexpr (F32) {
-        const float2 e = *reinterpret_cast<const float2*>(lds + addr);
+        const v2f_t e = *reinterpret_cast<const lds_float2*>((size_t)addr);
         vt[h] = e.x;
         vm[h] = e.y;
       } else {
-        const double2 e = *reinterpret_cast<const double2*>(lds + addr);
+        const v2d_t e = *reinterpret_cast<const lds_double2*>((size_t)addr);
         vt[h] = e.x;
         vm[h] = e.y;
       }
@@ -646,6 +672,203 @@ __global__ __launch_bounds__(1024) void k_topk_collect(TopkJob J, int64_t p, int
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Two-pass top-k for k <= kLocalMaxK (no global atomics, no fences). Pass 1: each block takes a
+// chunk of the row, keeps its values in registers and marks its own k first entries in the total
+// order (|w| descending, index ascending) by radix select on the unique 96-bit composite
+// (|w| bits, ~index); it writes them to its kmax candidate slots (unused slots index -1). The row's
+// k first entries are among the union of the blocks' k first. Pass 2: one block per row selects
+// the k first of all candidates the same way and sorts them by index.
+
+constexpr int kSelBits = 11;
+constexpr int kSelBins = 1 << kSelBits;  // 2048: two bins per thread of a 1024-thread block
+constexpr int kLocalMaxK = 512;
+constexpr int kLocalEPT = 8;   // entries per thread in pass 1: chunks of 8192
+constexpr int kFinalEPT = 8;   // candidates per thread in pass 2: up to 8192 per row
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ u128 sel_comp(uint64_t key, int32_t idx) {
+  return ((u128)key << 32) | (u128)(0xFFFFFFFFu - (uint32_t)idx);
+}
+
+// Sum of v over the threads >= tid (1024-thread block; sh holds 16 words).
+__device__ __forceinline__ uint32_t block_suffix_sum(uint32_t v, uint32_t* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_down(x, off, 64);
+    if (lane + off < 64) x += y;
+  }
+  if (lane == 0) sh[w] = x;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w2 = w + 1; w2 < 16; ++w2) add += sh[w2];
+  __syncthreads();
+  return x + add;
+}
+
+// Bit e of the result: entry e of this thread is among the k first valid entries of the block in
+// the total order; idx_of(e) gives the entry's index (-1: no entry). Radix select on the composite,
+// 11 bits at a time from the top (while the digit lies in the key, 64-bit arithmetic only),
+// stopping as soon as the bucket holding the k-th entry is taken whole. Needs 1 <= k <= number of
+// valid entries, E <= 32.
+template <int E, class IdxOf>
+__device__ uint32_t block_select(const uint64_t (&key)[E], IdxOf idx_of, uint32_t k, uint32_t* hist, uint32_t* sh) {
+  static_assert(E <= 32, "selection mask");
+  const int tid = threadIdx.x;
+  u128 prefix = 0;
+  uint32_t need = k;
+  int s = 96;  // composite bits [s, 96) are fixed by prefix
+  while (s > 0) {
+    const int ns = s > kSelBits ? s - kSelBits : 0;
+    const int nbits = s - ns;
+    const uint32_t dmask = (1u << nbits) - 1u;
+    hist[2 * tid] = 0u;
+    hist[2 * tid + 1] = 0u;
+    __syncthreads();
+    if (ns >= 32) {  // digit and prefix inside the key
+      const uint64_t pk = (uint64_t)prefix;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (idx_of(e) >= 0 && (s - 32 >= 64 ? 0ull : (key[e] >> (s - 32))) == pk)
+          atomicAdd(&hist[(uint32_t)(key[e] >> (ns - 32)) & dmask], 1u);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int32_t ix = idx_of(e);
+        if (ix >= 0) {
+          const u128 c = sel_comp(key[e], ix);
+          if ((c >> s) == prefix) atomicAdd(&hist[(uint32_t)(c >> ns) & dmask], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t h0 = hist[2 * tid], h1 = hist[2 * tid + 1];
+    const uint32_t incl = block_suffix_sum(h0 + h1, sh);  // entries in bins >= 2 tid
+    const uint32_t excl = incl - h0 - h1;                   // entries in bins >= 2 tid + 2
+    if (excl < need && incl >= need) {
+      if (excl + h1 >= need) {
+        sh[16] = 2u * tid + 1u;
+        sh[17] = excl;
+        sh[18] = h1;
+      } else {
+        sh[16] = 2u * tid;
+        sh[17] = excl + h1;
+        sh[18] = h0;
+      }
+    }
+    __syncthreads();
+    const uint32_t b = sh[16], above = sh[17], cnt = sh[18];
+    prefix = (prefix << nbits) | (u128)b;
+    need -= above;
+    s = ns;
+    __syncthreads();  // everyone has read sh[16..18]
+    if (cnt == need) break;
+  }
+  uint32_t take = 0u;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t ix = idx_of(e);
+    if (ix >= 0 && (sel_comp(key[e], ix) >> s) >= prefix) take |= 1u << e;
+  }
+  return take;
+}
+
+template <int EPT>
+__global__ __launch_bounds__(1024) void k_topk_local(TopkJob J, int64_t p) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.y, src)) return;
+  __shared__ uint32_t hist[kSelBins];
+  __shared__ uint32_t sh[32];
+  __shared__ uint32_t nout;
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * (1024 * EPT);
+  auto idx_of = [&](int e) -> int32_t {
+    const int64_t j = base + (int64_t)e * 1024 + tid;
+    return j < p ? (int32_t)j : -1;
+  };
+  uint64_t key[EPT];
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int32_t j = idx_of(e);
+    const double w = j >= 0 ? src.at(j) : 0.0;
+    bad |= !isfinite(w);
+    key[e] = abs_key(w);
+  }
+  if (bad) atomicOr(&src.tw.state[3], 1u);
+  const int64_t nvalid = min((int64_t)(1024 * EPT), p - base);
+  uint32_t take = 0u;
+  if (nvalid <= (int64_t)src.k) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (idx_of(e) >= 0) take |= 1u << e;
+  } else {
+    take = block_select<EPT>(key, idx_of, (uint32_t)src.k, hist, sh);
+  }
+  if (tid == 0) nout = 0u;
+  __syncthreads();
+  uint64_t* ok = src.tw.cand_key + (int64_t)blockIdx.x * J.kmax;
+  int32_t* oi = src.tw.cand_idx + (int64_t)blockIdx.x * J.kmax;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    if (take & (1u << e)) {
+      const uint32_t pos = atomicAdd(&nout, 1u);  // < min(k, nvalid) <= kmax
+      ok[pos] = key[e];
+      oi[pos] = idx_of(e);
+    }
+  }
+  __syncthreads();
+  for (int q = (int)nout + tid; q < J.kmax; q += 1024) oi[q] = -1;
+}
+
+__global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32_t nb) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.x, src)) return;
+  __shared__ uint32_t hist[kSelBins];
+  __shared__ uint32_t sh[32];
+  __shared__ int32_t sel[kLocalMaxK];
+  __shared__ uint32_t nsel;
+  const int tid = threadIdx.x;
+  const int64_t total = (int64_t)nb * J.kmax;  // <= 1024 * kFinalEPT (checked at launch)
+  uint64_t key[kFinalEPT];
+  int32_t idx[kFinalEPT];
+#pragma unroll
+  for (int e = 0; e < kFinalEPT; ++e) {
+    const int64_t q = tid + (int64_t)e * 1024;
+    idx[e] = q < total ? src.tw.cand_idx[q] : -1;
+    key[e] = idx[e] >= 0 ? src.tw.cand_key[q] : 0;
+  }
+  const int k = src.k;
+  const uint32_t take = block_select<kFinalEPT>(key, [&](int e) { return idx[e]; }, (uint32_t)k, hist, sh);
+  if (tid == 0) nsel = 0u;
+  for (int q = tid; q < kLocalMaxK; q += 1024) sel[q] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kFinalEPT; ++e) {
+    if (take & (1u << e)) {
+      const uint32_t pos = atomicAdd(&nsel, 1u);
+      if (pos < (uint32_t)kLocalMaxK) sel[pos] = idx[e];
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && nsel != (uint32_t)k) atomicOr(&src.tw.state[3], 2u);
+  // the k selected indices, ascending (indices are distinct)
+  for (int q = tid; q < k; q += 1024) {
+    const int32_t x = sel[q];
+    int rank = 0;
+    for (int q2 = 0; q2 < k; ++q2) rank += (sel[q2] < x) ? 1 : 0;
+    const bool ok = x >= 0 && x < p && rank < k;  // always true when the counts agree
+    if (!ok) atomicOr(&src.tw.state[3], 2u);
+    if (rank < k) {
+      src.out[rank] = ok ? x : 0;
+      if (src.vals) src.vals[rank] = ok ? src.at(x) : 0.0;
+    }
+  }
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ x, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0u;
@@ -707,9 +930,8 @@ size_t pass_lds_bytes(const PassGeom& G) { return 65536 + 40 * sizeof(double) + 
 // Launchers
 
 hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L, uint8_t* tiled, hipStream_t st) {
-  const int64_t segs = L.ntiles * L.p_pad;
-  const int64_t blocks = (segs + 255) / 256;
-  hipLaunchKernelGGL(k_retile, dim3((unsigned)blocks), dim3(256), 0, st, raw, row_bytes, L.n, L.p, L.p_pad, L.ntiles, tiled);
+  const dim3 grid((unsigned)(L.p_pad / kRetileSnps), (unsigned)((L.ntiles + kRetileTiles - 1) / kRetileTiles));
+  hipLaunchKernelGGL(k_retile, grid, dim3(256), 0, st, raw, row_bytes, L.n, L.p, L.p_pad, L.ntiles, tiled);
   return hipGetLastError();
 }
 
@@ -781,7 +1003,18 @@ hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* 
 }
 
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st) {
-  // chunk per block: about 2048 blocks over all rows, between 4096 and 65536 entries
+  // two-pass selection when every row's candidates fit pass 2
+  const int64_t chunk2 = 1024 * (int64_t)kLocalEPT;
+  const int64_t nb = (p + chunk2 - 1) / chunk2;
+  if (J.kmax <= kLocalMaxK && nb * J.kmax <= 1024 * (int64_t)kFinalEPT && nb * J.kmax <= J.cap) {
+    hipLaunchKernelGGL(k_topk_local<kLocalEPT>, dim3((unsigned)nb, (unsigned)rows), dim3(1024), 0, st, J, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb);
+    return hipGetLastError();
+  }
+  // histogram path (large k or very long rows): about 2048 blocks over all rows, 4096 to 65536
+  // entries per block
   int64_t chunk = 4096;
   while (chunk < 65536 && (p + chunk - 1) / chunk * rows > 2048) chunk <<= 1;
   const dim3 grid((unsigned)((p + chunk - 1) / chunk), (unsigned)rows);

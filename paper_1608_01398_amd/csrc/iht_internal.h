@@ -89,13 +89,14 @@ struct TopkJob {
   int32_t phase;
   int32_t k0;
   const int32_t* ks;
+  int32_t kmax;  // >= every row's k
   int64_t* out;  // support rows (ascending), stride ldo
   int64_t ldo;
   double* vals;  // w at the support, stride ldo (may be NULL)
   uint32_t* small;  // row t at small + t * kTopkRowWords
   uint64_t* cand_key;
   int32_t* cand_idx;
-  int64_t cap;  // candidate slots per row (>= p)
+  int64_t cap;  // candidate slots per row (>= p, >= 16384)
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
