@@ -296,8 +296,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
   iht_geno* G = const_cast<iht_geno*>(g);
   const Layout& L = g->L;
   HIPCHK(G->state.ensure(sizeof(FitState)));
-  const size_t pb = gradient_partial_bytes(L);
-  if (pb) HIPCHK(G->partial.ensure(pb));
+  HIPCHK(G->partial.ensure(gradient_work_bytes(L)));
   FitState* fs = G->state.as<FitState>();
   HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask.as<double>(), s->nT, s->u.as<double>(), s->v.as<double>(), fs,
                          precision, grad, G->partial.as<double>(), nullptr, st));
@@ -432,8 +431,7 @@ int run_fit(const FitArgs& A) {
 
   HIPCHK(W.beta.ensure(Tz * L.p * 8));
   HIPCHK(W.g.ensure(Tz * L.p * 8));
-  const size_t pb = gradient_partial_bytes(L);
-  if (pb) HIPCHK(W.partial.ensure(pb));
+  HIPCHK(W.partial.ensure(gradient_work_bytes(L)));
   HIPCHK(W.r.ensure(Tz * L.n_pad * 8));
   HIPCHK(W.S.ensure(Tz * kz * 8));
   HIPCHK(W.Sp.ensure(Tz * kz * 8));

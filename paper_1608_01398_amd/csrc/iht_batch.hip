@@ -56,6 +56,11 @@ __device__ double bmax(double x, double* sh) {
   return sh[32];
 }
 
+// Position along the matrix-core K dimension of subject s (0..31) of a tile: inside each 16-subject
+// half, subject 4e + q sits at 4q + e (the genotype operand below is built code plane by code
+// plane; both operands use the same order, so the products are unchanged).
+__device__ __forceinline__ int kpos(int s) { return (s & 16) | ((s & 3) << 2) | ((s >> 2) & 3); }
+
 // One block per slot: centre the slot's residual over its subject set, choose the scale, write the
 // digits and the exact digit sums. Slots at or past the live count are skipped: a matrix-core
 // column only ever meets its own digits, so their contents never reach a live slot.
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
     }
 #pragma unroll
     for (int d = 0; d < kDigits; ++d) {
-      R8[(((i >> 5) * kDigits + d) * T_pad + slot) * 32 + (i & 31)] = (int8_t)q[d];
+      R8[(((i >> 5) * kDigits + d) * T_pad + slot) * 32 + kpos((int)(i & 31))] = (int8_t)q[d];
       sq[d] += (double)q[d];  // integer-valued, exact
     }
   }
@@ -116,18 +121,11 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
   }
 }
 
-// byte of 4 two-bit codes -> (4 dosage bytes, 4 missing-flag bytes)
-__device__ __forceinline__ uint2 code_lut_entry(uint32_t b) {
-  uint32_t d = 0, m = 0;
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const uint32_t c = (b >> (2 * e)) & 3u;
-    const uint32_t dose = c == 3u ? 2u : (c == 2u ? 1u : 0u);
-    d |= dose << (8 * e);
-    m |= (c == 1u ? 1u : 0u) << (8 * e);
-  }
-  return make_uint2(d, m);
-}
+// Two-bit code -> dosage / missing flag, as byte tables for v_perm (selector bytes 0-3 pick bytes
+// 0-3 of the table): code 0 -> (0, 0), 1 (missing) -> (0, 1), 2 -> (1, 0), 3 -> (2, 0).
+constexpr uint32_t kDoseBytes = 0x02010000u;
+constexpr uint32_t kMissBytes = 0x00000100u;
+constexpr int kRbStride = 48;  // bytes per slot row of a staged digit plane (32 + 16: conflict-free)
 
 constexpr int kBlockSnps = 256;  // 4 waves x 64 SNPs
 constexpr int kBlockSolves = 32;
@@ -142,13 +140,11 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
                                                   const double* __restrict__ rsum, double* __restrict__ G, int64_t ldg) {
   const int live = count ? *count : T;
   if ((int)blockIdx.y * kBlockSolves >= live) return;  // no live slot in this block (uniform)
-  __shared__ uint2 lut[256];
-  __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * 32];  // 2 x 3 KB
+  __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * kRbStride];  // 2 x 4.5 KB
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int kh = lane >> 5;  // k-half: subjects 16 kh .. 16 kh + 15 of the tile
   const int col = lane & 31;
-  lut[tid] = code_lut_entry((uint32_t)tid);
 
   const int64_t j0 = (int64_t)blockIdx.x * kBlockSnps + 64 * w;
   const int64_t jA = j0 + col, jB = j0 + 32 + col;  // this lane's SNP in group 0 / group 1
@@ -160,12 +156,13 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
 #pragma unroll
   for (int e = 0; e < 4; ++e) sel |= ((4u * kh + e - rot) & 7u) << (8 * e);
 
-  // R digit chunk of this block for tile t: 3 x 1 KB at [(t*3 + d)*T_pad + tb][32]
+  // R digit chunk of this block for tile t: 3 x 1 KB at [(t*3 + d)*T_pad + tb][32], staged with a
+  // 48-byte row per slot
   auto stage_r = [&](int t, int buf) {
     if (tid < 192) {
       const int d = tid >> 6, part = tid & 63;
       const int4 x = *reinterpret_cast<const int4*>(R8 + (((int64_t)t * kDigits + d) * T_pad + tb) * 32 + part * 16);
-      *reinterpret_cast<int4*>(&rb[buf][d * 1024 + part * 16]) = x;
+      *reinterpret_cast<int4*>(&rb[buf][d * (kBlockSolves * kRbStride) + (part >> 1) * kRbStride + (part & 1) * 16]) = x;
     }
   };
   auto load_seg = [&](int t, int64_t j) -> uint2 {
@@ -192,22 +189,23 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
       nB = load_seg(t + 1, jB);
       stage_r(t + 1, buf ^ 1);
     }
-    // A operands: 4 packed bytes (16 subjects) of each SNP -> dosage and flag dwords
+    // A operands: 4 packed bytes (16 subjects) of each SNP; code plane q (the q-th code of every
+    // byte) gives the dosage and flag bytes of dword q
     v4i op[2][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint2 sg = h ? segB : segA;
       const uint32_t g4 = __builtin_amdgcn_perm(sg.y, sg.x, sel);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint2 L = lut[(g4 >> (8 * e)) & 0xFFu];
-        op[h][0][e] = (int32_t)L.x;
-        op[h][1][e] = (int32_t)L.y;
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t codes = (g4 >> (2 * q)) & 0x03030303u;
+        op[h][0][q] = (int32_t)__builtin_amdgcn_perm(0u, kDoseBytes, codes);
+        op[h][1][q] = (int32_t)__builtin_amdgcn_perm(0u, kMissBytes, codes);
       }
     }
 #pragma unroll
     for (int d = 0; d < kDigits; ++d) {
-      const v4i bop = *reinterpret_cast<const v4i*>(&rb[buf][d * 1024 + col * 32 + kh * 16]);
+      const v4i bop = *reinterpret_cast<const v4i*>(&rb[buf][d * (kBlockSolves * kRbStride) + col * kRbStride + kh * 16]);
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll

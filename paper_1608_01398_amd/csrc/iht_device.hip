@@ -153,101 +153,184 @@ __global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, 
 
 // ------------------------------------------------------------------------------------------------
 // The gradient pass.
-
-// LDS table: one 256-byte row per packed byte value v (0..255), 64 KB in all. FP64 rows hold
-// [buffer 0: 8 groups x (T, M) 16 B][buffer 1: same]; FP32 rows hold [buffer 0 copy 0: 8 x 8 B]
-// [buffer 0 copy 1][buffer 1 copy 0][buffer 1 copy 1]. The buffer is an immediate offset (+128).
-// At every lookup step the 8 (FP64, 16-byte reads) or 16 (FP32, two copies) lanes served together
-// read 8 different groups, which tile all 32 banks: no conflicts for any data.
-template <bool F32>
-struct Tab;
-template <>
-struct Tab<false> {
-  static constexpr uint32_t kGroupShift = 4;
-  __device__ static uint32_t slot_base(int lane) { return 0u; }
-};
-template <>
-struct Tab<true> {
-  static constexpr uint32_t kGroupShift = 3;
-  __device__ static uint32_t slot_base(int lane) { return (uint32_t)((lane >> 3) & 1) * 64u; }
-};
-
-__device__ __forceinline__ double dose_of(int c) { return c == 3 ? 2.0 : (c == 2 ? 1.0 : 0.0); }
-__device__ __forceinline__ double miss_of(int c) { return c == 1 ? 1.0 : 0.0; }
-
-// Builder thread: group gb = tid % 8 and byte values v = tid / 8 + (threads / 8) m. Entries are
-// T(v) = sum_k dose(c_k(v)) r_k and M(v) = sum_k [c_k(v) missing] r_k over the group's 4 subjects,
-// summed in subject order. 512 threads: 4 values per thread (the 4th subject's code varies);
-// 1024 threads: 2 values (the high bit of the 4th subject's code varies).
-template <bool F32, int THREADS>
-__device__ __forceinline__ void build_entries(char* lds, int buf, int gb, int vb, const double (&r)[4]) {
-  static_assert(THREADS == 512 || THREADS == 1024, "builder mapping");
-  constexpr int EPT = 2048 / THREADS;
-  const int c0 = vb & 3, c1 = (vb >> 2) & 3, c2 = (vb >> 4) & 3;
-  const double T6 = (dose_of(c0) * r[0] + dose_of(c1) * r[1]) + dose_of(c2) * r[2];
-  const double M6 = (miss_of(c0) * r[0] + miss_of(c1) * r[1]) + miss_of(c2) * r[2];
-#pragma unroll
-  for (int m = 0; m < EPT; ++m) {
-    const int v = vb + (THREADS / 8) * m;
-    const int c3 = v >> 6;
-    const double T = (c3 == 0 || c3 == 1) ? T6 : T6 + dose_of(c3) * r[3];
-    const double M = (c3 == 1) ? M6 + r[3] : M6;
-    char* row = lds + (v << 8) + buf * 128;
-    if constexpr (F32) {
-      const float2 e = make_float2((float)T, (float)M);
-      *reinterpret_cast<float2*>(row + (gb << 3)) = e;
-      *reinterpret_cast<float2*>(row + 64 + (gb << 3)) = e;
-    } else {
-      *reinterpret_cast<double2*>(row + (gb << 4)) = make_double2(T, M);
-    }
-  }
-}
+//
+// The block walks its subject range two tiles (64 subjects) at a time. For each pair it builds in
+// LDS, for every 4-subject group g (8 per tile) and every packed byte value v, the sums
+// T = sum dose * r and M = sum [missing] * r over the group's subjects (the "Four Russians" table);
+// each packed byte then costs one table read instead of 4 decodes and multiply-adds. Table of one
+// pair: 256 rows of 256 B, row v = [tile A: 8 groups][tile B: 8 groups] x 16 B (FP64 (T, M)); FP32
+// rows hold two copies of [A: 8 x 8 B][B: 8 x 8 B]. Two buffers: pair q builds into buffer q % 2;
+// buffer 0 is LDS [0, 64 KB), buffer 1 is [64 KB, 128 KB). The lookup address is one v_perm of a
+// per-lane offset register and the packed data: byte 0 = slot offset, byte 1 = packed byte value,
+// byte 2 = buffer (buffer 1's offset registers carry a 0x01 byte for it), byte 3 = 0.
+//
+// Conflict-free reads: the LDS serves 16 lanes per cycle for 16-byte reads (32 for 8-byte reads).
+// Lane L reads, at step b of a pair, the byte at position b % 8 of its SNP's segment of tile
+// (b / 8) ^ ((L / 8) % 2); by the per-SNP rotation of the layout that byte is group (b + L) % 8 of
+// that tile. So among 16 lanes served together, lanes 0-7 and 8-15 read different tiles (different
+// halves of the row) and different groups within them: 16 distinct bank quads for any data.
+constexpr uint32_t kPassBuf1 = 65536;  // LDS offset of table buffer 1
+constexpr size_t kPassLdsBytes = 2 * 65536;
 
 typedef double v2d_t __attribute__((ext_vector_type(2)));
 typedef float v2f_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) v2d_t lds_double2;
 typedef __attribute__((address_space(3))) v2f_t lds_float2;
 
-// Lookups and rotation-invariant tile sum of one SNP's 8-byte segment (buffer BUF).
-// The pairings {b, b+4}, {b, b+2}, {0, 1} of byte positions map to the same pairings of subject
-// groups for every rotation, and + is commutative, so the tile sum depends only on the column's
-// bytes: identical columns give bitwise identical gradients.
 template <bool F32>
-__device__ __forceinline__ void tile_sum(const char* lds, const uint32_t (&offs)[2], const uint2 d, double& accT,
-                                         double& accM) {
-  using acc_t = typename std::conditional<F32, float, double>::type;
-  acc_t PT[4], PM[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    acc_t vt[2], vm[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int b = c + 4 * h;
-      const uint32_t dw = h ? d.y : d.x;
-      // byte0 = slot offset of step b, byte1 = packed value, bytes 2-3 = 0
-      const uint32_t sel = (4u + (uint32_t)c) | ((uint32_t)c << 8) | (0x0Cu << 16) | (0x0Cu << 24);
-      // the table starts at LDS address 0, so the perm result is the LDS address itself
-      const uint32_t addr = __builtin_amdgcn_perm(offs[h], dw, sel);
-      if constexpr (F32) {
-        const v2f_t e = *reinterpret_cast<const lds_float2*>((size_t)addr);
-        vt[h] = e.x;
-        vm[h] = e.y;
-      } else {
-        const v2d_t e = *reinterpret_cast<const lds_double2*>((size_t)addr);
-        vt[h] = e.x;
-        vm[h] = e.y;
-      }
-      (void)b;
-    }
-    PT[c] = vt[0] + vt[1];
-    PM[c] = vm[0] + vm[1];
+struct PassTab;
+template <>
+struct PassTab<false> {
+  // slot offset inside a row: tile half * 128 + group * 16
+  __device__ static uint32_t slot(int lane, int tile, int grp) { return (uint32_t)(tile * 128 + grp * 16); }
+};
+template <>
+struct PassTab<true> {
+  // copy (lanes 16-31 of every 32) * 128 + tile half * 64 + group * 8
+  __device__ static uint32_t slot(int lane, int tile, int grp) {
+    return (uint32_t)(((lane >> 4) & 1) * 128 + tile * 64 + grp * 8);
   }
-  accT += (double)((PT[0] + PT[2]) + (PT[1] + PT[3]));
-  accM += (double)((PM[0] + PM[2]) + (PM[1] + PM[3]));
+};
+
+__device__ __forceinline__ double dose_of(int c) { return c == 3 ? 2.0 : (c == 2 ? 1.0 : 0.0); }
+__device__ __forceinline__ double miss_of(int c) { return c == 1 ? 1.0 : 0.0; }
+
+// Builder thread (1024 or 512 per block): group G = tid % 16 of the pair (tile G / 8, group G % 8)
+// and byte values v = tid / 16 + STEP m, STEP = threads / 16 (m < 4096 / threads). Codes c0, c1 and
+// the low bit of c2 come from tid / 16, the rest from m. Entries sum the group's 4 subjects in order:
+// T = ((d0 r0 + d1 r1) + d2 r2) + d3 r3; the part fixed by the thread and the two values of the
+// c2 term are formed once, so each entry costs one add for T and one for M, stored immediately.
+template <bool F32, int THREADS>
+__device__ __forceinline__ void build_pair(uint32_t buf, int G, int vb, const double (&r)[4]) {
+  static_assert(THREADS == 512 || THREADS == 1024, "builder mapping");
+  constexpr int EPT = 4096 / THREADS;
+  constexpr int STEP = THREADS / 16;
+  const int c0 = vb & 3, c1 = (vb >> 2) & 3;
+  const double T2 = dose_of(c0) * r[0] + dose_of(c1) * r[1];
+  const double M2 = miss_of(c0) * r[0] + miss_of(c1) * r[1];
+  // the two c2 values reachable from this thread (bit 4 of v is vb bit 4; bit 5 varies with m when
+  // STEP = 32, and comes from vb when STEP = 64)
+  double T3[2], M3[2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const int c2 = ((vb >> 4) & (STEP == 64 ? 3 : 1)) | (STEP == 64 ? 0 : hb << 1);
+    T3[hb] = T2 + dose_of(c2) * r[2];
+    M3[hb] = M2 + miss_of(c2) * r[2];
+  }
+  const uint32_t tile = (uint32_t)(G >> 3), grp = (uint32_t)(G & 7);
+#pragma unroll
+  for (int m = 0; m < EPT; ++m) {
+    const int v = vb + STEP * m;
+    const int hb = STEP == 64 ? 0 : (m & 1);
+    const int c3 = v >> 6;  // fixed per m: v = vb + STEP m with vb < STEP
+    const double T = c3 >= 2 ? T3[hb] + dose_of(c3) * r[3] : T3[hb];
+    const double M = c3 == 1 ? M3[hb] + r[3] : M3[hb];
+    const uint32_t row = buf + ((uint32_t)v << 8);
+    if constexpr (F32) {
+      const v2f_t e = {(float)T, (float)M};
+      const uint32_t off = row + tile * 64 + grp * 8;
+      *reinterpret_cast<lds_float2*>((size_t)off) = e;
+      *reinterpret_cast<lds_float2*>((size_t)(off + 128)) = e;
+    } else {
+      const v2d_t e = {T, M};
+      *reinterpret_cast<lds_double2*>((size_t)(row + tile * 128 + grp * 16)) = e;
+    }
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+  }
 }
 
-constexpr int kRing = 4;               // tiles of packed data held in registers (prefetch distance 3)
-constexpr int kMaxTilesPerBlock = 376;  // residual staged in LDS: 376 * 32 * 8 B next to the 64 KB table
+// A lookup unit: the 8 lookups of one tile of one SNP (steps 8 half .. 8 half + 7 of the pair).
+template <bool F32>
+struct Unit {
+  using acc_t = typename std::conditional<F32, float, double>::type;
+  acc_t t[8], m[8];
+};
+
+template <bool F32, int BUF>
+__device__ __forceinline__ void unit_lookup(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], uint2 d, int half,
+                                            Unit<F32>& U) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int b = half * 8 + c + 4 * h;  // step; byte c of dword h of the segment
+      const uint32_t dw = h ? d.y : d.x;
+      // buffer 0: offs0[b / 4] byte b % 4 holds the slot offset; bytes 2-3 of the address are 0.
+      // buffer 1: offs1[b / 3] byte b % 3 holds it and its byte 3 is 0x01 -> address byte 2.
+      uint32_t addr;
+      if constexpr (BUF == 0) {
+        const uint32_t sel = (uint32_t)(4 + (b & 3)) | ((uint32_t)c << 8) | (0x0Cu << 16) | (0x0Cu << 24);
+        addr = __builtin_amdgcn_perm(offs0[b >> 2], dw, sel);
+      } else {
+        const uint32_t sel = (uint32_t)(4 + (b % 3)) | ((uint32_t)c << 8) | (7u << 16) | (0x0Cu << 24);
+        addr = __builtin_amdgcn_perm(offs1[b / 3], dw, sel);
+      }
+      if constexpr (F32) {
+        const v2f_t e = *reinterpret_cast<const lds_float2*>((size_t)addr);
+        U.t[c + 4 * h] = e.x;
+        U.m[c + 4 * h] = e.y;
+      } else {
+        const v2d_t e = *reinterpret_cast<const lds_double2*>((size_t)addr);
+        U.t[c + 4 * h] = e.x;
+        U.m[c + 4 * h] = e.y;
+      }
+    }
+  }
+}
+
+// Rotation-invariant tree over byte positions: pairs {b, b+4}, then {0, 2} + {1, 3}. The same
+// pairings of byte positions are the same pairings of groups for every rotation, so the tile sum
+// depends only on the column's bytes.
+template <bool F32>
+__device__ __forceinline__ void unit_reduce(const Unit<F32>& U, typename Unit<F32>::acc_t& PT, typename Unit<F32>::acc_t& PM) {
+  typename Unit<F32>::acc_t QT[4], QM[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    QT[c] = U.t[c] + U.t[c + 4];
+    QM[c] = U.m[c] + U.m[c + 4];
+  }
+  PT = (QT[0] + QT[2]) + (QT[1] + QT[3]);
+  PM = (QM[0] + QM[2]) + (QM[1] + QM[3]);
+}
+
+// All lookups of one pair for the lane's NS SNPs, software-pipelined over the 2 NS units (tile
+// halves): the lookups of unit u+1 are issued before unit u is summed, so the LDS latency of one
+// unit overlaps the adds of the previous one; at most two units of results are live. The two tile
+// sums of a SNP are combined as acc += (A + B), which is commutative: identical columns give
+// bitwise identical gradients whichever tile a lane reads first.
+template <bool F32, int BUF, int NS>
+__device__ __forceinline__ void pair_step(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], const uint2 (&first)[NS],
+                                          const uint2 (&second)[NS], double (&accT)[NS], double (&accM)[NS]) {
+  using acc_t = typename Unit<F32>::acc_t;
+  constexpr int NU = 2 * NS;
+  Unit<F32> U[2];
+  acc_t PT0 = 0, PM0 = 0;  // first tile's sums of the current SNP
+  unit_lookup<F32, BUF>(offs0, offs1, first[0], 0, U[0]);
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    if (u + 1 < NU) {
+      const int s1 = (u + 1) >> 1, h1 = (u + 1) & 1;
+      unit_lookup<F32, BUF>(offs0, offs1, h1 ? second[s1] : first[s1], h1, U[(u + 1) & 1]);
+    }
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+    acc_t PT, PM;
+    unit_reduce<F32>(U[u & 1], PT, PM);
+    if (u & 1) {
+      accT[u >> 1] += (double)PT0 + (double)PT;
+      accM[u >> 1] += (double)PM0 + (double)PM;
+    } else {
+      PT0 = PT;
+      PM0 = PM;
+    }
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+  }
+}
 
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
@@ -267,76 +350,75 @@ __device__ __forceinline__ void load_tile(uint2 (&d)[NS], const uint2* __restric
   }
 }
 
+// Centred residual of the subject set: rc[i] = r_i - mean for i in T, 0 elsewhere (up to n_pad),
+// mean = sum_T r / |T|, R = sum_T rc (~0) in fs. X_st^T 1_T = 0, so centring leaves the gradient
+// unchanged and keeps the table entries small. One workgroup.
+__global__ __launch_bounds__(1024) void k_center(const double* __restrict__ r, const double* __restrict__ mask, int64_t n,
+                                                 int64_t n_pad, int64_t nT, double* __restrict__ rc, FitState* __restrict__ fs,
+                                                 const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ double red[40];
+  double s1 = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s1 += (mask[i] != 0.0) ? r[i] : 0.0;
+  const double mean = block_sum(s1, red) / (double)nT;
+  double s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x) {
+    const double x = (i < n && mask[i] != 0.0) ? r[i] - mean : 0.0;
+    rc[i] = x;
+    s2 += x;
+  }
+  const double R = block_sum(s2, red);
+  if (threadIdx.x == 0) {
+    fs->mean = mean;
+    fs->Rsum = R;
+  }
+}
+
 template <int NS, bool F32>
 __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
-                                                  int32_t tps, int64_t n, const double* __restrict__ r,
-                                                  const double* __restrict__ mask, int64_t nT, const double* __restrict__ u,
-                                                  const double* __restrict__ v, FitState* __restrict__ fs,
-                                                  double* __restrict__ g, double2* __restrict__ partial,
-                                                  const int32_t* __restrict__ gate) {
+                                                  int32_t tps, const double* __restrict__ rc,
+                                                  const double* __restrict__ u, const double* __restrict__ v,
+                                                  const FitState* __restrict__ fs, double* __restrict__ g,
+                                                  double2* __restrict__ partial, const int32_t* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  // The table sits at LDS address 0 (this kernel has no static LDS), so a v_perm result is the
-  // full lookup address; the residual of the block's subjects and the reduction scratch follow it.
-  extern __shared__ __attribute__((aligned(16))) uint4 dyn_lds[];
-  char* lds = reinterpret_cast<char*>(dyn_lds);               // 256 rows x 256 B table
-  double* red = reinterpret_cast<double*>(lds + 65536);      // 40 doubles of reduction scratch
-  double* rl = red + 40;                                      // centred residual of this block's subjects
-  constexpr uint32_t GS = Tab<F32>::kGroupShift;
+  // The kernel has no static LDS, so the dynamic allocation starts at LDS address 0: the table
+  // buffers are addressed by absolute LDS offsets.
 
   const int tid = threadIdx.x;
-  const int t0 = blockIdx.y * tps;
+  const int lane = tid & 63;
+  const int t0 = blockIdx.y * tps;  // even: tps is even
   const int t1 = min(ntiles, t0 + tps);
-  const int64_t i0 = (int64_t)t0 * kTileSubjects;
-  const int64_t nsub = (int64_t)(t1 - t0) * kTileSubjects;
 
   const int64_t jb = (int64_t)blockIdx.x * (kPassThreads * NS) + tid;
   const uint32_t voff = (uint32_t)(jb * 8);
-  // first tiles in flight before anything else
-  uint2 d[kRing][NS];
-#pragma unroll
-  for (int q = 0; q < kRing - 1; ++q) load_tile<NS>(d[q], tiled, p_pad, voff, t0 + q, t1);
+  // packed bytes of pair 0 in flight first
+  uint2 dA[2][NS], dB[2][NS];
+  load_tile<NS>(dA[0], tiled, p_pad, voff, t0, t1);
+  load_tile<NS>(dB[0], tiled, p_pad, voff, t0 + 1, t1);
 
-  // Centre the residual over the subject set: X_st^T 1_T = 0, so the gradient is unchanged and the
-  // table entries stay small. R = sum of the centred residual (~0) enters the epilogue.
-  double mean, R;
-  {
-    double s1 = 0.0;
-    for (int64_t i = tid; i < n; i += kPassThreads) s1 += (mask[i] != 0.0) ? r[i] : 0.0;
-    mean = block_sum(s1, red) / (double)nT;
-    double s2 = 0.0;
-    for (int64_t i = tid; i < n; i += kPassThreads) s2 += (mask[i] != 0.0) ? r[i] - mean : 0.0;
-    R = block_sum(s2, red);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
-      fs->mean = mean;
-      fs->Rsum = R;
-    }
-    for (int64_t q = tid; q < nsub; q += kPassThreads) {
-      const int64_t i = i0 + q;
-      rl[q] = (i < n && mask[i] != 0.0) ? r[i] - mean : 0.0;
-    }
+  // lane constants: the rotation of its SNPs (j % 8 == tid % 8) and which tile it reads first
+  const int rot = tid & 7;
+  const int hh = (lane >> 3) & 1;
+  // slot offset of step b: tile (b / 8) ^ hh, group (b % 8 + rot) % 8; packed 4 per register for
+  // buffer 0, 3 per register plus the 0x01 buffer byte for buffer 1
+  uint32_t offs0[4], offs1[6];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) offs0[k] = 0u;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) offs1[k] = 0x01000000u;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const uint32_t o = PassTab<F32>::slot(lane, (b >> 3) ^ hh, ((b & 7) + rot) & 7);
+    offs0[b >> 2] |= o << (8 * (b & 3));
+    offs1[b / 3] |= o << (8 * (b % 3));
   }
+  const int G = tid & 15, vb = tid >> 4;
 
-  const uint32_t rot = (uint32_t)tid & 7u;  // == j & 7 for every SNP slot of this lane
-  // offs[B][h] byte c = offset inside a table row of step b = c + 4h in LDS buffer B:
-  // B * 128 + copy base + (group (b + rot) mod 8) * entry size.
-  uint32_t offs[2][2];
-#pragma unroll
-  for (int B = 0; B < 2; ++B)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      uint32_t o = 0;
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        o |= ((uint32_t)B * 128u + Tab<F32>::slot_base(tid) + ((((uint32_t)(c + 4 * h) + rot) & 7u) << GS)) << (8 * c);
-      offs[B][h] = o;
-    }
-  const int gb = tid & 7, vb = tid >> 3;
-
-  // residuals of builder group gb in tile t (zero past the block's range -> all-zero table)
-  auto group_r = [&](int t, double (&rr)[4]) {
+  // centred residuals of builder group G in pair q (zero past the range: all-zero tables)
+  auto group_r = [&](int q, double (&rr)[4]) {
+    const int t = t0 + 2 * q + (G >> 3);
     const bool live = t < t1;
-    const int q = live ? (t - t0) * kTileSubjects + gb * 4 : 0;
-    const double4 x = *reinterpret_cast<const double4*>(rl + q);
+    const double4 x = *reinterpret_cast<const double4*>(rc + (int64_t)(live ? t : t0) * kTileSubjects + 4 * (G & 7));
     rr[0] = live ? x.x : 0.0;
     rr[1] = live ? x.y : 0.0;
     rr[2] = live ? x.z : 0.0;
@@ -349,35 +431,36 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
     accT[s] = 0.0;
     accM[s] = 0.0;
   }
-  __syncthreads();  // residual staged
-  {
-    double rr[4];
-    group_r(t0, rr);
-    build_entries<F32, kPassThreads>(lds, 0, gb, vb, rr);
-  }
+  double rr[4];
+  group_r(0, rr);
+  build_pair<F32, kPassThreads>(0u, G, vb, rr);
+  group_r(1, rr);
   __syncthreads();
 
-  // Tile t uses ring slot (t - t0) % 4 and LDS buffer (t - t0) % 2, both compile-time in the
-  // unrolled body. Each step prefetches tile t+3, builds the table of tile t+1 and consumes tile t.
-  // Tiles past t1 (at most 3 in the last trip) have all-zero tables and add exact zeros.
-  const int trips = (t1 - t0 + kRing - 1) / kRing;
+  // Pair q uses register slot q % 2 and table buffer q % 2, both compile-time in the unrolled body.
+  // Each step loads pair q+1, builds the table of pair q+1, prefetches the residuals of pair q+2 and
+  // consumes pair q. Pairs past the range (at most 1) have all-zero tables and add exact zeros.
+  const int npairs = (t1 - t0 + 1) / 2;
+  const int trips = (npairs + 1) / 2;
   for (int trip = 0; trip < trips; ++trip) {
 #pragma unroll
-    for (int uu = 0; uu < kRing; ++uu) {
-      const int t = t0 + trip * kRing + uu;
-      load_tile<NS>(d[(uu + kRing - 1) % kRing], tiled, p_pad, voff, t + kRing - 1, t1);
-      {
-        double rr[4];
-        group_r(t + 1, rr);
-        build_entries<F32, kPassThreads>(lds, (uu + 1) & 1, gb, vb, rr);
-      }
+    for (int uu = 0; uu < 2; ++uu) {
+      const int q = trip * 2 + uu;
+      const int tn = t0 + 2 * (q + 1);
+      load_tile<NS>(dA[uu ^ 1], tiled, p_pad, voff, tn, t1);
+      load_tile<NS>(dB[uu ^ 1], tiled, p_pad, voff, tn + 1, t1);
+      build_pair<F32, kPassThreads>(uu ? 0u : kPassBuf1, G, vb, rr);
+      group_r(q + 2, rr);
+      uint2 first[NS], second[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        tile_sum<F32>(lds, offs[uu & 1], d[uu][s], accT[s], accM[s]);
-#if IHT_PASS_SNP_BARRIER
-        __builtin_amdgcn_sched_barrier(0);
-#endif
+        first[s] = hh ? dB[uu][s] : dA[uu][s];
+        second[s] = hh ? dA[uu][s] : dB[uu][s];
       }
+      if (uu == 0)
+        pair_step<F32, 0, NS>(offs0, offs1, first, second, accT, accM);
+      else
+        pair_step<F32, 1, NS>(offs0, offs1, first, second, accT, accM);
       __syncthreads();
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -390,7 +473,7 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
       if (partial) {
         partial[(int64_t)blockIdx.y * p_pad + j] = make_double2(accT[s], accM[s]);
       } else {
-        g[j] = v[j] * (accT[s] - u[j] * (R - accM[s]));
+        g[j] = v[j] * (accT[s] - u[j] * (fs->Rsum - accM[s]));
       }
     }
   }
@@ -901,19 +984,19 @@ struct PassGeom {
 };
 
 PassGeom pass_geometry(const Layout& L, int precision) {
-  const int cand64[3] = {4, 2, 1}, cand32[3] = {4, 2, 1};
+  const int cand64[4] = {8, 4, 2, 1}, cand32[4] = {8, 4, 2, 1};
   const int* cand = precision == 1 ? cand32 : cand64;
-  const int ncand = 3;
-  const int64_t min_split = (L.ntiles + kMaxTilesPerBlock - 1) / kMaxTilesPerBlock;
-  PassGeom G{1, 1, (int)L.ntiles, 0};
+  const int ncand = 4;
+  PassGeom G{1, 1, (int)((L.ntiles + 1) / 2 * 2), 0};
   for (int ci = 0; ci < ncand; ++ci) {
     const int ns = cand[ci];
+    if (ns > kPassMaxNS) continue;
     const int64_t groups = (L.p + (int64_t)kPassThreads * ns - 1) / ((int64_t)kPassThreads * ns);
     if (groups * 2 >= 256 || ns == 1 || (groups >= 64 && L.ntiles >= 8)) {
       int64_t split = std::max<int64_t>(1, 256 / groups);
-      split = std::min<int64_t>(split, L.ntiles);
-      split = std::max<int64_t>(split, min_split);
-      const int tps = (int)((L.ntiles + split - 1) / split);
+      split = std::min<int64_t>(split, (L.ntiles + 1) / 2);
+      int tps = (int)((L.ntiles + split - 1) / split);
+      tps += tps & 1;  // whole tile pairs per block
       split = (L.ntiles + tps - 1) / tps;
       G = PassGeom{ns, (int)split, tps, groups};
       break;
@@ -922,7 +1005,6 @@ PassGeom pass_geometry(const Layout& L, int precision) {
   return G;
 }
 
-size_t pass_lds_bytes(const PassGeom& G) { return 65536 + 40 * sizeof(double) + (size_t)G.tps * kTileSubjects * sizeof(double); }
 
 }  // namespace
 
@@ -943,56 +1025,61 @@ hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* m
   return hipGetLastError();
 }
 
-size_t gradient_partial_bytes(const Layout& L) {
+size_t gradient_work_bytes(const Layout& L) {
   size_t b = 0;
   for (int prec = 0; prec < 2; ++prec) {
     const PassGeom G = pass_geometry(L, prec);
     if (G.split > 1) b = std::max(b, (size_t)G.split * (size_t)L.p_pad * sizeof(double2));
   }
-  return b;
+  return (size_t)L.n_pad * sizeof(double) + b;
 }
 
 template <int NS, bool F32>
-static void launch_pass_one(dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* r,
-                            const double* mask, int64_t nT, const double* u, const double* v, FitState* fs, double* g,
-                            double2* partial, const int32_t* gate) {
+static void launch_pass_one(dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* rc,
+                            const double* u, const double* v, const FitState* fs, double* g, double2* partial,
+                            const int32_t* gate) {
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pass<NS, F32>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              65536 + 40 * (int)sizeof(double) + kMaxTilesPerBlock * kTileSubjects * (int)sizeof(double));
+                              (int)kPassLdsBytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL((k_pass<NS, F32>), grid, dim3(kPassThreads), lds, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles, tps, L.n, r,
-                     mask, nT, u, v, fs, g, partial, gate);
+  hipLaunchKernelGGL((k_pass<NS, F32>), grid, dim3(kPassThreads), kPassLdsBytes, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles,
+                     tps, rc, u, v, fs, g, partial, gate);
 }
 
 template <int NS>
-static void launch_pass_ns(bool f32, dim3 grid, size_t lds, hipStream_t st, const uint2* tiled, const Layout& L, int tps,
-                           const double* r, const double* mask, int64_t nT, const double* u, const double* v, FitState* fs,
-                           double* g, double2* partial, const int32_t* gate) {
+static void launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* rc,
+                           const double* u, const double* v, const FitState* fs, double* g, double2* partial,
+                           const int32_t* gate) {
   if (!f32) {
-    launch_pass_one<NS, false>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial, gate);
+    launch_pass_one<NS, false>(grid, st, tiled, L, tps, rc, u, v, fs, g, partial, gate);
     return;
   }
-  launch_pass_one<NS, true>(grid, lds, st, tiled, L, tps, r, mask, nT, u, v, fs, g, partial, gate);
+  launch_pass_one<NS, true>(grid, st, tiled, L, tps, rc, u, v, fs, g, partial, gate);
 }
 
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
-                           const double* u, const double* v, FitState* fs, int precision, double* g, double* partial,
+                           const double* u, const double* v, FitState* fs, int precision, double* g, double* work,
                            const int32_t* gate, hipStream_t st) {
   const PassGeom G = pass_geometry(L, precision);
+  double* rc = work;
+  double2* part = (G.split > 1) ? reinterpret_cast<double2*>(work + L.n_pad) : nullptr;
+  hipLaunchKernelGGL(k_center, dim3(1), dim3(1024), 0, st, r, mask, L.n, L.n_pad, nT, rc, fs, gate);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const dim3 grid((unsigned)G.groups, (unsigned)G.split);
-  double2* part = (G.split > 1) ? reinterpret_cast<double2*>(partial) : nullptr;
   const bool f32 = precision == 1;
   const uint2* t4 = reinterpret_cast<const uint2*>(tiled);
-  const size_t lds = pass_lds_bytes(G);
-  if (G.ns == 4)
-    launch_pass_ns<4>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
+  if (G.ns == 8)
+    launch_pass_ns<8>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, gate);
+  else if (G.ns == 4)
+    launch_pass_ns<4>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, gate);
   else if (G.ns == 2)
-    launch_pass_ns<2>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
+    launch_pass_ns<2>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, gate);
   else
-    launch_pass_ns<1>(f32, grid, lds, st, t4, L, G.tps, r, mask, nT, u, v, fs, g, part, gate);
-  hipError_t e = hipGetLastError();
+    launch_pass_ns<1>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, gate);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (part) {
     hipLaunchKernelGGL(k_pass_finalize, dim3((unsigned)((L.p + 255) / 256)), dim3(256), 0, st, part, G.split, L.p, L.p_pad, u,

@@ -18,9 +18,13 @@ constexpr int64_t kSnpAlign = 8192;  // p is padded to this (covers 1024 lanes x
 #define IHT_PASS_THREADS 512
 #endif
 #ifndef IHT_PASS_SNP_BARRIER
-#define IHT_PASS_SNP_BARRIER 1
+#define IHT_PASS_SNP_BARRIER 0
 #endif
-constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (64 KB table + residual in LDS)
+#ifndef IHT_PASS_MAX_NS
+#define IHT_PASS_MAX_NS 8
+#endif
+constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (128 KB of table in LDS)
+constexpr int kPassMaxNS = IHT_PASS_MAX_NS;     // SNPs per lane, at most
 constexpr int kSmallThreads = 1024;
 constexpr int kMaxUnpenalized = 64;  // dense covariates + intercept
 constexpr int kTopkBins0 = 8192;     // first-level histogram: key bits 62..50
@@ -106,16 +110,13 @@ hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L,
 hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
                         hipStream_t st);
 
-// g = X_st^T r over the subject set (mask, nT): one pass kernel (plus a finalize kernel when the
-// subjects are split over workgroups; `partial` then holds split * p_pad (D, M) pairs). The pass
-// writes the subject-set mean of r and R = sum of the centred residual to fs.
+// g = X_st^T r over the subject set (mask, nT): a centring kernel (mean and R = sum of the centred
+// residual into fs, centred residual into `work`), the pass kernel, and a finalize kernel when the
+// subjects are split over workgroups. `work` holds gradient_work_bytes(L).
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
-                           const double* u, const double* v, FitState* fs, int precision, double* g, double* partial,
+                           const double* u, const double* v, FitState* fs, int precision, double* g, double* work,
                            const int32_t* gate, hipStream_t st);
-size_t gradient_partial_bytes(const Layout& L);
-
-hipError_t launch_decode_cols(const uint8_t* tiled, const Layout& L, const int64_t* cols, int32_t kc, const double* u,
-                              const double* v, const double* mask, double* out, hipStream_t st);
+size_t gradient_work_bytes(const Layout& L);
 
 // Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st);

@@ -70,6 +70,26 @@ def test_stats_degenerate_columns():
 GRAD_CASES = [(1, 3), (5, 17), (32, 8192), (33, 8193), (100, 1), (1001, 1234), (1000, 10_000), (2500, 40_000)]
 
 
+# p chosen so the pass runs each of its geometries at n = 1000 (32 tiles): 8, 4, 2 SNPs per lane,
+# the larger ones with the subject range split over workgroups (partial sums + finalize)
+@pytest.mark.parametrize("p", [70_000, 140_000, 270_000])
+@pytest.mark.parametrize("precision", [iht.FP64, iht.FP32])
+def test_gradient_parity_pass_geometries(p, precision):
+    n = 1000
+    say(f"gradient geometry n={n} p={p} precision={precision}")
+    bed, _ = synth.make_genotypes(n, p, seed=p + 3)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    r = np.random.default_rng(p).standard_normal(n)
+    got = iht.gradient(g, s, dev(r), precision).cpu().numpy()
+    u, v = oracle.stats(bed, n)
+    ref = oracle.gradient(bed, n, u, v, r)
+    e = rel(got, ref)
+    assert e <= (1e-12 if precision == iht.FP64 else 2e-6), e
+    if precision == iht.FP64:
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("n,p", GRAD_CASES)
 @pytest.mark.parametrize("precision", [iht.FP64, iht.FP32])
 def test_gradient_parity(n, p, precision):
