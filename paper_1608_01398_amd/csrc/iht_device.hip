@@ -241,20 +241,29 @@ __device__ __forceinline__ void build_pair(uint32_t buf, int G, int vb, const do
   }
 }
 
-// A lookup unit: the 8 lookups of one tile of one SNP (steps 8 half .. 8 half + 7 of the pair).
+// A lookup unit: kUnitLookups lookups of one tile of one SNP. With 8, a unit is the whole tile
+// (steps 8 half .. 8 half + 7 of the pair); with 4 it is the byte positions {c, c+4} for two
+// consecutive c, so a tile takes two units.
+constexpr int kUnitLookups = IHT_PASS_UNIT;
+constexpr int kUnitsPerTile = 8 / kUnitLookups;
+
 template <bool F32>
 struct Unit {
   using acc_t = typename std::conditional<F32, float, double>::type;
-  acc_t t[8], m[8];
+  acc_t t[kUnitLookups], m[kUnitLookups];
 };
 
+// Unit `part` of tile `half`: byte positions c + 4h for c in [part * C, part * C + C), h in {0, 1},
+// C = kUnitLookups / 2; value index (c - part * C) + C h.
 template <bool F32, int BUF>
 __device__ __forceinline__ void unit_lookup(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], uint2 d, int half,
-                                            Unit<F32>& U) {
+                                            int part, Unit<F32>& U) {
+  constexpr int C = kUnitLookups / 2;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int cc = 0; cc < C; ++cc) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      const int c = part * C + cc;
       const int b = half * 8 + c + 4 * h;  // step; byte c of dword h of the segment
       const uint32_t dw = h ? d.y : d.x;
       // buffer 0: offs0[b / 4] byte b % 4 holds the slot offset; bytes 2-3 of the address are 0.
@@ -269,62 +278,69 @@ __device__ __forceinline__ void unit_lookup(const uint32_t (&offs0)[4], const ui
       }
       if constexpr (F32) {
         const v2f_t e = *reinterpret_cast<const lds_float2*>((size_t)addr);
-        U.t[c + 4 * h] = e.x;
-        U.m[c + 4 * h] = e.y;
+        U.t[cc + C * h] = e.x;
+        U.m[cc + C * h] = e.y;
       } else {
         const v2d_t e = *reinterpret_cast<const lds_double2*>((size_t)addr);
-        U.t[c + 4 * h] = e.x;
-        U.m[c + 4 * h] = e.y;
+        U.t[cc + C * h] = e.x;
+        U.m[cc + C * h] = e.y;
       }
     }
   }
 }
 
-// Rotation-invariant tree over byte positions: pairs {b, b+4}, then {0, 2} + {1, 3}. The same
-// pairings of byte positions are the same pairings of groups for every rotation, so the tile sum
-// depends only on the column's bytes.
+// Rotation-invariant tree over byte positions: QT[c] = v[c] + v[c+4], then (QT0 + QT2) + (QT1 + QT3).
+// The same pairings of byte positions are the same pairings of groups for every rotation, so the
+// tile sum depends only on the column's bytes. q[] collects the QT of a tile across its units.
 template <bool F32>
-__device__ __forceinline__ void unit_reduce(const Unit<F32>& U, typename Unit<F32>::acc_t& PT, typename Unit<F32>::acc_t& PM) {
-  typename Unit<F32>::acc_t QT[4], QM[4];
+__device__ __forceinline__ void unit_pairs(const Unit<F32>& U, int part, typename Unit<F32>::acc_t (&qt)[4],
+                                           typename Unit<F32>::acc_t (&qm)[4]) {
+  constexpr int C = kUnitLookups / 2;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    QT[c] = U.t[c] + U.t[c + 4];
-    QM[c] = U.m[c] + U.m[c + 4];
+  for (int cc = 0; cc < C; ++cc) {
+    qt[part * C + cc] = U.t[cc] + U.t[cc + C];
+    qm[part * C + cc] = U.m[cc] + U.m[cc + C];
   }
-  PT = (QT[0] + QT[2]) + (QT[1] + QT[3]);
-  PM = (QM[0] + QM[2]) + (QM[1] + QM[3]);
 }
 
-// All lookups of one pair for the lane's NS SNPs, software-pipelined over the 2 NS units (tile
-// halves): the lookups of unit u+1 are issued before unit u is summed, so the LDS latency of one
-// unit overlaps the adds of the previous one; at most two units of results are live. The two tile
-// sums of a SNP are combined as acc += (A + B), which is commutative: identical columns give
-// bitwise identical gradients whichever tile a lane reads first.
+// All lookups of one pair for the lane's NS SNPs, software-pipelined over the units (kPassPipeDepth
+// units of lookups in flight ahead of the one being summed). The two tile sums of a SNP are
+// combined as acc += (A + B), which is commutative: identical columns give bitwise identical
+// gradients whichever tile a lane reads first.
 template <bool F32, int BUF, int NS>
 __device__ __forceinline__ void pair_step(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], const uint2 (&first)[NS],
                                           const uint2 (&second)[NS], double (&accT)[NS], double (&accM)[NS]) {
   using acc_t = typename Unit<F32>::acc_t;
-  constexpr int NU = 2 * NS;
-  Unit<F32> U[2];
+  constexpr int UPS = 2 * kUnitsPerTile;  // units per SNP
+  constexpr int NU = NS * UPS;
+  constexpr int D = kPassPipeDepth;
+  Unit<F32> U[D + 1];
+  acc_t qt[4], qm[4];      // pair sums of the tile in progress
   acc_t PT0 = 0, PM0 = 0;  // first tile's sums of the current SNP
-  unit_lookup<F32, BUF>(offs0, offs1, first[0], 0, U[0]);
+  auto issue = [&](int u, Unit<F32>& dst) {
+    const int snp = u / UPS, half = (u % UPS) / kUnitsPerTile, part = u % kUnitsPerTile;
+    unit_lookup<F32, BUF>(offs0, offs1, half ? second[snp] : first[snp], half, part, dst);
+  };
+#pragma unroll
+  for (int u = 0; u < D && u < NU; ++u) issue(u, U[u]);
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    if (u + 1 < NU) {
-      const int s1 = (u + 1) >> 1, h1 = (u + 1) & 1;
-      unit_lookup<F32, BUF>(offs0, offs1, h1 ? second[s1] : first[s1], h1, U[(u + 1) & 1]);
-    }
+    if (u + D < NU) issue(u + D, U[(u + D) % (D + 1)]);
 #if IHT_PASS_SNP_BARRIER
     __builtin_amdgcn_sched_barrier(0);
 #endif
-    acc_t PT, PM;
-    unit_reduce<F32>(U[u & 1], PT, PM);
-    if (u & 1) {
-      accT[u >> 1] += (double)PT0 + (double)PT;
-      accM[u >> 1] += (double)PM0 + (double)PM;
-    } else {
-      PT0 = PT;
-      PM0 = PM;
+    const int snp = u / UPS, half = (u % UPS) / kUnitsPerTile, part = u % kUnitsPerTile;
+    unit_pairs<F32>(U[u % (D + 1)], part, qt, qm);
+    if (part == kUnitsPerTile - 1) {
+      const acc_t PT = (qt[0] + qt[2]) + (qt[1] + qt[3]);
+      const acc_t PM = (qm[0] + qm[2]) + (qm[1] + qm[3]);
+      if (half) {
+        accT[snp] += (double)PT0 + (double)PT;
+        accM[snp] += (double)PM0 + (double)PM;
+      } else {
+        PT0 = PT;
+        PM0 = PM;
+      }
     }
 #if IHT_PASS_SNP_BARRIER
     __builtin_amdgcn_sched_barrier(0);

@@ -15,16 +15,23 @@ constexpr int kTileSubjects = 32;
 constexpr int kSegBytes = 8;
 constexpr int64_t kSnpAlign = 8192;  // p is padded to this (covers 1024 lanes x 8 SNPs per lane)
 #ifndef IHT_PASS_THREADS
-#define IHT_PASS_THREADS 512
+#define IHT_PASS_THREADS 1024
 #endif
 #ifndef IHT_PASS_SNP_BARRIER
 #define IHT_PASS_SNP_BARRIER 0
 #endif
 #ifndef IHT_PASS_MAX_NS
-#define IHT_PASS_MAX_NS 8
+#define IHT_PASS_MAX_NS 4
 #endif
 constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (128 KB of table in LDS)
 constexpr int kPassMaxNS = IHT_PASS_MAX_NS;     // SNPs per lane, at most
+#ifndef IHT_PASS_PIPE_DEPTH
+#define IHT_PASS_PIPE_DEPTH 1
+#endif
+constexpr int kPassPipeDepth = IHT_PASS_PIPE_DEPTH;  // lookup units in flight ahead of the one summed
+#ifndef IHT_PASS_UNIT
+#define IHT_PASS_UNIT 4
+#endif
 constexpr int kSmallThreads = 1024;
 constexpr int kMaxUnpenalized = 64;  // dense covariates + intercept
 constexpr int kTopkBins0 = 8192;     // first-level histogram: key bits 62..50
