@@ -109,7 +109,7 @@ struct TopkArea {
 // handle), plus the pinned host copy of their FitStates.
 namespace {
 struct SolveWork {
-  DevBuf beta, g, partial, r, S, Sp, betap, X, bc, bcp, gc, fs, uidx, udel, pw, ks, sv;
+  DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, uidx, udel, pw, ks, sv;
   DevBuf r8, scale, rsum, slots, count;
   TopkArea topk;
   FitState* host = nullptr;
@@ -433,6 +433,7 @@ int run_fit(const FitArgs& A) {
   HIPCHK(W.g.ensure(Tz * L.p * 8));
   HIPCHK(W.partial.ensure(gradient_work_bytes(L)));
   HIPCHK(W.r.ensure(Tz * L.n_pad * 8));
+  HIPCHK(W.rc.ensure(Tz * L.n_pad * 8));
   HIPCHK(W.S.ensure(Tz * kz * 8));
   HIPCHK(W.Sp.ensure(Tz * kz * 8));
   HIPCHK(W.betap.ensure(Tz * kz * 8));
@@ -480,6 +481,7 @@ int run_fit(const FitArgs& A) {
   Q.beta = W.beta.as<double>();
   Q.g = W.g.as<double>();
   Q.r = W.r.as<double>();
+  Q.rc = W.rc.as<double>();
   Q.S = W.S.as<int64_t>();
   Q.Sp = W.Sp.as<int64_t>();
   Q.betap = W.betap.as<double>();
@@ -522,21 +524,24 @@ int run_fit(const FitArgs& A) {
     for (int32_t t = 0; t < T; ++t)
       HIPCHK(launch_gradient(tiled, L, Q.r + (size_t)t * L.n_pad, sv[t].mask, sv[t].nT, sv[t].u, sv[t].v, Q.fs + t,
                              o.precision, Q.g + (size_t)t * L.p, W.partial.as<double>(),
-                             phase == kPhaseInit ? nullptr : &Q.fs[t].go, st));
+                             phase == kPhaseInit ? nullptr : &Q.fs[t].go, st, Q.rc + (size_t)t * L.n_pad));
     return IHT_OK;
   };
+  // proposal of the solves in `phase`: projection, then columns, backtracking test and (for the
+  // accepted ones) residual, loss and centred residual
   auto propose = [&](int32_t phase) -> int {
     J.phase = phase;
     J.out = Q.Sp;
     J.vals = Q.betap;
     HIPCHK(launch_topk(J, L.p, T, st));
     HIPCHK(solve_decode(tiled, Q, 1, phase, st));
+    HIPCHK(solve_check_residual(Q, phase, o.c, o.max_backtrack, st));
     return IHT_OK;
   };
+  // gradient of the accepted proposals, commit, and the next step size
   auto tail = [&]() -> int {
-    HIPCHK(solve_residual(Q, kPhaseGo, 0, st));
     if (int rc = gradient(kPhaseGo)) return rc;
-    HIPCHK(solve_commit(Q, tol_main, o.max_iter, st));
+    HIPCHK(solve_commit_mu(Q, 1, tol_main, o.max_iter, st));
     return IHT_OK;
   };
   auto read_states = [&]() -> int {
@@ -550,31 +555,39 @@ int run_fit(const FitArgs& A) {
     return c;
   };
 
-  // initial state: beta = 0, r = y on each subject set, g = A^T r, S = top-k |g| (mu = 1, beta = 0)
+  // initial state: beta = 0, r = y on each subject set, g = A^T r, S = top-k |g| (mu = 1, beta = 0),
+  // then the first step size
   HIPCHK(launch_topk_clear_errors(J.small, T, st));
   HIPCHK(solve_init(Q, o.max_iter, st));
-  HIPCHK(solve_residual(Q, kPhaseInit, 1, st));
+  HIPCHK(solve_residual0(Q, st));
   if (int rc = gradient(kPhaseInit)) return rc;
   J.phase = kPhaseInit;
   J.out = Q.S;
   J.vals = nullptr;
   HIPCHK(launch_topk(J, L.p, T, st));
   HIPCHK(solve_decode(tiled, Q, 0, kPhaseInit, st));
+  HIPCHK(solve_commit_mu(Q, 0, tol_main, o.max_iter, st));
   if (int rc = read_states()) return rc;
 
-  for (int32_t m = 0; m < o.max_iter && count_if([](const FitState& f) { return f.active != 0; }) > 0; ++m) {
-    HIPCHK(solve_mu(Q, st));
-    if (int rc = propose(kPhaseActive)) return rc;
-    HIPCHK(solve_bt_check(Q, kPhaseActive, o.c, o.max_backtrack, st));
-    if (int rc = tail()) return rc;
-    if (int rc = read_states()) return rc;
+  // The first proposal, then turns of: halving rounds for the solves whose proposal was rejected,
+  // and kAhead speculative iterations (gradient, commit + next step size, next proposal) per read
+  // of the flags. Every kernel is gated per solve on the device flags, and a proposal step is
+  // idempotent for a solve waiting for a halving (same step size, same proposal, same rejection),
+  // so running ahead never changes a result; solves that finished skip the extra launches.
+  constexpr int kAhead = 2;
+  if (int rc = propose(kPhaseActive)) return rc;
+  if (int rc = read_states()) return rc;
+  for (int32_t turn = 0; turn <= o.max_iter && count_if([](const FitState& f) { return f.active != 0; }) > 0; ++turn) {
     while (count_if([](const FitState& f) { return f.active != 0 && f.need_bt != 0; }) > 0) {
       HIPCHK(solve_shrink(Q, o.shrink, st));
       if (int rc = propose(kPhaseBacktrack)) return rc;
-      HIPCHK(solve_bt_check(Q, kPhaseBacktrack, o.c, o.max_backtrack, st));
-      if (int rc = tail()) return rc;
       if (int rc = read_states()) return rc;
     }
+    for (int a = 0; a < kAhead; ++a) {
+      if (int rc = tail()) return rc;
+      if (int rc = propose(kPhaseActive)) return rc;
+    }
+    if (int rc = read_states()) return rc;
   }
   if (o.precision != IHT_FP64 && o.polish_iter > 0) HIPCHK(solve_polish(Q, o.tol, o.polish_iter, st));
   HIPCHK(solve_output(Q, A.support, A.beta_S, A.beta_cov, kmax, nc, st));

@@ -1077,13 +1077,16 @@ static void launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* til
 
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
                            const double* u, const double* v, FitState* fs, int precision, double* g, double* work,
-                           const int32_t* gate, hipStream_t st) {
+                           const int32_t* gate, hipStream_t st, const double* rc_ready) {
   const PassGeom G = pass_geometry(L, precision);
-  double* rc = work;
+  const double* rc = rc_ready ? rc_ready : work;
   double2* part = (G.split > 1) ? reinterpret_cast<double2*>(work + L.n_pad) : nullptr;
-  hipLaunchKernelGGL(k_center, dim3(1), dim3(1024), 0, st, r, mask, L.n, L.n_pad, nT, rc, fs, gate);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!rc_ready) {
+    hipLaunchKernelGGL(k_center, dim3(1), dim3(1024), 0, st, r, mask, L.n, L.n_pad, nT, work, fs, gate);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   const dim3 grid((unsigned)G.groups, (unsigned)G.split);
   const bool f32 = precision == 1;
   const uint2* t4 = reinterpret_cast<const uint2*>(tiled);

@@ -119,10 +119,11 @@ hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* m
 
 // g = X_st^T r over the subject set (mask, nT): a centring kernel (mean and R = sum of the centred
 // residual into fs, centred residual into `work`), the pass kernel, and a finalize kernel when the
-// subjects are split over workgroups. `work` holds gradient_work_bytes(L).
+// subjects are split over workgroups. `work` holds gradient_work_bytes(L). With rc_ready the
+// centred residual (and fs->Rsum) come from the caller and the centring kernel is skipped.
 hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
                            const double* u, const double* v, FitState* fs, int precision, double* g, double* work,
-                           const int32_t* gate, hipStream_t st);
+                           const int32_t* gate, hipStream_t st, const double* rc_ready = nullptr);
 size_t gradient_work_bytes(const Layout& L);
 
 // Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.

@@ -18,6 +18,7 @@ struct SolveSet {
   double* beta;  // [T][p] dense coefficients (zero off the support)
   double* g;     // [T][p] gradient X_st^T r
   double* r;     // [T][n_pad] residual (zero outside the subject set)
+  double* rc;    // [T][n_pad] residual centred over the subject set (gradient pass input)
   int64_t* S;    // [T][kmax] support, ascending
   int64_t* Sp;   // [T][kmax] proposed support
   double* betap;  // [T][kmax] proposal on Sp
@@ -34,13 +35,16 @@ struct SolveSet {
 };
 
 hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st);
-hipError_t solve_residual(const SolveSet& Q, int32_t phase, int32_t initial, hipStream_t st);
-hipError_t solve_mu(const SolveSet& Q, hipStream_t st);
-hipError_t solve_bt_check(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st);
-hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
-hipError_t solve_commit(const SolveSet& Q, double tol, int32_t max_iter, hipStream_t st);
-// which = 0: columns of S into the current cache; 1: columns of S+ into the other one.
+// residual at beta = 0 (and its centred copy) of the solves with finite inputs
+hipError_t solve_residual0(const SolveSet& Q, hipStream_t st);
+// columns of S (which = 0, current cache) or S+ (which = 1, other cache) of the solves in `phase`
 hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, int32_t phase, hipStream_t st);
+// backtracking test of the decoded proposal, and residual/loss/centred residual if it is taken
+hipError_t solve_check_residual(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st);
+// mode 1: commit accepted proposals, then the next step size of those still iterating;
+// mode 0: step size of every active solve
+hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t max_iter, hipStream_t st);
+hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
 hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStream_t st);
 hipError_t solve_output(const SolveSet& Q, int64_t* support, double* beta_S, double* beta_cov, int64_t ldk, int64_t ldc,
                         hipStream_t st);

@@ -7,6 +7,8 @@
 // at different points of their iteration.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "iht.h"
 #include "iht_solve.h"
 
@@ -58,6 +60,7 @@ struct View {
   double* beta;
   double* g;
   double* r;
+  double* rc;  // centred residual (gradient pass input)
   int64_t* S;
   int64_t* Sp;
   double* betap;
@@ -83,6 +86,7 @@ __device__ __forceinline__ View view(const SolveSet& Q, int t) {
   V.beta = Q.beta + (int64_t)t * Q.p;
   V.g = Q.g + (int64_t)t * Q.p;
   V.r = Q.r + (int64_t)t * Q.n_pad;
+  V.rc = Q.rc + (int64_t)t * Q.n_pad;
   V.S = Q.S + (int64_t)t * Q.kmax;
   V.Sp = Q.Sp + (int64_t)t * Q.kmax;
   V.betap = Q.betap + (int64_t)t * Q.kmax;
@@ -157,12 +161,15 @@ __device__ __forceinline__ void apply_cols(const double* X, int64_t n_pad, const
 
 // beta = 0 (eq. ihta starts from the zero vector), non-finite y or covariates inside the subject
 // set flagged, mu = 1 so that the first projection of beta + mu g is the top-k of |g|.
+__global__ __launch_bounds__(256) void k_zero_beta(SolveSet Q) {
+  const int64_t total = (int64_t)Q.T * Q.p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) Q.beta[e] = 0.0;
+}
+
 __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter) {
   const int t = blockIdx.x;
   const double* mask = Q.sv[t].mask;
   const double* y = Q.Y + (int64_t)t * Q.ldy;
-  double* beta = Q.beta + (int64_t)t * Q.p;
-  for (int64_t j = threadIdx.x; j < Q.p; j += kThreads) beta[j] = 0.0;
   for (int c = threadIdx.x; c < kMaxUnpenalized; c += kThreads) {
     Q.bc[(int64_t)t * kMaxUnpenalized + c] = 0.0;
     Q.bcp[(int64_t)t * kMaxUnpenalized + c] = 0.0;
@@ -190,27 +197,59 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter)
   }
 }
 
-// ---------------------------------------------------------------------------- residual and loss
+// ---------------------------------------------------------------------------- block-level steps
+// Each step below is executed by the whole workgroup of one solve; `vec` is a block-shared vector of
+// kTopkMaxK doubles, `sh` a small reduction scratch. Steps end with the block synchronised.
 
-// r = mask (y - A_{S+ u C} beta+) and loss = 1/2 ||r||^2 into the trace (entry iter + 1), or at
-// beta = 0 into entry 0 when `initial`; gc = A_C^T r.
-__global__ __launch_bounds__(kThreads) void k_residual(SolveSet Q, int32_t phase, int32_t initial) {
-  if (!fs_selected(Q.fs + blockIdx.x, phase)) return;
-  const View V = view(Q, blockIdx.x);
-  __shared__ double sh[40];
-  __shared__ double bl[kTopkMaxK];
+// Support columns of S (which = 0, into the current cache) or of S+ (which = 1, into the other
+// cache): X[q][i] = v_j (x_ij - u_j) for j = that column, 0 for a missing entry and outside the
+// subject set. Only the support's columns are ever decoded (Methods, "Bandwidth optimization of
+// IHT").
+__device__ __forceinline__ double decode_entry(const uint8_t* __restrict__ tiled, int64_t p_pad, int64_t j, int64_t i,
+                                               const double* u, const double* v, const double* mask) {
+  const int64_t tile = i / kTileSubjects;
+  const int grp = (int)((i % kTileSubjects) >> 2);
+  const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
+  const uint8_t byte = tiled[(tile * p_pad + j) * kSegBytes + b];
+  const int code = (byte >> (2 * (i & 3))) & 3;
+  if (mask[i] == 0.0 || code == 1) return 0.0;
+  const double d = (code == 0) ? 0.0 : (double)(code - 1);
+  return v[j] * (d - u[j]);
+}
+
+// Wide decode (grid: subjects / 256 x kmax x T) of the columns of S (which = 0, into the current
+// cache) or of S+ (which = 1, into the other cache) of the solves in `phase`.
+__global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ tiled, SolveSet Q, int32_t which, int32_t phase) {
+  const int t = blockIdx.z;
+  const FitState* fs = Q.fs + t;
+  if (!fs_selected(fs, phase)) return;
+  const int q = blockIdx.y;
+  if (q >= Q.ks[t]) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Q.n_pad) return;
+  const int64_t* cols = (which ? Q.Sp : Q.S) + (int64_t)t * Q.kmax;
+  const int cache = which ? 1 - fs->xcur : fs->xcur;
+  double* out = Q.X + (((int64_t)t * 2 + cache) * Q.kmax + q) * Q.n_pad;
+  out[i] = decode_entry(tiled, Q.p_pad, cols[q], i, Q.sv[t].u, Q.sv[t].v, Q.sv[t].mask);
+}
+
+// r = mask (y - A_{S+ u C} beta+) and loss = 1/2 ||r||^2 (eq. leastsquaresloss) into the trace
+// (entry iter + 1), or at beta = 0 into entry 0 when `initial`; gc = A_C^T r. Then the residual
+// centred over the subject set for the gradient pass: rc = r - mean on T, 0 elsewhere (up to
+// n_pad), R = sum rc into fs (X_st^T 1_T = 0: centring leaves the gradient unchanged).
+__device__ void blk_residual(const SolveSet& Q, const View& V, int initial, double* vec, double* sh) {
   __shared__ double bcl[kMaxUnpenalized];
   const int kc = initial ? 0 : V.k;
-  for (int q = threadIdx.x; q < kc; q += kThreads) bl[q] = V.betap[q];
+  for (int q = threadIdx.x; q < kc; q += kThreads) vec[q] = V.betap[q];
   for (int q = threadIdx.x; q < V.nc; q += kThreads) bcl[q] = initial ? 0.0 : V.bcp[q];
   __syncthreads();
-  double rr = 0.0;
+  double rr = 0.0, rs = 0.0;
   for (int64_t i0 = threadIdx.x; i0 < Q.n; i0 += (int64_t)kSubjUnroll * kThreads) {
     int64_t ii[kSubjUnroll];
     bool ok[kSubjUnroll];
     double sm[kSubjUnroll];
     subj_block(i0, Q.n, V.mask, ii, ok);
-    apply_cols(V.Xp, Q.n_pad, bl, kc, Q.U, Q.n, bcl, ii, sm);
+    apply_cols(V.Xp, Q.n_pad, vec, kc, Q.U, Q.n, bcl, ii, sm);
 #pragma unroll
     for (int w = 0; w < kSubjUnroll; ++w) {
       const int64_t i = i0 + (int64_t)w * kThreads;
@@ -218,38 +257,45 @@ __global__ __launch_bounds__(kThreads) void k_residual(SolveSet Q, int32_t phase
         const double ri = ok[w] ? V.y[i] - sm[w] : 0.0;
         V.r[i] = ri;
         rr += ri * ri;
+        rs += ri;  // zero outside the subject set
       }
     }
   }
   const double loss = 0.5 * ssum(rr, sh);
+  const double mean = ssum(rs, sh) / (double)Q.sv[V.t].nT;
   for (int c = 0; c < V.nc; ++c) {
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < Q.n; i += kThreads) s += (V.mask[i] != 0.0) ? ucol(Q.U, Q.n, c, i) * V.r[i] : 0.0;
     s = ssum(s, sh);
     if (threadIdx.x == 0) V.gc[c] = s;
   }
+  double R = 0.0;
+  for (int64_t i = threadIdx.x; i < Q.n_pad; i += kThreads) {
+    const double x = (i < Q.n && V.mask[i] != 0.0) ? V.r[i] - mean : 0.0;
+    V.rc[i] = x;
+    R += x;
+  }
+  R = ssum(R, sh);
   if (threadIdx.x == 0) {
     V.trace[initial ? 0 : V.fs->iter + 1] = loss;
     V.fs->loss = loss;
+    V.fs->mean = mean;
+    V.fs->Rsum = R;
   }
+  __syncthreads();
 }
 
-// ---------------------------------------------------------------------------- step size
-
-// mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2. A zero denominator means the gradient vanishes
-// on S u C: nothing can move, the solve ends there (converged).
-__global__ __launch_bounds__(kThreads) void k_mu(SolveSet Q) {
-  if (!fs_selected(Q.fs + blockIdx.x, kPhaseActive)) return;
-  const View V = view(Q, blockIdx.x);
-  __shared__ double sh[40];
-  __shared__ double gl[kTopkMaxK];
+// mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2 ("IHT step sizes", normalised form). A zero
+// denominator means the gradient vanishes on S u C: nothing can move, the solve ends there
+// (converged).
+__device__ void blk_mu(const SolveSet& Q, const View& V, double* vec, double* sh) {
   __shared__ double gcl[kMaxUnpenalized];
-  for (int q = threadIdx.x; q < V.k; q += kThreads) gl[q] = V.g[V.S[q]];
+  for (int q = threadIdx.x; q < V.k; q += kThreads) vec[q] = V.g[V.S[q]];
   for (int q = threadIdx.x; q < V.nc; q += kThreads) gcl[q] = V.gc[q];
   __syncthreads();
   double num = 0.0;
   if (threadIdx.x == 0) {
-    for (int q = 0; q < V.k; ++q) num += gl[q] * gl[q];
+    for (int q = 0; q < V.k; ++q) num += vec[q] * vec[q];
     for (int q = 0; q < V.nc; ++q) num += gcl[q] * gcl[q];
   }
   double dd = 0.0;
@@ -258,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_mu(SolveSet Q) {
     bool ok[kSubjUnroll];
     double sm[kSubjUnroll];
     subj_block(i0, Q.n, V.mask, ii, ok);
-    apply_cols(V.Xs, Q.n_pad, gl, V.k, Q.U, Q.n, gcl, ii, sm);
+    apply_cols(V.Xs, Q.n_pad, vec, V.k, Q.U, Q.n, gcl, ii, sm);
 #pragma unroll
     for (int w = 0; w < kSubjUnroll; ++w)
       if (ok[w]) dd += sm[w] * sm[w];
@@ -281,20 +327,16 @@ __global__ __launch_bounds__(kThreads) void k_mu(SolveSet Q) {
       fs->mu = num / den;
     }
   }
+  __syncthreads();
 }
-
-// ---------------------------------------------------------------------------- backtracking test
 
 // Support comparison, unpenalised proposal bcp = bc + mu gc and, when the support moved,
 // omega = (1-c)||Delta||^2 / ||A Delta||^2 over S u S+ u C. The proposal is taken when the support is
 // unchanged or mu < omega; otherwise the solve needs a halving, and with the budget spent it stops
-// (stalled) keeping beta.
-__global__ __launch_bounds__(kThreads) void k_bt_check(SolveSet Q, int32_t phase, double c, int32_t max_backtrack) {
-  if (!fs_selected(Q.fs + blockIdx.x, phase)) return;
-  const View V = view(Q, blockIdx.x);
-  __shared__ double sh[40];
+// (stalled) keeping beta. Returns the accept flag (block-uniform).
+__device__ int blk_bt_check(const SolveSet& Q, const View& V, double c, int32_t max_backtrack, double* sh) {
   __shared__ double dcl[kMaxUnpenalized];
-  __shared__ int same_s, nu_s;
+  __shared__ int same_s, nu_s, acc_s;
   __shared__ double dd_s;
   const int k = V.k;
   const double mu = V.fs->mu;
@@ -388,27 +430,17 @@ __global__ __launch_bounds__(kThreads) void k_bt_check(SolveSet Q, int32_t phase
       fs->active = 0;
       fs->status = IHT_STALLED;
     }
+    acc_s = accept;
   }
+  __syncthreads();
+  return acc_s;
 }
-
-__global__ void k_shrink(SolveSet Q, double shrink) {
-  FitState* fs = Q.fs + blockIdx.x;
-  if (threadIdx.x == 0 && fs_selected(fs, kPhaseBacktrack)) {
-    fs->mu = fs->mu * shrink;
-    fs->nbt += 1;
-  }
-}
-
-// ---------------------------------------------------------------------------- commit
 
 // Convergence (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf); with S+ = S the union of
 // the supports is S itself, so the norms run over S+ and C), then beta <- beta+, S <- S+, the column
-// caches trade roles and one more iteration is counted.
-__global__ __launch_bounds__(kThreads) void k_commit(SolveSet Q, double tol, int32_t max_iter) {
-  if (!fs_selected(Q.fs + blockIdx.x, kPhaseGo)) return;
-  const View V = view(Q, blockIdx.x);
-  __shared__ double sh[40];
-  __shared__ int same_s;
+// caches trade roles and one more iteration is counted. Returns 1 if the solve is still iterating.
+__device__ int blk_commit(const SolveSet& Q, const View& V, double tol, int32_t max_iter, double* sh) {
+  __shared__ int same_s, act_s;
   if (threadIdx.x == 0) same_s = 1;
   __syncthreads();
   double dmax = 0.0, bmax = 0.0;
@@ -433,7 +465,6 @@ __global__ __launch_bounds__(kThreads) void k_commit(SolveSet Q, double tol, int
     V.S[q] = V.Sp[q];
   }
   for (int q = threadIdx.x; q < V.nc; q += kThreads) V.bc[q] = V.bcp[q];
-  __syncthreads();
   if (threadIdx.x == 0) {
     FitState* fs = V.fs;
     fs->conv = conv;
@@ -450,41 +481,61 @@ __global__ __launch_bounds__(kThreads) void k_commit(SolveSet Q, double tol, int
       fs->active = 0;
       fs->status = IHT_NOT_CONVERGED;
     }
+    act_s = fs->active;
+  }
+  __syncthreads();
+  return act_s;
+}
+
+// ---------------------------------------------------------------------------- step kernels
+
+// Initial residual (at beta = 0) of the solves with finite inputs.
+__global__ __launch_bounds__(kThreads) void k_residual0(SolveSet Q) {
+  if (!fs_selected(Q.fs + blockIdx.x, kPhaseInit)) return;
+  __shared__ double sh[40];
+  __shared__ double vec[kTopkMaxK];
+  const View V = view(Q, blockIdx.x);
+  blk_residual(Q, V, 1, vec, sh);
+}
+
+// A proposal (S+, beta+ from the projection, its columns decoded) of the solves in `phase`: the
+// backtracking test and, when the proposal is taken, its residual, loss and centred residual for
+// the gradient pass.
+__global__ __launch_bounds__(kThreads) void k_check_residual(SolveSet Q, int32_t phase, double c, int32_t max_backtrack) {
+  if (!fs_selected(Q.fs + blockIdx.x, phase)) return;
+  __shared__ double sh[40];
+  __shared__ double vec[kTopkMaxK];
+  const View V = view(Q, blockIdx.x);
+  if (blk_bt_check(Q, V, c, max_backtrack, sh)) blk_residual(Q, V, 0, vec, sh);
+}
+
+// Commit of the accepted proposals (mode 1), then the step size of the next iteration for the
+// solves that committed and still iterate; mode 0: step size of every active solve (first
+// iteration).
+__global__ __launch_bounds__(kThreads) void k_commit_mu(SolveSet Q, int32_t mode, double tol, int32_t max_iter) {
+  __shared__ double sh[40];
+  __shared__ double vec[kTopkMaxK];
+  const FitState* fs = Q.fs + blockIdx.x;
+  if (mode == 0) {
+    if (!fs_selected(fs, kPhaseActive)) return;
+    const View V = view(Q, blockIdx.x);
+    blk_mu(Q, V, vec, sh);
+    return;
+  }
+  if (!fs_selected(fs, kPhaseGo)) return;
+  const View V = view(Q, blockIdx.x);
+  if (blk_commit(Q, V, tol, max_iter, sh)) {
+    const View V2 = view(Q, blockIdx.x);  // the column caches have traded roles
+    blk_mu(Q, V2, vec, sh);
   }
 }
 
-// ---------------------------------------------------------------------------- support columns
-
-// Column q of S (which = 0, into the current cache) or of S+ (which = 1, into the other cache):
-// X[q][i] = v_j (x_ij - u_j) for j = that column, 0 for a missing entry and outside the subject set.
-// Only the support's columns are ever decoded (Methods, "Bandwidth optimization of IHT").
-__global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ tiled, SolveSet Q, int32_t which,
-                                                int32_t phase) {
-  const int t = blockIdx.z;
-  const FitState* fs = Q.fs + t;
-  if (!fs_selected(fs, phase)) return;
-  const int q = blockIdx.y;
-  if (q >= Q.ks[t]) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Q.n_pad) return;
-  const int64_t* cols = (which ? Q.Sp : Q.S) + (int64_t)t * Q.kmax;
-  const int cache = which ? 1 - fs->xcur : fs->xcur;
-  double* out = Q.X + (((int64_t)t * 2 + cache) * Q.kmax + q) * Q.n_pad;
-  const double* u = Q.sv[t].u;
-  const double* v = Q.sv[t].v;
-  const double* mask = Q.sv[t].mask;
-  const int64_t j = cols[q];
-  const int64_t tile = i / kTileSubjects;
-  const int grp = (int)((i % kTileSubjects) >> 2);
-  const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
-  const uint8_t byte = tiled[(tile * Q.p_pad + j) * kSegBytes + b];
-  const int code = (byte >> (2 * (i & 3))) & 3;
-  double x = 0.0;
-  if (mask[i] != 0.0 && code != 1) {
-    const double d = (code == 0) ? 0.0 : (double)(code - 1);
-    x = v[j] * (d - u[j]);
+__global__ void k_shrink(SolveSet Q, double shrink) {
+  FitState* fs = Q.fs + blockIdx.x;
+  if (threadIdx.x == 0 && fs_selected(fs, kPhaseBacktrack)) {
+    fs->mu = fs->mu * shrink;
+    fs->nbt += 1;
   }
-  out[i] = x;
 }
 
 // ---------------------------------------------------------------------------- FP64 polish
@@ -636,38 +687,37 @@ __global__ __launch_bounds__(64) void k_slots(const FitState* __restrict__ fs, i
 // ---------------------------------------------------------------------------- launchers
 
 hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st) {
+  const int64_t total = (int64_t)Q.T * Q.p;
+  hipLaunchKernelGGL(k_zero_beta, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256), 0, st, Q);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_init, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, max_iter);
   return hipGetLastError();
 }
 
-hipError_t solve_residual(const SolveSet& Q, int32_t phase, int32_t initial, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, phase, initial);
-  return hipGetLastError();
-}
-
-hipError_t solve_mu(const SolveSet& Q, hipStream_t st) {
-  hipLaunchKernelGGL(k_mu, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q);
-  return hipGetLastError();
-}
-
-hipError_t solve_bt_check(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st) {
-  hipLaunchKernelGGL(k_bt_check, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, phase, c, max_backtrack);
-  return hipGetLastError();
-}
-
-hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st) {
-  hipLaunchKernelGGL(k_shrink, dim3((unsigned)Q.T), dim3(64), 0, st, Q, shrink);
-  return hipGetLastError();
-}
-
-hipError_t solve_commit(const SolveSet& Q, double tol, int32_t max_iter, hipStream_t st) {
-  hipLaunchKernelGGL(k_commit, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, tol, max_iter);
+hipError_t solve_residual0(const SolveSet& Q, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual0, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q);
   return hipGetLastError();
 }
 
 hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, int32_t phase, hipStream_t st) {
   const dim3 grid((unsigned)((Q.n_pad + 255) / 256), (unsigned)Q.kmax, (unsigned)Q.T);
   hipLaunchKernelGGL(k_decode, grid, dim3(256), 0, st, tiled, Q, which, phase);
+  return hipGetLastError();
+}
+
+hipError_t solve_check_residual(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_residual, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, phase, c, max_backtrack);
+  return hipGetLastError();
+}
+
+hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_commit_mu, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, mode, tol, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st) {
+  hipLaunchKernelGGL(k_shrink, dim3((unsigned)Q.T), dim3(64), 0, st, Q, shrink);
   return hipGetLastError();
 }
 
