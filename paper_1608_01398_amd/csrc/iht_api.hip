@@ -109,7 +109,7 @@ struct TopkArea {
 // handle), plus the pinned host copy of their FitStates.
 namespace {
 struct SolveWork {
-  DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, uidx, udel, pw, ks, sv;
+  DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv;
   DevBuf r8, scale, rsum, slots, count;
   TopkArea topk;
   FitState* host = nullptr;
@@ -442,8 +442,10 @@ int run_fit(const FitArgs& A) {
   HIPCHK(W.bcp.ensure(Tz * kMaxUnpenalized * 8));
   HIPCHK(W.gc.ensure(Tz * kMaxUnpenalized * 8));
   HIPCHK(W.fs.ensure(Tz * sizeof(FitState)));
-  HIPCHK(W.uidx.ensure(Tz * 2 * kz * 4));
-  HIPCHK(W.udel.ensure(Tz * 2 * kz * 8));
+  const int32_t nb = solve_subject_blocks(L.n), pst = solve_partial_stride(nc);
+  HIPCHK(W.part.ensure(Tz * (size_t)nb * (size_t)pst * 8));
+  HIPCHK(W.pmu.ensure(Tz * (size_t)nb * 8));
+  HIPCHK(W.ysum.ensure(Tz * kYsumStride * 8));
   HIPCHK(W.pw.ensure(Tz * 3 * (kz + kMaxUnpenalized) * 8));
   HIPCHK(W.ks.ensure(Tz * 4));
   HIPCHK(W.sv.ensure(Tz * sizeof(BatchSolve)));
@@ -492,8 +494,11 @@ int run_fit(const FitArgs& A) {
   Q.fs = W.fs.as<FitState>();
   Q.trace = A.trace;
   Q.ldt = (int64_t)o.max_iter + 1;
-  Q.uidx = W.uidx.as<int32_t>();
-  Q.udel = W.udel.as<double>();
+  Q.nb = nb;
+  Q.pst = pst;
+  Q.part = W.part.as<double>();
+  Q.pmu = W.pmu.as<double>();
+  Q.ysum = W.ysum.as<double>();
   Q.pw = W.pw.as<double>();
 
   TopkJob J{};

@@ -29,10 +29,22 @@ struct SolveSet {
   FitState* fs;   // [T]
   double* trace;  // [T][ldt] loss trace
   int64_t ldt;
-  int32_t* uidx;  // [T][2 kmax] backtracking work: column sources of S u S+
-  double* udel;   // [T][2 kmax] and beta+ - beta there
   double* pw;     // [T][3][kmax + kMaxUnpenalized] polish vectors
+  // subject-split steps: nb = solve_subject_blocks(n) workgroups per solve, each leaving its
+  // partial sums in part (residual step) and pmu (step-size denominator)
+  int32_t nb, pst;
+  double* part;  // [T][nb][pst]
+  double* pmu;   // [T][nb]
+  double* ysum;  // [T][kYsumStride]: sum_T y, then sum_T A_c of the unpenalised columns
 };
+
+// Subjects per workgroup of the subject-split steps (one per lane).
+constexpr int kSubjBlock = 64;
+inline int32_t solve_subject_blocks(int64_t n) { return (int32_t)((n + kSubjBlock - 1) / kSubjBlock); }
+// Partial sums per workgroup of the residual step: ||r||^2, sum rc, ||A Delta||^2, ||Delta||^2, the
+// support-unchanged flag, then A_C^T r.
+inline int32_t solve_partial_stride(int32_t nc) { return 5 + nc; }
+constexpr int kYsumStride = 1 + kMaxUnpenalized;
 
 hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st);
 // residual at beta = 0 (and its centred copy) of the solves with finite inputs

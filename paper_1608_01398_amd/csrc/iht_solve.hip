@@ -1,7 +1,7 @@
-// iht_solve.hip -- per-solve step kernels of the IHT loop (one workgroup per solve).
+// iht_solve.hip -- per-solve step kernels of the IHT loop.
 //
-// Every kernel here works on solve t = blockIdx.x (or blockIdx.z) of a SolveSet; a single fit is
-// the case T = 1. The update is eq. (ihta) of Methods with the normalised step and the omega rule
+// Every kernel here works on solve t = blockIdx.x (or blockIdx.y, blockIdx.z) of a SolveSet; a
+// single fit is the case T = 1. The update is eq. (ihta) of Methods with the normalised step and the omega rule
 // of "IHT step sizes"; the loss is eq. (leastsquaresloss). The per-solve control state (active,
 // committed iterations, halvings, status) lives in FitState, so one launch serves solves that are
 // at different points of their iteration.
@@ -71,8 +71,6 @@ struct View {
   double* gc;
   FitState* fs;
   double* trace;
-  int32_t* uidx;
-  double* udel;
   double* pw;
 };
 
@@ -98,8 +96,6 @@ __device__ __forceinline__ View view(const SolveSet& Q, int t) {
   V.bcp = Q.bcp + (int64_t)t * kMaxUnpenalized;
   V.gc = Q.gc + (int64_t)t * kMaxUnpenalized;
   V.trace = Q.trace + (int64_t)t * Q.ldt;
-  V.uidx = Q.uidx + (int64_t)t * 2 * Q.kmax;
-  V.udel = Q.udel + (int64_t)t * 2 * Q.kmax;
   V.pw = Q.pw + (int64_t)t * 3 * (Q.kmax + kMaxUnpenalized);
   return V;
 }
@@ -176,16 +172,29 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter)
     Q.gc[(int64_t)t * kMaxUnpenalized + c] = 0.0;
   }
   __shared__ int bad;
+  __shared__ double sh[40];
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   int b = 0;
+  double sy = 0.0;
   for (int64_t i = threadIdx.x; i < Q.n; i += kThreads) {
     if (mask[i] == 0.0) continue;
     if (!isfinite(y[i])) b = 1;
+    sy += y[i];
     for (int c = 0; c < Q.U.cz; ++c)
       if (!isfinite(Q.U.Z[(int64_t)c * Q.n + i])) b = 1;
   }
   if (b) atomicOr(&bad, 1);
+  // sums over the subject set of y and of the unpenalised columns (the centring constants)
+  double* ys = Q.ysum + (int64_t)t * kYsumStride;
+  sy = ssum(sy, sh);
+  if (threadIdx.x == 0) ys[0] = sy;
+  for (int c = 0; c < Q.U.cz + Q.U.icpt; ++c) {
+    double sz = 0.0;
+    for (int64_t i = threadIdx.x; i < Q.n; i += kThreads) sz += (mask[i] != 0.0) ? ucol(Q.U, Q.n, c, i) : 0.0;
+    sz = ssum(sz, sh);
+    if (threadIdx.x == 0) ys[1 + c] = sz;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     FitState z{};
@@ -197,9 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter)
   }
 }
 
-// ---------------------------------------------------------------------------- block-level steps
-// Each step below is executed by the whole workgroup of one solve; `vec` is a block-shared vector of
-// kTopkMaxK doubles, `sh` a small reduction scratch. Steps end with the block synchronised.
+// ---------------------------------------------------------------------------- support columns
 
 // Support columns of S (which = 0, into the current cache) or of S+ (which = 1, into the other
 // cache): X[q][i] = v_j (x_ij - u_j) for j = that column, 0 for a missing entry and outside the
@@ -233,85 +240,386 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ tile
   out[i] = decode_entry(tiled, Q.p_pad, cols[q], i, Q.sv[t].u, Q.sv[t].v, Q.sv[t].mask);
 }
 
-// r = mask (y - A_{S+ u C} beta+) and loss = 1/2 ||r||^2 (eq. leastsquaresloss) into the trace
-// (entry iter + 1), or at beta = 0 into entry 0 when `initial`; gc = A_C^T r. Then the residual
-// centred over the subject set for the gradient pass: rc = r - mean on T, 0 elsewhere (up to
-// n_pad), R = sum rc into fs (X_st^T 1_T = 0: centring leaves the gradient unchanged).
-__device__ void blk_residual(const SolveSet& Q, const View& V, int initial, double* vec, double* sh) {
-  __shared__ double bcl[kMaxUnpenalized];
-  const int kc = initial ? 0 : V.k;
-  for (int q = threadIdx.x; q < kc; q += kThreads) vec[q] = V.betap[q];
-  for (int q = threadIdx.x; q < V.nc; q += kThreads) bcl[q] = initial ? 0.0 : V.bcp[q];
-  __syncthreads();
-  double rr = 0.0, rs = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < Q.n; i0 += (int64_t)kSubjUnroll * kThreads) {
-    int64_t ii[kSubjUnroll];
-    bool ok[kSubjUnroll];
-    double sm[kSubjUnroll];
-    subj_block(i0, Q.n, V.mask, ii, ok);
-    apply_cols(V.Xp, Q.n_pad, vec, kc, Q.U, Q.n, bcl, ii, sm);
+// ---------------------------------------------------------------------------- subject-split steps
+// The residual, backtracking and step-size steps split the subjects of each solve over nb =
+// ceil(n / 64) workgroups (grid nb x T): lane l of workgroup b takes subject 64 b + l, and the four
+// waves take every fourth support column, so that all column loads of a step are in flight at
+// once. Every workgroup leaves its partial sums in Q.part (Q.pmu); a one-workgroup-per-solve kernel
+// that follows adds them up in workgroup order, takes the solve's decisions and writes its state
+// (the kernel boundary publishes the partials, no device-wide fence is needed). The summation
+// order depends on n alone, never on the other solves of the launch.
+
+constexpr int kMbThreads = 256;
+constexpr int kMbWaves = kMbThreads / 64;
+constexpr int kMbChunk = 512;  // support entries staged in LDS at a time
+constexpr int kMbBatch = 8;    // column loads issued together by a lane
+
+struct Stage {
+  double coef[kMbChunk];
+  int32_t col[kMbChunk];  // column (cache * kmax + q) of the solve's column caches, -1: entry skipped
+  double ucoef[kMaxUnpenalized];
+  double dcoef[kMaxUnpenalized];
+  double red[kMbWaves][64];
+  double sh[kMbWaves];
+  int32_t flag;
+};
+
+__device__ __forceinline__ double wsum(double x) {  // wave sum, valid in lane 0
 #pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w) {
-      const int64_t i = i0 + (int64_t)w * kThreads;
-      if (i < Q.n) {
-        const double ri = ok[w] ? V.y[i] - sm[w] : 0.0;
-        V.r[i] = ri;
-        rr += ri * ri;
-        rs += ri;  // zero outside the subject set
-      }
-    }
-  }
-  const double loss = 0.5 * ssum(rr, sh);
-  const double mean = ssum(rs, sh) / (double)Q.sv[V.t].nT;
-  for (int c = 0; c < V.nc; ++c) {
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < Q.n; i += kThreads) s += (V.mask[i] != 0.0) ? ucol(Q.U, Q.n, c, i) * V.r[i] : 0.0;
-    s = ssum(s, sh);
-    if (threadIdx.x == 0) V.gc[c] = s;
-  }
-  double R = 0.0;
-  for (int64_t i = threadIdx.x; i < Q.n_pad; i += kThreads) {
-    const double x = (i < Q.n && V.mask[i] != 0.0) ? V.r[i] - mean : 0.0;
-    V.rc[i] = x;
-    R += x;
-  }
-  R = ssum(R, sh);
-  if (threadIdx.x == 0) {
-    V.trace[initial ? 0 : V.fs->iter + 1] = loss;
-    V.fs->loss = loss;
-    V.fs->mean = mean;
-    V.fs->Rsum = R;
-  }
-  __syncthreads();
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+  return x;
 }
 
-// mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2 ("IHT step sizes", normalised form). A zero
-// denominator means the gradient vanishes on S u C: nothing can move, the solve ends there
-// (converged).
-__device__ void blk_mu(const SolveSet& Q, const View& V, double* vec, double* sh) {
-  __shared__ double gcl[kMaxUnpenalized];
-  for (int q = threadIdx.x; q < V.k; q += kThreads) vec[q] = V.g[V.S[q]];
-  for (int q = threadIdx.x; q < V.nc; q += kThreads) gcl[q] = V.gc[q];
+__device__ double bsum(double x, Stage& s) {  // workgroup sum, in every thread
+  x = wsum(x);
   __syncthreads();
-  double num = 0.0;
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < V.k; ++q) num += vec[q] * vec[q];
-    for (int q = 0; q < V.nc; ++q) num += gcl[q] * gcl[q];
-  }
-  double dd = 0.0;
-  for (int64_t i0 = threadIdx.x; i0 < Q.n; i0 += (int64_t)kSubjUnroll * kThreads) {
-    int64_t ii[kSubjUnroll];
-    bool ok[kSubjUnroll];
-    double sm[kSubjUnroll];
-    subj_block(i0, Q.n, V.mask, ii, ok);
-    apply_cols(V.Xs, Q.n_pad, vec, V.k, Q.U, Q.n, gcl, ii, sm);
+  if ((threadIdx.x & 63) == 0) s.sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  return (s.sh[0] + s.sh[1]) + (s.sh[2] + s.sh[3]);
+}
+
+__device__ double bmax(double x, Stage& s) {  // workgroup max, in every thread
 #pragma unroll
-    for (int w = 0; w < kSubjUnroll; ++w)
-      if (ok[w]) dd += sm[w] * sm[w];
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_down(x, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s.sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  return fmax(fmax(s.sh[0], s.sh[1]), fmax(s.sh[2], s.sh[3]));
+}
+
+// a + sum over the staged entries e = wave, wave + 4, ... of X[col_e][ii] coef_e.
+__device__ __forceinline__ double acc_chunk(const double* __restrict__ Xt, int64_t n_pad, const Stage& s, int ne, int64_t ii,
+                                            double a) {
+  for (int e = threadIdx.x >> 6; e < ne; e += kMbBatch * kMbWaves) {
+    double x[kMbBatch], cf[kMbBatch];
+#pragma unroll
+    for (int q = 0; q < kMbBatch; ++q) {
+      const int idx = e + q * kMbWaves;
+      const int c = idx < ne ? s.col[idx] : -1;
+      x[q] = c >= 0 ? Xt[(int64_t)c * n_pad + ii] : 0.0;
+      cf[q] = c >= 0 ? s.coef[idx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kMbBatch; ++q) a += x[q] * cf[q];
   }
-  const double den = ssum(dd, sh);
+  return a;
+}
+
+// a + sum over the unpenalised columns c = wave, wave + 4, ... of A_c(ii) coef_c.
+__device__ __forceinline__ double acc_unpen(const Unpen& U, int64_t n, const double* coef, int nc, int64_t ii, double a) {
+  for (int c = threadIdx.x >> 6; c < nc; c += kMbWaves) a += ucol(U, n, c, ii) * coef[c];
+  return a;
+}
+
+// Sum of the four wave partials of this lane's subject (in every wave).
+__device__ __forceinline__ double combine_waves(double a, Stage& s) {
+  __syncthreads();
+  s.red[threadIdx.x >> 6][threadIdx.x & 63] = a;
+  __syncthreads();
+  const int l = threadIdx.x & 63;
+  return (s.red[0][l] + s.red[1][l]) + (s.red[2][l] + s.red[3][l]);
+}
+
+__device__ __forceinline__ bool in_sorted(const int64_t* __restrict__ a, int k, int64_t x) {
+  int lo = 0, hi = k;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < k && a[lo] == x;
+}
+
+// Sum over the solve's workgroups of partial field f of P0 (thread-strided, then the workgroup tree).
+__device__ double sum_partials(const double* P0, int32_t nb, int32_t pst, int f, Stage& s) {
+  double x = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kMbThreads) x += P0[(int64_t)b * pst + f];
+  return bsum(x, s);
+}
+
+// Residual of the solves in `phase` at their proposal (kCheck), or at beta = 0 for every solve with
+// finite inputs: r = mask (y - A_{S+ u C} beta+) and the residual centred over the subject set for
+// the gradient pass, rc = r - m on T, 0 elsewhere (up to n_pad). The centring constant m is the
+// mean of r over T in exact arithmetic: the decoded SNP columns sum to zero over T, so
+// m = (sum_T y - sum_c bcp_c sum_T A_c) / |T|, known before r is. Any constant leaves the gradient
+// unchanged (X_st^T 1_T = 0) as long as R = sum rc is the one used, and this one keeps rc small.
+// Partial sums per workgroup: ||r||^2, R, ||A Delta||^2 and sum_T A_C r; the first workgroup adds
+// ||Delta||^2 and the support-unchanged flag. k_decide turns them into the solve's state.
+//
+// With kCheck the proposal is under the backtracking test of "IHT step sizes": the unpenalised
+// proposal is bcp = bc + mu gc and, when the support moved, omega = (1-c)||Delta||^2 / ||A Delta||^2
+// over S u S+ u C, with Delta = beta+ - beta on S+, -beta on S \ S+, bcp - bc on C. r and rc are
+// formed before the decision: until a proposal is taken nothing reads them.
+template <bool kCheck>
+__global__ __launch_bounds__(kMbThreads) void k_residual(SolveSet Q, int32_t phase) {
+  const int t = blockIdx.y, b = blockIdx.x;
+  if (!fs_selected(Q.fs + t, kCheck ? phase : kPhaseInit)) return;
+  __shared__ Stage s;
+  const View V = view(Q, t);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)b * kSubjBlock + lane;
+  const bool in_n = i < Q.n;
+  const int64_t ii = in_n ? i : 0;
+  const bool ok = in_n && V.mask[ii] != 0.0;
+  const int k = V.k, nc = V.nc;
+  const double* Xt = Q.X + (int64_t)t * 2 * Q.kmax * Q.n_pad;
+  const int cs = V.fs->xcur, cp = 1 - cs;
+  const double mu = V.fs->mu;
+  const double* ys = Q.ysum + (int64_t)t * kYsumStride;
+
+  int same = 1;
+  double fit = 0.0;
+  if (kCheck) {
+    int diff = 0;
+    for (int q = threadIdx.x; q < k; q += kMbThreads) diff |= (V.S[q] != V.Sp[q]) ? 1 : 0;
+    for (int q = threadIdx.x; q < nc; q += kMbThreads) s.ucoef[q] = V.bc[q] + mu * V.gc[q];
+    same = __syncthreads_or(diff) ? 0 : 1;
+    // fit at the proposal, A_{S+} beta+ + A_C bcp
+    double a = 0.0;
+    for (int e0 = 0; e0 < k; e0 += kMbChunk) {
+      const int ne = min(kMbChunk, k - e0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < ne; e += kMbThreads) {
+        s.col[e] = cp * Q.kmax + e0 + e;
+        s.coef[e] = V.betap[e0 + e];
+      }
+      __syncthreads();
+      a = acc_chunk(Xt, Q.n_pad, s, ne, ii, a);
+    }
+    a = acc_unpen(Q.U, Q.n, s.ucoef, nc, ii, a);
+    fit = combine_waves(a, s);
+  }
+  double msum = ys[0];
+  if (kCheck)
+    for (int q = 0; q < nc; ++q) msum -= s.ucoef[q] * ys[1 + q];
+  const double m = msum / (double)Q.sv[t].nT;
+  const double ri = ok ? V.y[ii] - fit : 0.0;
+  const double rci = ok ? ri - m : 0.0;
+  if (w == 0 && i < Q.n_pad) {
+    V.r[i] = ri;
+    V.rc[i] = rci;
+  }
+
+  double ad2 = 0.0, dd = 0.0;
+  if (kCheck && !same) {
+    double dd_t = 0.0, a = 0.0;
+    for (int e0 = 0; e0 < 2 * k; e0 += kMbChunk) {
+      const int ne = min(kMbChunk, 2 * k - e0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < ne; e += kMbThreads) {
+        const int q = e0 + e;
+        int col;
+        double d;
+        if (q < k) {
+          col = cp * Q.kmax + q;
+          d = V.betap[q] - V.beta[V.Sp[q]];
+        } else {
+          const int64_t j = V.S[q - k];
+          const bool kept = in_sorted(V.Sp, k, j);
+          col = kept ? -1 : cs * Q.kmax + (q - k);
+          d = kept ? 0.0 : 0.0 - V.beta[j];
+        }
+        s.col[e] = col;
+        s.coef[e] = d;
+        dd_t += d * d;
+      }
+      __syncthreads();
+      a = acc_chunk(Xt, Q.n_pad, s, ne, ii, a);
+    }
+    for (int q = threadIdx.x; q < nc; q += kMbThreads) {
+      const double d = s.ucoef[q] - V.bc[q];
+      s.dcoef[q] = d;
+      dd_t += d * d;
+    }
+    __syncthreads();
+    a = acc_unpen(Q.U, Q.n, s.dcoef, nc, ii, a);
+    const double x = combine_waves(a, s);
+    ad2 = ok ? x * x : 0.0;
+    if (b == 0) dd = bsum(dd_t, s);  // workgroup-uniform branch
+  }
+
+  if (w == 0) {
+    double* P = Q.part + ((int64_t)t * Q.nb + b) * Q.pst;
+    const double rr = wsum(ri * ri), R = wsum(rci), sa = wsum(ad2);
+    if (lane == 0) {
+      P[0] = rr;
+      P[1] = R;
+      P[2] = sa;
+      P[3] = dd;
+      P[4] = (double)same;
+    }
+    for (int q = 0; q < nc; ++q) {
+      const double gq = wsum(ucol(Q.U, Q.n, q, ii) * ri);
+      if (lane == 0) P[5 + q] = gq;
+    }
+  }
+}
+
+// The solve's state from the partial sums of k_residual (grid T). kCheck: the backtracking decision
+// (taken when the support is unchanged or mu < omega; otherwise a halving is needed, and with the
+// budget spent the solve stops, stalled, keeping beta) and bcp. For a taken proposal (and at the
+// start): loss 1/2 ||r||^2 (eq. leastsquaresloss) into the trace (entry iter + 1, or 0), gc = A_C^T r
+// and R for the gradient pass.
+template <bool kCheck>
+__global__ __launch_bounds__(kMbThreads) void k_decide(SolveSet Q, int32_t phase, double c, int32_t max_backtrack) {
+  const int t = blockIdx.x;
+  if (!fs_selected(Q.fs + t, kCheck ? phase : kPhaseInit)) return;
+  __shared__ Stage s;
+  const View V = view(Q, t);
+  FitState* fs = V.fs;
+  const double* P0 = Q.part + (int64_t)t * Q.nb * Q.pst;
+  const int nc = V.nc;
+  if (kCheck) {
+    const double mu = fs->mu;
+    const int same = P0[4] != 0.0 ? 1 : 0;
+    double omega = 0.0;
+    int accept = 1;
+    if (!same) {
+      const double sa = sum_partials(P0, Q.nb, Q.pst, 2, s);
+      omega = (1.0 - c) * P0[3] / sa;
+      accept = mu < omega ? 1 : 0;
+    }
+    for (int q = threadIdx.x; q < nc; q += kMbThreads) V.bcp[q] = V.bc[q] + mu * V.gc[q];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      fs->same = same;
+      fs->omega = omega;
+      fs->accept = accept;
+      fs->go = accept;
+      fs->need_bt = accept ? 0 : 1;
+      if (!accept && fs->nbt >= max_backtrack) {
+        fs->need_bt = 0;
+        fs->active = 0;
+        fs->status = IHT_STALLED;
+      }
+    }
+    if (!accept) return;
+  }
+  const double loss = 0.5 * sum_partials(P0, Q.nb, Q.pst, 0, s);
+  const double R = sum_partials(P0, Q.nb, Q.pst, 1, s);
+  for (int q = 0; q < nc; ++q) {
+    const double gq = sum_partials(P0, Q.nb, Q.pst, 5 + q, s);
+    if (threadIdx.x == 0) V.gc[q] = gq;
+  }
   if (threadIdx.x == 0) {
-    FitState* fs = V.fs;
+    V.trace[kCheck ? fs->iter + 1 : 0] = loss;
+    fs->loss = loss;
+    fs->Rsum = R;
+  }
+}
+
+// Partial sums of the step-size denominator ||A_{S u C} g_{S u C}||^2 ("IHT step sizes", normalised
+// form) over each workgroup's subjects, on S (mode 0, first iteration, every active solve) or on S+
+// (mode 1, the solves whose proposal was taken). In mode 1 the first workgroup also commits the
+// proposal: the convergence test (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf); with
+// S+ = S the union of the supports is S itself, so the norms run over S+ and C), then beta <- beta+,
+// S <- S+, bc <- bcp. The control state changes in k_mu.
+__global__ __launch_bounds__(kMbThreads) void k_commit_den(SolveSet Q, int32_t mode, double tol) {
+  const int t = blockIdx.y, b = blockIdx.x;
+  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseActive : kPhaseGo)) return;
+  __shared__ Stage s;
+  const View V = view(Q, t);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)b * kSubjBlock + lane;
+  const bool in_n = i < Q.n;
+  const int64_t ii = in_n ? i : 0;
+  const bool ok = in_n && V.mask[ii] != 0.0;
+  const int k = V.k, nc = V.nc;
+  const double* Xt = Q.X + (int64_t)t * 2 * Q.kmax * Q.n_pad;
+  const int64_t* Sn = mode ? V.Sp : V.S;
+  const int cn = mode ? 1 - V.fs->xcur : V.fs->xcur;
+
+  for (int q = threadIdx.x; q < nc; q += kMbThreads) s.ucoef[q] = V.gc[q];
+  double a = 0.0;
+  for (int e0 = 0; e0 < k; e0 += kMbChunk) {
+    const int ne = min(kMbChunk, k - e0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ne; e += kMbThreads) {
+      s.col[e] = cn * Q.kmax + e0 + e;
+      s.coef[e] = V.g[Sn[e0 + e]];
+    }
+    __syncthreads();
+    a = acc_chunk(Xt, Q.n_pad, s, ne, ii, a);
+  }
+  a = acc_unpen(Q.U, Q.n, s.ucoef, nc, ii, a);
+  const double x = combine_waves(a, s);
+  if (w == 0) {
+    const double dd = wsum(ok ? x * x : 0.0);
+    if (lane == 0) Q.pmu[(int64_t)t * Q.nb + b] = dd;
+  }
+  if (mode == 0 || b != 0) return;
+
+  // commit (first workgroup; the others read neither beta, S nor bc)
+  FitState* fs = V.fs;
+  int diff = 0;
+  double dmax = 0.0, bmx = 0.0;
+  for (int q = threadIdx.x; q < k; q += kMbThreads) {
+    diff |= (V.S[q] != V.Sp[q]) ? 1 : 0;
+    dmax = fmax(dmax, fabs(V.betap[q] - V.beta[V.Sp[q]]));
+    bmx = fmax(bmx, fabs(V.betap[q]));
+  }
+  for (int q = threadIdx.x; q < nc; q += kMbThreads) {
+    dmax = fmax(dmax, fabs(V.bcp[q] - V.bc[q]));
+    bmx = fmax(bmx, fabs(V.bcp[q]));
+  }
+  const int same = __syncthreads_or(diff) ? 0 : 1;
+  dmax = bmax(dmax, s);
+  bmx = bmax(bmx, s);
+  for (int q = threadIdx.x; q < k; q += kMbThreads) V.beta[V.S[q]] = 0.0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < k; q += kMbThreads) {
+    V.beta[V.Sp[q]] = V.betap[q];
+    V.S[q] = V.Sp[q];
+  }
+  for (int q = threadIdx.x; q < nc; q += kMbThreads) V.bc[q] = V.bcp[q];
+  if (threadIdx.x == 0) {
+    fs->same = same;
+    fs->dmax = dmax;
+    fs->bmax = bmx;
+    fs->conv = same && dmax <= tol * fmax(1.0, bmx);
+  }
+}
+
+// Control state after k_commit_den (grid T). Mode 1: the committed solves count one more iteration,
+// their column caches trade roles (the proposal's cache now holds the columns of S), and they stop
+// when converged or at max_iter. Then the step size mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2 of
+// those still iterating; a zero denominator means the gradient vanishes on S u C: nothing can move,
+// the solve ends there (converged).
+__global__ __launch_bounds__(kMbThreads) void k_mu(SolveSet Q, int32_t mode, int32_t max_iter) {
+  const int t = blockIdx.x;
+  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseActive : kPhaseGo)) return;
+  __shared__ Stage s;
+  const View V = view(Q, t);
+  FitState* fs = V.fs;
+  if (mode == 1) {
+    __syncthreads();  // every thread has read the selection flags
+    if (threadIdx.x == 0) {
+      fs->iter += 1;
+      fs->go = 0;
+      fs->xcur ^= 1;
+      if (fs->conv) {
+        fs->active = 0;
+        fs->status = IHT_OK;
+      } else if (fs->iter >= max_iter) {
+        fs->active = 0;
+        fs->status = IHT_NOT_CONVERGED;
+      }
+      s.flag = fs->active;
+    }
+    __syncthreads();
+    if (!s.flag) return;
+  }
+  const double den = sum_partials(Q.pmu + (int64_t)t * Q.nb, Q.nb, 1, 0, s);
+  double nm = 0.0;
+  for (int q = threadIdx.x; q < V.k; q += kMbThreads) {
+    const double gq = V.g[V.S[q]];
+    nm += gq * gq;
+  }
+  for (int q = threadIdx.x; q < V.nc; q += kMbThreads) nm += V.gc[q] * V.gc[q];
+  const double num = bsum(nm, s);
+  if (threadIdx.x == 0) {
     fs->num = num;
     fs->den = den;
     fs->nbt = 0;
@@ -326,207 +634,6 @@ __device__ void blk_mu(const SolveSet& Q, const View& V, double* vec, double* sh
       fs->den_zero = 0;
       fs->mu = num / den;
     }
-  }
-  __syncthreads();
-}
-
-// Support comparison, unpenalised proposal bcp = bc + mu gc and, when the support moved,
-// omega = (1-c)||Delta||^2 / ||A Delta||^2 over S u S+ u C. The proposal is taken when the support is
-// unchanged or mu < omega; otherwise the solve needs a halving, and with the budget spent it stops
-// (stalled) keeping beta. Returns the accept flag (block-uniform).
-__device__ int blk_bt_check(const SolveSet& Q, const View& V, double c, int32_t max_backtrack, double* sh) {
-  __shared__ double dcl[kMaxUnpenalized];
-  __shared__ int same_s, nu_s, acc_s;
-  __shared__ double dd_s;
-  const int k = V.k;
-  const double mu = V.fs->mu;
-  if (threadIdx.x == 0) {
-    int same = 1;
-    for (int q = 0; q < k; ++q)
-      if (V.S[q] != V.Sp[q]) same = 0;
-    same_s = same;
-    double dd = 0.0;
-    int nu = 0;
-    if (!same) {
-      // merge S and S+ ascending; uidx: q (column q of the S cache) or -(q+1) (column q of S+)
-      int a = 0, b = 0;
-      while (a < k || b < k) {
-        if (b >= k || (a < k && V.S[a] < V.Sp[b])) {
-          const double d = 0.0 - V.beta[V.S[a]];
-          V.uidx[nu] = a;
-          V.udel[nu++] = d;
-          dd += d * d;
-          ++a;
-        } else if (a >= k || V.Sp[b] < V.S[a]) {
-          const double d = V.betap[b] - 0.0;
-          V.uidx[nu] = -(b + 1);
-          V.udel[nu++] = d;
-          dd += d * d;
-          ++b;
-        } else {
-          const double d = V.betap[b] - V.beta[V.S[a]];
-          V.uidx[nu] = -(b + 1);
-          V.udel[nu++] = d;
-          dd += d * d;
-          ++a;
-          ++b;
-        }
-      }
-    }
-    for (int q = 0; q < V.nc; ++q) {
-      const double np = V.bc[q] + mu * V.gc[q];
-      V.bcp[q] = np;
-      const double d = np - V.bc[q];
-      dcl[q] = d;
-      dd += d * d;
-    }
-    nu_s = nu;
-    dd_s = dd;
-  }
-  __syncthreads();
-  double omega = 0.0;
-  if (!same_s) {
-    const int nu = nu_s;
-    double sa = 0.0;
-    for (int64_t i0 = threadIdx.x; i0 < Q.n; i0 += (int64_t)kSubjUnroll * kThreads) {
-      int64_t ii[kSubjUnroll];
-      bool ok[kSubjUnroll];
-      double sm[kSubjUnroll];
-      subj_block(i0, Q.n, V.mask, ii, ok);
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w) sm[w] = 0.0;
-      for (int q = 0; q < nu; ++q) {
-        const int src = V.uidx[q];
-        const double* col = (src >= 0) ? V.Xs + (int64_t)src * Q.n_pad : V.Xp + (int64_t)(-src - 1) * Q.n_pad;
-        const double dq = V.udel[q];
-#pragma unroll
-        for (int w = 0; w < kSubjUnroll; ++w) sm[w] += col[ii[w]] * dq;
-      }
-      for (int cc = 0; cc < Q.U.cz; ++cc) {
-#pragma unroll
-        for (int w = 0; w < kSubjUnroll; ++w) sm[w] += (double)Q.U.Z[(int64_t)cc * Q.n + ii[w]] * dcl[cc];
-      }
-      if (Q.U.icpt) {
-#pragma unroll
-        for (int w = 0; w < kSubjUnroll; ++w) sm[w] += 1.0 * dcl[Q.U.cz];
-      }
-#pragma unroll
-      for (int w = 0; w < kSubjUnroll; ++w)
-        if (ok[w]) sa += sm[w] * sm[w];
-    }
-    const double dA = ssum(sa, sh);
-    omega = (1.0 - c) * dd_s / dA;
-  }
-  if (threadIdx.x == 0) {
-    FitState* fs = V.fs;
-    const int accept = same_s ? 1 : (mu < omega ? 1 : 0);
-    fs->same = same_s;
-    fs->omega = omega;
-    fs->accept = accept;
-    fs->go = accept;
-    fs->need_bt = accept ? 0 : 1;
-    if (!accept && fs->nbt >= max_backtrack) {
-      fs->need_bt = 0;
-      fs->active = 0;
-      fs->status = IHT_STALLED;
-    }
-    acc_s = accept;
-  }
-  __syncthreads();
-  return acc_s;
-}
-
-// Convergence (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf); with S+ = S the union of
-// the supports is S itself, so the norms run over S+ and C), then beta <- beta+, S <- S+, the column
-// caches trade roles and one more iteration is counted. Returns 1 if the solve is still iterating.
-__device__ int blk_commit(const SolveSet& Q, const View& V, double tol, int32_t max_iter, double* sh) {
-  __shared__ int same_s, act_s;
-  if (threadIdx.x == 0) same_s = 1;
-  __syncthreads();
-  double dmax = 0.0, bmax = 0.0;
-  for (int q = threadIdx.x; q < V.k; q += kThreads) {
-    if (V.S[q] != V.Sp[q]) atomicAnd(&same_s, 0);
-    dmax = fmax(dmax, fabs(V.betap[q] - V.beta[V.Sp[q]]));
-    bmax = fmax(bmax, fabs(V.betap[q]));
-  }
-  for (int q = threadIdx.x; q < V.nc; q += kThreads) {
-    dmax = fmax(dmax, fabs(V.bcp[q] - V.bc[q]));
-    bmax = fmax(bmax, fabs(V.bcp[q]));
-  }
-  dmax = smax(dmax, sh);
-  bmax = smax(bmax, sh);
-  const int same = same_s;
-  const int conv = same && dmax <= tol * fmax(1.0, bmax);
-  __syncthreads();
-  for (int q = threadIdx.x; q < V.k; q += kThreads) V.beta[V.S[q]] = 0.0;
-  __syncthreads();
-  for (int q = threadIdx.x; q < V.k; q += kThreads) {
-    V.beta[V.Sp[q]] = V.betap[q];
-    V.S[q] = V.Sp[q];
-  }
-  for (int q = threadIdx.x; q < V.nc; q += kThreads) V.bc[q] = V.bcp[q];
-  if (threadIdx.x == 0) {
-    FitState* fs = V.fs;
-    fs->conv = conv;
-    fs->same = same;
-    fs->dmax = dmax;
-    fs->bmax = bmax;
-    fs->iter += 1;
-    fs->go = 0;
-    fs->xcur ^= 1;  // the proposal's cache now holds the columns of S
-    if (conv) {
-      fs->active = 0;
-      fs->status = IHT_OK;
-    } else if (fs->iter >= max_iter) {
-      fs->active = 0;
-      fs->status = IHT_NOT_CONVERGED;
-    }
-    act_s = fs->active;
-  }
-  __syncthreads();
-  return act_s;
-}
-
-// ---------------------------------------------------------------------------- step kernels
-
-// Initial residual (at beta = 0) of the solves with finite inputs.
-__global__ __launch_bounds__(kThreads) void k_residual0(SolveSet Q) {
-  if (!fs_selected(Q.fs + blockIdx.x, kPhaseInit)) return;
-  __shared__ double sh[40];
-  __shared__ double vec[kTopkMaxK];
-  const View V = view(Q, blockIdx.x);
-  blk_residual(Q, V, 1, vec, sh);
-}
-
-// A proposal (S+, beta+ from the projection, its columns decoded) of the solves in `phase`: the
-// backtracking test and, when the proposal is taken, its residual, loss and centred residual for
-// the gradient pass.
-__global__ __launch_bounds__(kThreads) void k_check_residual(SolveSet Q, int32_t phase, double c, int32_t max_backtrack) {
-  if (!fs_selected(Q.fs + blockIdx.x, phase)) return;
-  __shared__ double sh[40];
-  __shared__ double vec[kTopkMaxK];
-  const View V = view(Q, blockIdx.x);
-  if (blk_bt_check(Q, V, c, max_backtrack, sh)) blk_residual(Q, V, 0, vec, sh);
-}
-
-// Commit of the accepted proposals (mode 1), then the step size of the next iteration for the
-// solves that committed and still iterate; mode 0: step size of every active solve (first
-// iteration).
-__global__ __launch_bounds__(kThreads) void k_commit_mu(SolveSet Q, int32_t mode, double tol, int32_t max_iter) {
-  __shared__ double sh[40];
-  __shared__ double vec[kTopkMaxK];
-  const FitState* fs = Q.fs + blockIdx.x;
-  if (mode == 0) {
-    if (!fs_selected(fs, kPhaseActive)) return;
-    const View V = view(Q, blockIdx.x);
-    blk_mu(Q, V, vec, sh);
-    return;
-  }
-  if (!fs_selected(fs, kPhaseGo)) return;
-  const View V = view(Q, blockIdx.x);
-  if (blk_commit(Q, V, tol, max_iter, sh)) {
-    const View V2 = view(Q, blockIdx.x);  // the column caches have traded roles
-    blk_mu(Q, V2, vec, sh);
   }
 }
 
@@ -696,7 +803,10 @@ hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st) {
 }
 
 hipError_t solve_residual0(const SolveSet& Q, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual0, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q);
+  hipLaunchKernelGGL(k_residual<false>, dim3((unsigned)Q.nb, (unsigned)Q.T), dim3(kMbThreads), 0, st, Q, kPhaseInit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_decide<false>, dim3((unsigned)Q.T), dim3(kMbThreads), 0, st, Q, kPhaseInit, 0.0, 0);
   return hipGetLastError();
 }
 
@@ -707,12 +817,18 @@ hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, 
 }
 
 hipError_t solve_check_residual(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st) {
-  hipLaunchKernelGGL(k_check_residual, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, phase, c, max_backtrack);
+  hipLaunchKernelGGL(k_residual<true>, dim3((unsigned)Q.nb, (unsigned)Q.T), dim3(kMbThreads), 0, st, Q, phase);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_decide<true>, dim3((unsigned)Q.T), dim3(kMbThreads), 0, st, Q, phase, c, max_backtrack);
   return hipGetLastError();
 }
 
 hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t max_iter, hipStream_t st) {
-  hipLaunchKernelGGL(k_commit_mu, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, mode, tol, max_iter);
+  hipLaunchKernelGGL(k_commit_den, dim3((unsigned)Q.nb, (unsigned)Q.T), dim3(kMbThreads), 0, st, Q, mode, tol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mu, dim3((unsigned)Q.T), dim3(kMbThreads), 0, st, Q, mode, max_iter);
   return hipGetLastError();
 }
 
