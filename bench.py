@@ -167,12 +167,13 @@ def main():
         "hbm_frac_whole_solve": round(value / HBM_PEAK_GBS, 4),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_pass (gradient pass X_st^T r)",
+            "kernel": "one iht_gradient call, g = X_st^T r: k_center + k_pass + k_pass_finalize",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": pass_traffic() if (prec == iht.FP64 and cfg == "c2") else None,
+            "traffic_unit": "HBM bytes per call (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launch_us": round(pass_ms * 1e3, 2),
             "algorithmic_bytes_per_launch": pass_bytes,
         },
