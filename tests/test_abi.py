@@ -58,6 +58,10 @@ def test_library_loads_and_answers_host_only_calls(lib_path):
     buf = (ctypes.c_uint8 * 30)()
     rc = L.iht_geno_create(ctypes.cast(buf, ctypes.c_void_p), 10, 10, 2, 0, None, ctypes.byref(h))
     assert rc == iht.EINVAL and b"row_bytes" in L.iht_last_error()
+    # size limits: a tile's packed bytes stay addressable with 32-bit offsets
+    for n, p in ((10, (1 << 28) - 8192 + 1), ((1 << 24) + 1, 10), (0, 10), (10, 0)):
+        rc = L.iht_geno_create(ctypes.cast(buf, ctypes.c_void_p), n, p, 3, 0, None, ctypes.byref(h))
+        assert rc == iht.EINVAL and b"out of range" in L.iht_last_error(), (n, p)
     rc = L.iht_project(None, 10, 3, None, None, None)
     assert rc == iht.EINVAL
     assert L.iht_fit(None, None, None, None, 0, 1, 3, None, None, None, None, None, None, None) == iht.EINVAL
