@@ -147,6 +147,19 @@ int iht_gradient_batch(const iht_geno *g, const iht_stats *const *stats, int32_t
 int iht_project(const double *w, int64_t p, int32_t k, int64_t *support, double *w_out, void *stream);
 
 /*
+ * The same projection, warm-started (the IHT loop of Methods, eq. ihta, projects beta + mu g whose
+ * support moves little between iterations): `hint` holds k distinct indices (e.g. the previous
+ * support), so the smallest |w| over them bounds the k-th largest from below and one filtering pass
+ * over w keeps the entries at or above it; the k largest are then selected among those. The result
+ * is the one of iht_project for any valid hint; the hint only changes the cost.
+ *   hint     device [k] int64, distinct indices in [0, p) (an index outside [0, p) gives no bound).
+ * Used for k <= 512; larger k take iht_project's path. Errors: as iht_project, and IHT_EINVAL if the
+ * hint repeats an index so that fewer than k entries reach its bound.
+ */
+int iht_project_hint(const double *w, int64_t p, int32_t k, const int64_t *hint, int64_t *support, double *w_out,
+                     void *stream);
+
+/*
  * Full IHT solve (Methods, eq. ihta with the normalised step and the omega backtracking rule of
  * "IHT step sizes"): beta <- P_Sk[beta + mu A^T(y - A beta)], beta^0 = 0,
  * mu = ||g_{S u C}||^2 / ||A_{S u C} g_{S u C}||^2 with C the unpenalised columns; when the support

@@ -339,13 +339,14 @@ static TopkArea* project_area() {
   return areas[dev];
 }
 
-int iht_project(const double* w, int64_t p, int32_t k, int64_t* support, double* w_out, void* stream) {
-  if (!w || !support) return fail(IHT_EINVAL, "iht_project: NULL argument");
-  if (p < 1 || p > (int64_t(1) << 31) - 1) return fail(IHT_EINVAL, "iht_project: p out of range");
-  if (k < 1 || k > p || k > IHT_MAX_K) return fail(IHT_EINVAL, "iht_project: k out of range");
+static int project(const char* who, const double* w, int64_t p, int32_t k, const int64_t* hint, int64_t* support,
+                   double* w_out, void* stream) {
+  if (!w || !support) return fail(IHT_EINVAL, std::string(who) + ": NULL argument");
+  if (p < 1 || p > (int64_t(1) << 31) - 1) return fail(IHT_EINVAL, std::string(who) + ": p out of range");
+  if (k < 1 || k > p || k > IHT_MAX_K) return fail(IHT_EINVAL, std::string(who) + ": k out of range");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   TopkArea* Ap = project_area();
-  if (!Ap) return fail(IHT_ENOMEM, "iht_project: work area");
+  if (!Ap) return fail(IHT_ENOMEM, std::string(who) + ": work area");
   TopkArea& A = *Ap;
   if (int rc = A.ensure(p, 1, st)) return rc;
   HIPCHK(launch_topk_clear_errors(A.small.as<uint32_t>(), 1, st));
@@ -363,18 +364,32 @@ int iht_project(const double* w, int64_t p, int32_t k, int64_t* support, double*
   J.cand_key = A.cand_key();
   J.cand_idx = A.cand_idx();
   J.cap = A.cap;
+  J.prev = hint;
+  J.ldprev = k;
   HIPCHK(launch_topk(J, p, 1, st));
   if (w_out) {
     HIPCHK(launch_fill(w_out, p, 0.0, st));
-    HIPCHK(launch_scatter(support, vals.as<double>(), k, w_out, st));
+    HIPCHK(launch_scatter(support, vals.as<double>(), k, p, w_out, st));
   }
   uint32_t err = 0;
   HIPCHK(hipMemcpyAsync(&err, A.small.as<uint32_t>() + kTopkErrorWord, 4, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (err & 1u) return fail(IHT_ENONFINITE, "iht_project: non-finite entry in w");
-  if (err & 2u) return fail(IHT_EDEVICE, "iht_project: internal top-k count mismatch");
+  if (err & 1u) return fail(IHT_ENONFINITE, std::string(who) + ": non-finite entry in w");
+  if (err & 4u) return fail(IHT_EINVAL, std::string(who) + ": hint does not hold k distinct indices");
+  if (err & 2u) return fail(IHT_EDEVICE, std::string(who) + ": internal top-k count mismatch");
   return IHT_OK;
 }
+
+int iht_project(const double* w, int64_t p, int32_t k, int64_t* support, double* w_out, void* stream) {
+  return project("iht_project", w, p, k, nullptr, support, w_out, stream);
+}
+
+int iht_project_hint(const double* w, int64_t p, int32_t k, const int64_t* hint, int64_t* support, double* w_out,
+                     void* stream) {
+  if (!hint) return fail(IHT_EINVAL, "iht_project_hint: NULL argument");
+  return project("iht_project_hint", w, p, k, hint, support, w_out, stream);
+}
+
 
 }  // extern "C"
 
@@ -538,6 +553,8 @@ int run_fit(const FitArgs& A) {
     J.phase = phase;
     J.out = Q.Sp;
     J.vals = Q.betap;
+    J.prev = Q.S;  // the current support bounds the new k-th largest |w| from below
+    J.ldprev = kmax;
     HIPCHK(launch_topk(J, L.p, T, st));
     HIPCHK(solve_decode(tiled, Q, 1, phase, st));
     HIPCHK(solve_check_residual(Q, phase, o.c, o.max_backtrack, st));
@@ -569,6 +586,7 @@ int run_fit(const FitArgs& A) {
   J.phase = kPhaseInit;
   J.out = Q.S;
   J.vals = nullptr;
+  J.prev = nullptr;
   HIPCHK(launch_topk(J, L.p, T, st));
   HIPCHK(solve_decode(tiled, Q, 0, kPhaseInit, st));
   HIPCHK(solve_commit_mu(Q, 0, tol_main, o.max_iter, st));
@@ -602,7 +620,8 @@ int run_fit(const FitArgs& A) {
   if (int rc = read_states()) return rc;
   int worst = IHT_OK;
   for (int32_t t = 0; t < T; ++t) {
-    if (terr[t] && !h[t].nonfinite) return fail(IHT_EDEVICE, "internal top-k error");
+    if (terr[t] && !h[t].nonfinite)
+      return fail(IHT_EDEVICE, "internal top-k error (solve " + std::to_string(t) + ", flags " + std::to_string(terr[t]) + ")");
     A.n_iter[t] = h[t].iter;
     A.status[t] = h[t].status;
     if (h[t].status < 0)

@@ -784,14 +784,18 @@ constexpr int kSelBins = 1 << kSelBits;  // 2048: two bins per thread of a 1024-
 constexpr int kLocalMaxK = 512;
 constexpr int kLocalEPT = 8;   // entries per thread in pass 1: chunks of 8192
 constexpr int kFinalEPT = 8;   // candidates per thread in pass 2: up to 8192 per row
+constexpr int64_t kSmallChunk = 256 * kLocalEPT;   // pass-1 chunk of a 256-thread block
+constexpr int64_t kLargeChunk = 1024 * kLocalEPT;  // pass-1 chunk of a 1024-thread block
 typedef unsigned __int128 u128;
 
 __device__ __forceinline__ u128 sel_comp(uint64_t key, int32_t idx) {
   return ((u128)key << 32) | (u128)(0xFFFFFFFFu - (uint32_t)idx);
 }
 
-// Sum of v over the threads >= tid (1024-thread block; sh holds 16 words).
+// Sum of v over the threads >= tid (THREADS-thread block; sh holds THREADS / 64 words).
+template <int THREADS>
 __device__ __forceinline__ uint32_t block_suffix_sum(uint32_t v, uint32_t* sh) {
+  constexpr int W = THREADS / 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t x = v;
 #pragma unroll
@@ -802,7 +806,7 @@ __device__ __forceinline__ uint32_t block_suffix_sum(uint32_t v, uint32_t* sh) {
   if (lane == 0) sh[w] = x;
   __syncthreads();
   uint32_t add = 0;
-  for (int w2 = w + 1; w2 < 16; ++w2) add += sh[w2];
+  for (int w2 = w + 1; w2 < W; ++w2) add += sh[w2];
   __syncthreads();
   return x + add;
 }
@@ -810,11 +814,13 @@ __device__ __forceinline__ uint32_t block_suffix_sum(uint32_t v, uint32_t* sh) {
 // Bit e of the result: entry e of this thread is among the k first valid entries of the block in
 // the total order; idx_of(e) gives the entry's index (-1: no entry). Radix select on the composite,
 // 11 bits at a time from the top (while the digit lies in the key, 64-bit arithmetic only),
-// stopping as soon as the bucket holding the k-th entry is taken whole. Needs 1 <= k <= number of
-// valid entries, E <= 32.
-template <int E, class IdxOf>
+// stopping as soon as the bucket holding the k-th entry is taken whole. Thread t owns the
+// kSelBins / THREADS consecutive bins from BPT t. Needs 1 <= k <= number of valid entries, E <= 32.
+template <int THREADS, int E, class IdxOf>
 __device__ uint32_t block_select(const uint64_t (&key)[E], IdxOf idx_of, uint32_t k, uint32_t* hist, uint32_t* sh) {
   static_assert(E <= 32, "selection mask");
+  constexpr int BPT = kSelBins / THREADS;  // 2 (1024 threads) or 8 (256 threads)
+  constexpr int SH = THREADS / 64;         // sh[SH .. SH + 2] carry the chosen bin
   const int tid = threadIdx.x;
   u128 prefix = 0;
   uint32_t need = k;
@@ -823,8 +829,8 @@ __device__ uint32_t block_select(const uint64_t (&key)[E], IdxOf idx_of, uint32_
     const int ns = s > kSelBits ? s - kSelBits : 0;
     const int nbits = s - ns;
     const uint32_t dmask = (1u << nbits) - 1u;
-    hist[2 * tid] = 0u;
-    hist[2 * tid + 1] = 0u;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) hist[BPT * tid + i] = 0u;
     __syncthreads();
     if (ns >= 32) {  // digit and prefix inside the key
       const uint64_t pk = (uint64_t)prefix;
@@ -844,9 +850,170 @@ __device__ uint32_t block_select(const uint64_t (&key)[E], IdxOf idx_of, uint32_
       }
     }
     __syncthreads();
+    uint32_t h[BPT], tot = 0;
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+      h[i] = hist[BPT * tid + i];
+      tot += h[i];
+    }
+    const uint32_t incl = block_suffix_sum<THREADS>(tot, sh);  // entries in bins >= BPT tid
+    const uint32_t excl = incl - tot;                          // entries in bins >= BPT (tid + 1)
+    if (excl < need && incl >= need) {
+      uint32_t acc = excl;
+#pragma unroll
+      for (int i = BPT - 1; i >= 0; --i) {
+        if (acc < need && acc + h[i] >= need) {
+          sh[SH] = (uint32_t)(BPT * tid + i);
+          sh[SH + 1] = acc;
+          sh[SH + 2] = h[i];
+        }
+        acc += h[i];
+      }
+    }
+    __syncthreads();
+    const uint32_t b = sh[SH], above = sh[SH + 1], cnt = sh[SH + 2];
+    prefix = (prefix << nbits) | (u128)b;
+    need -= above;
+    s = ns;
+    __syncthreads();  // everyone has read the chosen bin
+    if (cnt == need) break;
+  }
+  uint32_t take = 0u;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int32_t ix = idx_of(e);
+    if (ix >= 0 && (sel_comp(key[e], ix) >> s) >= prefix) take |= 1u << e;
+  }
+  return take;
+}
+
+template <int THREADS, int EPT>
+__global__ __launch_bounds__(THREADS) void k_topk_local(TopkJob J, int64_t p) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.y, src)) return;
+  __shared__ uint32_t hist[kSelBins];
+  __shared__ uint32_t sh[32];
+  __shared__ uint32_t nout;
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * (THREADS * EPT);
+  auto idx_of = [&](int e) -> int32_t {
+    const int64_t j = base + (int64_t)e * THREADS + tid;
+    return j < p ? (int32_t)j : -1;
+  };
+  uint64_t key[EPT];
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int32_t j = idx_of(e);
+    const double w = j >= 0 ? src.at(j) : 0.0;
+    bad |= !isfinite(w);
+    key[e] = abs_key(w);
+  }
+  if (bad) atomicOr(&src.tw.state[3], 1u);
+  const int64_t nvalid = min((int64_t)(THREADS * EPT), p - base);
+  uint32_t take = 0u;
+  if (nvalid <= (int64_t)src.k) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (idx_of(e) >= 0) take |= 1u << e;
+  } else {
+    take = block_select<THREADS, EPT>(key, idx_of, (uint32_t)src.k, hist, sh);
+  }
+  if (tid == 0) nout = 0u;
+  __syncthreads();
+  uint64_t* ok = src.tw.cand_key + (int64_t)blockIdx.x * J.kmax;
+  int32_t* oi = src.tw.cand_idx + (int64_t)blockIdx.x * J.kmax;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    if (take & (1u << e)) {
+      const uint32_t pos = atomicAdd(&nout, 1u);  // < min(k, nvalid) <= kmax
+      ok[pos] = key[e];
+      oi[pos] = idx_of(e);
+    }
+  }
+  __syncthreads();
+  for (int q = (int)nout + tid; q < J.kmax; q += THREADS) oi[q] = -1;
+}
+
+// Pass 1 with a threshold (TopkJob::prev): the smallest key over the row's k distinct previous
+// indices is at most the k-th largest key, so every entry at or above it is a candidate (a superset
+// of the k first, ties included). Each wave appends its candidates to the row's list with one atomic add;
+// the order of the list does not matter to pass 2.
+__global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.y, src)) return;
+  __shared__ uint64_t shk[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t* prev = J.prev + (int64_t)blockIdx.y * J.ldprev;
+  // (64-bit keys compared as integers throughout: no min() overload that could convert them)
+  uint64_t tk = ~0ull;
+  for (int q = tid; q < src.k; q += 256) {
+    const int64_t h = prev[q];
+    const uint64_t kq = (h >= 0 && h < p) ? abs_key(src.at(h)) : (uint64_t)0;  // out of range: no bound
+    tk = kq < tk ? kq : tk;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(tk, off, 64);
+    tk = o < tk ? o : tk;
+  }
+  if (lane == 0) shk[w] = tk;
+  __syncthreads();
+  tk = shk[0];
+#pragma unroll
+  for (int i = 1; i < 4; ++i) tk = shk[i] < tk ? shk[i] : tk;
+  const int64_t base = (int64_t)blockIdx.x * kSmallChunk;
+  uint64_t key[kLocalEPT];
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e < kLocalEPT; ++e) {
+    const int64_t j = base + (int64_t)e * 256 + tid;
+    const double v = j < p ? src.at(j) : 0.0;
+    bad |= !isfinite(v);
+    key[e] = abs_key(v);
+  }
+  if (bad) atomicOr(&src.tw.state[3], 1u);
+#pragma unroll
+  for (int e = 0; e < kLocalEPT; ++e) {
+    const int64_t j = base + (int64_t)e * 256 + tid;
+    const bool in = j < p && key[e] >= tk;
+    const uint64_t m = __ballot(in);
+    if (m == 0ull) continue;
+    uint32_t at = 0u;
+    if (lane == __ffsll((long long)m) - 1) at = atomicAdd(&src.tw.counters[4], (uint32_t)__popcll(m));
+    at = __shfl(at, __ffsll((long long)m) - 1, 64);
+    const uint32_t pos = at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (in && (int64_t)pos < J.cap) {  // the count starts at 0 and cannot pass p <= cap
+      src.tw.cand_key[pos] = key[e];
+      src.tw.cand_idx[pos] = (int32_t)j;
+    }
+  }
+}
+
+// Radix select, by one block, of the k first of n candidates held in global memory (the same
+// composite order as block_select): on return the selected ones are those whose composite >> s is
+// >= prefix. Used when a filtered candidate list is too long for registers.
+__device__ void select_global(const uint64_t* __restrict__ keys, const int32_t* __restrict__ idx, int64_t n, uint32_t k,
+                              uint32_t* hist, uint32_t* sh, u128& prefix_out, int& s_out) {
+  const int tid = threadIdx.x;
+  u128 prefix = 0;
+  uint32_t need = k;
+  int s = 96;
+  while (s > 0) {
+    const int ns = s > kSelBits ? s - kSelBits : 0;
+    const int nbits = s - ns;
+    const uint32_t dmask = (1u << nbits) - 1u;
+    hist[2 * tid] = 0u;
+    hist[2 * tid + 1] = 0u;
+    __syncthreads();
+    for (int64_t q = tid; q < n; q += 1024) {
+      const u128 c = sel_comp(keys[q], idx[q]);
+      if ((c >> s) == prefix) atomicAdd(&hist[(uint32_t)(c >> ns) & dmask], 1u);
+    }
+    __syncthreads();
     const uint32_t h0 = hist[2 * tid], h1 = hist[2 * tid + 1];
-    const uint32_t incl = block_suffix_sum(h0 + h1, sh);  // entries in bins >= 2 tid
-    const uint32_t excl = incl - h0 - h1;                   // entries in bins >= 2 tid + 2
+    const uint32_t incl = block_suffix_sum<1024>(h0 + h1, sh);
+    const uint32_t excl = incl - h0 - h1;
     if (excl < need && incl >= need) {
       if (excl + h1 >= need) {
         sh[16] = 2u * tid + 1u;
@@ -863,66 +1030,15 @@ __device__ uint32_t block_select(const uint64_t (&key)[E], IdxOf idx_of, uint32_
     prefix = (prefix << nbits) | (u128)b;
     need -= above;
     s = ns;
-    __syncthreads();  // everyone has read sh[16..18]
+    __syncthreads();
     if (cnt == need) break;
   }
-  uint32_t take = 0u;
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int32_t ix = idx_of(e);
-    if (ix >= 0 && (sel_comp(key[e], ix) >> s) >= prefix) take |= 1u << e;
-  }
-  return take;
+  prefix_out = prefix;
+  s_out = s;
 }
 
-template <int EPT>
-__global__ __launch_bounds__(1024) void k_topk_local(TopkJob J, int64_t p) {
-  TopkRow src;
-  if (!topk_row(J, blockIdx.y, src)) return;
-  __shared__ uint32_t hist[kSelBins];
-  __shared__ uint32_t sh[32];
-  __shared__ uint32_t nout;
-  const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * (1024 * EPT);
-  auto idx_of = [&](int e) -> int32_t {
-    const int64_t j = base + (int64_t)e * 1024 + tid;
-    return j < p ? (int32_t)j : -1;
-  };
-  uint64_t key[EPT];
-  bool bad = false;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int32_t j = idx_of(e);
-    const double w = j >= 0 ? src.at(j) : 0.0;
-    bad |= !isfinite(w);
-    key[e] = abs_key(w);
-  }
-  if (bad) atomicOr(&src.tw.state[3], 1u);
-  const int64_t nvalid = min((int64_t)(1024 * EPT), p - base);
-  uint32_t take = 0u;
-  if (nvalid <= (int64_t)src.k) {
-#pragma unroll
-    for (int e = 0; e < EPT; ++e)
-      if (idx_of(e) >= 0) take |= 1u << e;
-  } else {
-    take = block_select<EPT>(key, idx_of, (uint32_t)src.k, hist, sh);
-  }
-  if (tid == 0) nout = 0u;
-  __syncthreads();
-  uint64_t* ok = src.tw.cand_key + (int64_t)blockIdx.x * J.kmax;
-  int32_t* oi = src.tw.cand_idx + (int64_t)blockIdx.x * J.kmax;
-#pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    if (take & (1u << e)) {
-      const uint32_t pos = atomicAdd(&nout, 1u);  // < min(k, nvalid) <= kmax
-      ok[pos] = key[e];
-      oi[pos] = idx_of(e);
-    }
-  }
-  __syncthreads();
-  for (int q = (int)nout + tid; q < J.kmax; q += 1024) oi[q] = -1;
-}
-
+// Pass 2, one block per row: the k first of the row's candidates (nb blocks x kmax slots, or the
+// filtered list), sorted by index.
 __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32_t nb) {
   TopkRow src;
   if (!topk_row(J, blockIdx.x, src)) return;
@@ -931,29 +1047,63 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
   __shared__ int32_t sel[kLocalMaxK];
   __shared__ uint32_t nsel;
   const int tid = threadIdx.x;
-  const int64_t total = (int64_t)nb * J.kmax;  // <= 1024 * kFinalEPT (checked at launch)
-  uint64_t key[kFinalEPT];
-  int32_t idx[kFinalEPT];
-#pragma unroll
-  for (int e = 0; e < kFinalEPT; ++e) {
-    const int64_t q = tid + (int64_t)e * 1024;
-    idx[e] = q < total ? src.tw.cand_idx[q] : -1;
-    key[e] = idx[e] >= 0 ? src.tw.cand_key[q] : 0;
-  }
   const int k = src.k;
-  const uint32_t take = block_select<kFinalEPT>(key, [&](int e) { return idx[e]; }, (uint32_t)k, hist, sh);
+  int64_t total = (int64_t)nb * J.kmax;  // <= 1024 * kFinalEPT (checked at launch)
+  if (J.prev) {
+    // the count was formed by device-scope atomics: take it (and reset it) with one, so that no
+    // cached copy of the word is read
+    if (tid == 0) {
+      const uint32_t c = atomicExch(&src.tw.counters[4], 0u);
+      nsel = c;
+      if ((int64_t)c < k) atomicOr(&src.tw.state[3], 4u);  // the bound came from repeated indices
+    }
+    __syncthreads();
+    total = min((int64_t)nsel, J.cap);
+    __syncthreads();  // every thread has read it before nsel is reused
+  }
   if (tid == 0) nsel = 0u;
   for (int q = tid; q < kLocalMaxK; q += 1024) sel[q] = 0;
   __syncthreads();
+  if (total <= 1024 * (int64_t)kFinalEPT) {
+    uint64_t key[kFinalEPT];
+    int32_t idx[kFinalEPT];
 #pragma unroll
-  for (int e = 0; e < kFinalEPT; ++e) {
-    if (take & (1u << e)) {
-      const uint32_t pos = atomicAdd(&nsel, 1u);
-      if (pos < (uint32_t)kLocalMaxK) sel[pos] = idx[e];
+    for (int e = 0; e < kFinalEPT; ++e) {
+      const int64_t q = tid + (int64_t)e * 1024;
+      idx[e] = q < total ? src.tw.cand_idx[q] : -1;
+      key[e] = idx[e] >= 0 ? src.tw.cand_key[q] : 0;
+    }
+    const uint32_t take = block_select<1024, kFinalEPT>(key, [&](int e) { return idx[e]; }, (uint32_t)k, hist, sh);
+#pragma unroll
+    for (int e = 0; e < kFinalEPT; ++e) {
+      if (take & (1u << e)) {
+        const uint32_t pos = atomicAdd(&nsel, 1u);
+        if (pos < (uint32_t)kLocalMaxK) sel[pos] = idx[e];
+      }
+    }
+  } else {
+    u128 prefix;
+    int s;
+    select_global(src.tw.cand_key, src.tw.cand_idx, total, (uint32_t)k, hist, sh, prefix, s);
+    for (int64_t q = tid; q < total; q += 1024) {
+      const int32_t ix = src.tw.cand_idx[q];
+      if ((sel_comp(src.tw.cand_key[q], ix) >> s) >= prefix) {
+        const uint32_t pos = atomicAdd(&nsel, 1u);
+        if (pos < (uint32_t)kLocalMaxK) sel[pos] = ix;
+      }
     }
   }
   __syncthreads();
-  if (tid == 0 && nsel != (uint32_t)k) atomicOr(&src.tw.state[3], 2u);
+  if (nsel != (uint32_t)k) {
+    // cannot happen for a valid job (flagged; the caller reports an error): the output still gets
+    // k valid indices, so that nothing downstream indexes with an unset entry
+    if (tid == 0) atomicOr(&src.tw.state[3], 2u);
+    for (int q = tid; q < k; q += 1024) {
+      src.out[q] = q;
+      if (src.vals) src.vals[q] = 0.0;
+    }
+    return;
+  }
   // the k selected indices, ascending (indices are distinct)
   for (int q = tid; q < k; q += 1024) {
     const int32_t x = sel[q];
@@ -975,7 +1125,10 @@ __global__ void k_zero_u32(uint32_t* __restrict__ x, int64_t n) {
 
 __global__ void k_topk_clear_errors(uint32_t* __restrict__ small, int32_t rows) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < rows) small[t * kTopkRowWords + kTopkErrorWord] = 0u;
+  if (t < rows) {  // words that kernels update with device-scope atomics are cleared with one
+    (void)atomicExch(&small[t * kTopkRowWords + kTopkErrorWord], 0u);
+    (void)atomicExch(&small[t * kTopkRowWords + kTopkBins0 + 4], 0u);  // filtered-candidate count
+  }
 }
 
 __global__ void k_fill(double* __restrict__ x, int64_t n, double val) {
@@ -983,10 +1136,13 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double val) {
   if (i < n) x[i] = val;
 }
 
-__global__ void k_scatter(const int64_t* __restrict__ idx, const double* __restrict__ vals, int32_t k,
+__global__ void k_scatter(const int64_t* __restrict__ idx, const double* __restrict__ vals, int32_t k, int64_t p,
                           double* __restrict__ out) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < k) out[idx[q]] = vals[q];
+  if (q < k) {
+    const int64_t j = idx[q];
+    if (j >= 0 && j < p) out[j] = vals[q];
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1109,14 +1265,30 @@ hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* 
 }
 
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st) {
-  // two-pass selection when every row's candidates fit pass 2
-  const int64_t chunk2 = 1024 * (int64_t)kLocalEPT;
-  const int64_t nb = (p + chunk2 - 1) / chunk2;
-  if (J.kmax <= kLocalMaxK && nb * J.kmax <= 1024 * (int64_t)kFinalEPT && nb * J.kmax <= J.cap) {
-    hipLaunchKernelGGL(k_topk_local<kLocalEPT>, dim3((unsigned)nb, (unsigned)rows), dim3(1024), 0, st, J, p);
+  // two-pass selection when every row's candidates fit pass 2: chunks of 2048 (256-thread blocks,
+  // enough of them to fill the chip) when they do, else of 8192
+  const int64_t cap2 = 1024 * (int64_t)kFinalEPT;
+  const int64_t nb_s = (p + kSmallChunk - 1) / kSmallChunk;
+  const int64_t nb_l = (p + kLargeChunk - 1) / kLargeChunk;
+  if (J.prev && J.kmax <= kLocalMaxK && J.cap >= p) {
+    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, J, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb);
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, 0);
+    return hipGetLastError();
+  }
+  if (J.kmax <= kLocalMaxK && nb_s * J.kmax <= cap2 && nb_s * J.kmax <= J.cap) {
+    hipLaunchKernelGGL((k_topk_local<256, kLocalEPT>), dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, J, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_s);
+    return hipGetLastError();
+  }
+  if (J.kmax <= kLocalMaxK && nb_l * J.kmax <= cap2 && nb_l * J.kmax <= J.cap) {
+    hipLaunchKernelGGL((k_topk_local<1024, kLocalEPT>), dim3((unsigned)nb_l, (unsigned)rows), dim3(1024), 0, st, J, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_l);
     return hipGetLastError();
   }
   // histogram path (large k or very long rows): about 2048 blocks over all rows, 4096 to 65536
@@ -1148,8 +1320,8 @@ hipError_t launch_fill(double* x, int64_t n, double val, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, idx, vals, k, out);
+hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, int64_t p, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, st, idx, vals, k, p, out);
   return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ __device__ __forceinline__ bool fs_selected(const FitState* fs, int32_t phase) {
 // them). Rows are laid out kTopkRowWords apart in one small buffer; candidates `cap` apart.
 struct TopkWork {
   uint32_t* hist;      // [kTopkBins0]
-  uint32_t* counters;  // [8]: 0 hist ticket, 1 collect ticket, 2 n_sel, 3 n_cand
+  uint32_t* counters;  // [8]: 0 hist ticket, 1 collect ticket, 2 n_sel, 3 n_cand, 4 filtered candidates
   uint32_t* state;     // [8]: bucket, n_above, n_eq, error (bit 0 non-finite, bit 1 count mismatch)
   int32_t* sel;        // [kTopkMaxK]
   uint64_t* cand_key;  // [cap]
@@ -92,6 +92,9 @@ constexpr int64_t kTopkErrorWord = kTopkBins0 + 8 + 3;  // state[3] of a row
 //   w = g_t                     (beta == NULL), or
 //   w = beta_t + mu_t g_t       (mu_t = fs[t].mu),
 // keeping k_t = ks ? ks[t] : k0 entries; rows whose FitState is outside `phase` are skipped.
+// With `prev` (k_t distinct indices per row, stride ldprev, e.g. the current support), the smallest
+// |w| over them bounds the k_t-th largest from below, and one filtering pass keeps the entries at or
+// above it as the candidates.
 struct TopkJob {
   const double* beta;
   const double* g;
@@ -108,6 +111,8 @@ struct TopkJob {
   uint64_t* cand_key;
   int32_t* cand_idx;
   int64_t cap;  // candidate slots per row (>= p, >= 16384)
+  const int64_t* prev;  // may be NULL
+  int64_t ldprev;
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
@@ -128,7 +133,7 @@ size_t gradient_work_bytes(const Layout& L);
 
 // Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st);
-// Zero the error word of rows 0 .. rows-1 of a top-k work area.
+// Zero the error word and the filtered-candidate count of rows 0 .. rows-1 of a top-k work area.
 hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, hipStream_t st);
 
 // Unpenalised columns: dense covariates and the intercept.
@@ -140,6 +145,6 @@ struct Unpen {
 
 hipError_t launch_fill(double* x, int64_t n, double val, hipStream_t st);
 hipError_t launch_zero_u32(uint32_t* x, int64_t n, hipStream_t st);
-hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, double* out, hipStream_t st);
+hipError_t launch_scatter(const int64_t* idx, const double* vals, int32_t k, int64_t p, double* out, hipStream_t st);
 
 }  // namespace iht

@@ -21,8 +21,8 @@ HOST_PTR, DEVICE_PTR = 0, 1
 MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
-           "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit",
-           "iht_fit_batch", "iht_status_str", "iht_last_error")
+           "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
+           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -61,11 +61,13 @@ def load():
     L.iht_gradient.argtypes = [P, P, P, P, I32, P]
     L.iht_gradient_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, P, P]
     L.iht_project.argtypes = [P, I64, I32, P, P, P]
+    L.iht_project_hint.argtypes = [P, I64, I32, P, P, P, P]
     L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
     L.iht_fit_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, I64, P, I32, I32, P, ctypes.POINTER(Opts),
                                 P, P, P, P, P, P, P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
-              "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_fit", "iht_fit_batch"):
+              "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_project_hint", "iht_fit",
+              "iht_fit_batch"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -216,14 +218,21 @@ def gradient_batch(geno: Geno, stats, R, out=None):
     return out
 
 
-def project(w, k: int):
-    """(support int64 [k] ascending, w_out [p]) of the k largest |w| (iht_project)."""
+def project(w, k: int, hint=None):
+    """(support int64 [k] ascending, w_out [p]) of the k largest |w| (iht_project; with `hint`, k
+    distinct indices such as the previous support, iht_project_hint)."""
     torch = _torch()
     wp = _dev(w, torch.float64, None, "w")
     p = w.shape[0]
     sup = torch.empty(k, dtype=torch.int64, device=w.device)
     out = torch.empty(p, dtype=torch.float64, device=w.device)
-    _check(load().iht_project(wp, p, k, ctypes.c_void_p(sup.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream()))
+    if hint is None:
+        _check(load().iht_project(wp, p, k, ctypes.c_void_p(sup.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                  _stream()))
+    else:
+        hp = _dev(hint, torch.int64, (k,), "hint")
+        _check(load().iht_project_hint(wp, p, k, hp, ctypes.c_void_p(sup.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), _stream()))
     return sup, out
 
 

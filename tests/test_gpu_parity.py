@@ -155,7 +155,10 @@ def test_gradient_deterministic():
 
 # ------------------------------------------------------------------ projection
 
-@pytest.mark.parametrize("p,k", [(1, 1), (10, 10), (257, 7), (5000, 64), (100_000, 20), (300_000, 4096)])
+# (100_000, 20) and (5000, 64) take the 2048-entry chunks, (200_000, 100) and (40_000, 500) the 8192-entry
+# chunks, (300_000, 4096) the histogram path
+@pytest.mark.parametrize("p,k", [(1, 1), (10, 10), (257, 7), (5000, 64), (100_000, 20), (200_000, 100), (40_000, 500),
+                                 (300_000, 4096)])
 def test_project_parity(p, k):
     say(f"project p={p} k={k}")
     rng = np.random.default_rng(p + k)
@@ -173,6 +176,45 @@ def test_project_all_equal_and_zeros():
             sup, _ = iht.project(dev(w), k)
             rs, _ = oracle.project(w, k)
             assert np.array_equal(sup.cpu().numpy(), rs)
+
+
+@pytest.mark.parametrize("p,k,kind", [(1000, 1, "perfect"), (100_000, 1, "random"), (100_000, 20, "perfect"),
+                                      (100_000, 20, "random"), (100_000, 20, "zero"),
+                                      (5000, 64, "random"), (300_000, 500, "perfect"), (40_000, 700, "random"),
+                                      (20_000, 7, "out_of_range")])
+def test_project_hint_parity(p, k, kind):
+    """Warm-started projection: any k distinct indices give the result of the plain projection. A
+    hint on an entry of value 0 makes every entry a candidate (more than fit in registers: the
+    candidates are selected from global memory); k > 512 takes the plain path."""
+    say(f"project_hint p={p} k={k} {kind}")
+    rng = np.random.default_rng(p + 3 * k)
+    w = np.round(rng.standard_normal(p), 2)
+    w[rng.integers(0, p, max(1, p // 10))] *= -1
+    rs, ro = oracle.project(w, k)
+    if kind == "perfect":
+        hint = rs.copy()
+    elif kind == "zero":
+        w[5] = 0.0
+        rs, ro = oracle.project(w, k)
+        hint = np.concatenate([[5], rng.choice(np.arange(6, p), k - 1, replace=False)])
+    else:
+        hint = rng.choice(p, k, replace=False)
+        if kind == "out_of_range":
+            hint[0] = p + 12
+    sup, out = iht.project(dev(w), k, hint=dev(hint.astype(np.int64), torch.int64))
+    assert np.array_equal(sup.cpu().numpy(), rs)
+    assert np.array_equal(out.cpu().numpy(), ro)
+
+
+def test_project_hint_rejects_repeated_indices():
+    w = np.arange(1000, dtype=np.float64)
+    hint = np.full(10, 999, dtype=np.int64)  # bound = the largest entry: fewer than k reach it
+    with pytest.raises(iht.IHTError) as e:
+        iht.project(dev(w), 10, hint=dev(hint, torch.int64))
+    assert e.value.code == iht.EINVAL
+    # the next call on the same work area is unaffected
+    sup, _ = iht.project(dev(w), 10, hint=dev(np.arange(10, dtype=np.int64), torch.int64))
+    assert np.array_equal(sup.cpu().numpy(), np.arange(990, 1000))
 
 
 def test_project_rejects_nonfinite():
