@@ -104,33 +104,50 @@ __global__ __launch_bounds__(256) void k_retile(const uint8_t* __restrict__ raw,
 // ------------------------------------------------------------------------------------------------
 // Exact genotype class counts over the subject set -> u, v (Methods, "Bandwidth optimization of IHT").
 
-__device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {  // bit q -> bit 2q
-  return (m & 1u) | ((m & 2u) << 1) | ((m & 4u) << 2) | ((m & 8u) << 3);
+// Bit q of m -> bit 2q: byte g of the result is the subject mask of 4-subject group g of a tile, on
+// the low bits of the groups' 2-bit codes.
+__device__ __forceinline__ uint64_t spread32(uint32_t m) {
+  uint64_t x = m;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
 }
 
+// One SNP per thread, the tiles 8 at a time with their loads issued first. Each 2-bit code adds to
+// one of het (10), hom (11) or missing (01); 00 adds nothing, which is also what the cleared bits
+// of subjects past n hold, so with the whole subject set (FULL) no mask is applied. Otherwise the
+// tile's subject bits are spread onto the codes' low bits and rotated by the SNP's byte rotation
+// (byte b of the segment holds group (b + j) mod 8).
+template <bool FULL>
 __global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
                                                const uint32_t* __restrict__ mask_bits, int64_t nT, double* __restrict__ u,
                                                double* __restrict__ v) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= p) return;
-  const int rot = (int)(j & (kSegBytes - 1));
+  const int rot8 = 8 * (int)(j & (kSegBytes - 1));
   uint32_t het = 0, hom = 0, mis = 0;
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const uint32_t m32 = mask_bits[t];
-    const uint2 d = tiled[t * p_pad + j];
-    const uint32_t dw[2] = {d.x, d.y};
+  constexpr int U = 8;
+  for (int64_t t0 = 0; t0 < ntiles; t0 += U) {
+    uint2 d[U];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      uint32_t mm = 0;
+    for (int e = 0; e < U; ++e) d[e] = (t0 + e < ntiles) ? tiled[(t0 + e) * p_pad + j] : make_uint2(0u, 0u);
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const int grp = (4 * q + bb + rot) & (kSegBytes - 1);
-        mm |= spread_nibble((m32 >> (4 * grp)) & 15u) << (8 * bb);
+    for (int e = 0; e < U; ++e) {
+      uint32_t m0 = 0xFFFFFFFFu, m1 = 0xFFFFFFFFu;
+      if (!FULL) {
+        const uint64_t s64 = spread32(t0 + e < ntiles ? mask_bits[t0 + e] : 0u);
+        const uint64_t seg = rot8 ? (s64 >> rot8) | (s64 << (64 - rot8)) : s64;
+        m0 = (uint32_t)seg;
+        m1 = (uint32_t)(seg >> 32);
       }
-      const uint32_t lo = dw[q] & 0x55555555u, hi = (dw[q] >> 1) & 0x55555555u;
-      het += __popc(hi & ~lo & mm);
-      hom += __popc(hi & lo & mm);
-      mis += __popc(lo & ~hi & mm);
+      const uint32_t lo0 = d[e].x & 0x55555555u, hi0 = (d[e].x >> 1) & 0x55555555u;
+      const uint32_t lo1 = d[e].y & 0x55555555u, hi1 = (d[e].y >> 1) & 0x55555555u;
+      het += __popc(hi0 & ~lo0 & m0) + __popc(hi1 & ~lo1 & m1);
+      hom += __popc(hi0 & lo0 & m0) + __popc(hi1 & lo1 & m1);
+      mis += __popc(lo0 & ~hi0 & m0) + __popc(lo1 & ~hi1 & m1);
     }
   }
   const int64_t nobs = nT - (int64_t)mis;
@@ -1192,8 +1209,12 @@ hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L,
 hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
                         hipStream_t st) {
   const int64_t blocks = (L.p + 255) / 256;
-  hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad,
-                     L.ntiles, mask_bits, nT, u, v);
+  if (nT == L.n)  // the whole subject set: no mask
+    hipLaunchKernelGGL(k_stats<true>, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p,
+                       L.p_pad, L.ntiles, mask_bits, nT, u, v);
+  else
+    hipLaunchKernelGGL(k_stats<false>, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p,
+                       L.p_pad, L.ntiles, mask_bits, nT, u, v);
   return hipGetLastError();
 }
 
