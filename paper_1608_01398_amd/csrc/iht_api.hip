@@ -112,10 +112,13 @@ struct SolveWork {
   DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv;
   DevBuf r8, scale, rsum, slots, count;
   TopkArea topk;
-  FitState* host = nullptr;
+  FitState* host = nullptr;  // pinned: the solves' FitStates as last read
   int32_t host_cap = 0;
+  char* stage = nullptr;  // pinned: ks, the BatchSolves and the top-k error words of a call
+  size_t stage_cap = 0;
   ~SolveWork() {
     if (host) (void)hipHostFree(host);
+    if (stage) (void)hipHostFree(stage);
   }
 };
 }  // namespace
@@ -133,7 +136,12 @@ struct iht_geno {
 struct iht_stats {
   const iht_geno* geno = nullptr;
   int64_t nT = 0;
-  DevBuf u, v, mask, mask_bits;
+  // one allocation: u [p], v [p], the FP64 subject mask [n_pad], then the subject bits [ntiles]
+  DevBuf buf;
+  double* u = nullptr;
+  double* v = nullptr;
+  double* mask = nullptr;
+  uint32_t* mask_bits = nullptr;
 };
 
 extern "C" {
@@ -224,19 +232,22 @@ int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht
   *out = nullptr;
   if (!g) return fail(IHT_EINVAL, "iht_stats_create: NULL geno");
   const Layout& L = g->L;
-  std::vector<double> mask(L.n_pad, 0.0);
-  std::vector<uint32_t> bits(L.ntiles, 0);
-  int64_t nT = 0;
-  for (int64_t i = 0; i < L.n; ++i) {
-    const uint8_t m = subset ? subset[i] : 1;
-    if (m > 1) return fail(IHT_EINVAL, "iht_stats_create: subset entries must be 0 or 1");
-    if (m) {
-      mask[i] = 1.0;
-      bits[i / kTileSubjects] |= uint32_t(1) << (i % kTileSubjects);
-      ++nT;
+  // the subject bits of a subset (the whole set is built on the device)
+  std::vector<uint32_t> bits;
+  int64_t nT = L.n;
+  if (subset) {
+    bits.assign(L.ntiles, 0u);
+    nT = 0;
+    for (int64_t i = 0; i < L.n; ++i) {
+      const uint8_t m = subset[i];
+      if (m > 1) return fail(IHT_EINVAL, "iht_stats_create: subset entries must be 0 or 1");
+      if (m) {
+        bits[i / kTileSubjects] |= uint32_t(1) << (i % kTileSubjects);
+        ++nT;
+      }
     }
+    if (nT < 1) return fail(IHT_EINVAL, "iht_stats_create: empty subject set");
   }
-  if (nT < 1) return fail(IHT_EINVAL, "iht_stats_create: empty subject set");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   iht_stats* S = new (std::nothrow) iht_stats();
   if (!S) return fail(IHT_ENOMEM, "iht_stats_create: host allocation");
@@ -244,24 +255,29 @@ int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht
   S->nT = nT;
   int rc = IHT_OK;
   do {
-    hipError_t e;
-    if ((e = S->u.ensure(L.p * 8)) != hipSuccess || (e = S->v.ensure(L.p * 8)) != hipSuccess ||
-        (e = S->mask.ensure(L.n_pad * 8)) != hipSuccess || (e = S->mask_bits.ensure(L.ntiles * 4)) != hipSuccess) {
+    const size_t fbytes = (size_t)(2 * L.p + L.n_pad) * 8;
+    hipError_t e = S->buf.ensure(fbytes + (size_t)L.ntiles * 4);
+    if (e != hipSuccess) {
       rc = hip_fail(e, "hipMalloc(stats)");
       break;
     }
-    if ((e = hipMemcpyAsync(S->mask.p, mask.data(), L.n_pad * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(S->mask_bits.p, bits.data(), L.ntiles * 4, hipMemcpyHostToDevice, st)) != hipSuccess) {
-      rc = hip_fail(e, "hipMemcpyAsync(mask)");
-      break;
+    S->u = S->buf.as<double>();
+    S->v = S->u + L.p;
+    S->mask = S->v + L.p;
+    S->mask_bits = reinterpret_cast<uint32_t*>(S->buf.as<char>() + fbytes);
+    if (subset) {
+      // pageable source: the copy has read it when the stream is synchronised below
+      if ((e = hipMemcpyAsync(S->mask_bits, bits.data(), L.ntiles * 4, hipMemcpyHostToDevice, st)) != hipSuccess) {
+        rc = hip_fail(e, "hipMemcpyAsync(subject bits)");
+        break;
+      }
     }
-    if ((e = launch_stats(g->tiled.as<uint8_t>(), L, S->mask_bits.as<uint32_t>(), nT, S->u.as<double>(), S->v.as<double>(),
-                          st)) != hipSuccess) {
+    if ((e = launch_subject_mask(L, subset != nullptr, S->mask_bits, S->mask, st)) != hipSuccess ||
+        (e = launch_stats(g->tiled.as<uint8_t>(), L, S->mask_bits, nT, S->u, S->v, st)) != hipSuccess) {
       rc = hip_fail(e, "stats launch");
       break;
     }
-    // the host vectors are freed on return: wait for the copies
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) {
+    if (subset && (e = hipStreamSynchronize(st)) != hipSuccess) {
       rc = hip_fail(e, "stats");
       break;
     }
@@ -283,8 +299,8 @@ int iht_stats_read(const iht_stats* s, double* u, double* v, void* stream) {
   if (!s) return fail(IHT_EINVAL, "iht_stats_read: NULL handle");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const size_t b = (size_t)s->geno->L.p * 8;
-  if (u) HIPCHK(hipMemcpyAsync(u, s->u.p, b, hipMemcpyDeviceToDevice, st));
-  if (v) HIPCHK(hipMemcpyAsync(v, s->v.p, b, hipMemcpyDeviceToDevice, st));
+  if (u) HIPCHK(hipMemcpyAsync(u, s->u, b, hipMemcpyDeviceToDevice, st));
+  if (v) HIPCHK(hipMemcpyAsync(v, s->v, b, hipMemcpyDeviceToDevice, st));
   return IHT_OK;
 }
 
@@ -298,7 +314,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
   HIPCHK(G->state.ensure(sizeof(FitState)));
   HIPCHK(G->partial.ensure(gradient_work_bytes(L)));
   FitState* fs = G->state.as<FitState>();
-  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask.as<double>(), s->nT, s->u.as<double>(), s->v.as<double>(), fs,
+  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask, s->nT, s->u, s->v, fs,
                          precision, grad, G->partial.as<double>(), nullptr, st));
   return IHT_OK;
 }
@@ -311,7 +327,7 @@ int iht_gradient_batch(const iht_geno* g, const iht_stats* const* stats, int32_t
   for (int32_t t = 0; t < T; ++t) {
     if (!stats[t]) return fail(IHT_EINVAL, "iht_gradient_batch: NULL stats handle");
     if (stats[t]->geno != g) return fail(IHT_EINVAL, "iht_gradient_batch: stats belong to another genotype handle");
-    sv[t] = BatchSolve{stats[t]->u.as<double>(), stats[t]->v.as<double>(), stats[t]->mask.as<double>(), stats[t]->nT};
+    sv[t] = BatchSolve{stats[t]->u, stats[t]->v, stats[t]->mask, stats[t]->nT};
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   iht_geno* Gh = const_cast<iht_geno*>(g);
@@ -442,7 +458,7 @@ int run_fit(const FitArgs& A) {
 
   std::vector<BatchSolve> sv(Tz);
   for (int32_t t = 0; t < T; ++t)
-    sv[t] = BatchSolve{A.stats[t]->u.as<double>(), A.stats[t]->v.as<double>(), A.stats[t]->mask.as<double>(), A.stats[t]->nT};
+    sv[t] = BatchSolve{A.stats[t]->u, A.stats[t]->v, A.stats[t]->mask, A.stats[t]->nT};
 
   HIPCHK(W.beta.ensure(Tz * L.p * 8));
   HIPCHK(W.g.ensure(Tz * L.p * 8));
@@ -480,8 +496,22 @@ int run_fit(const FitArgs& A) {
     HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.host), Tz * sizeof(FitState), hipHostMallocDefault));
     W.host_cap = T;
   }
-  HIPCHK(hipMemcpyAsync(W.ks.p, A.ks, Tz * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(W.sv.p, sv.data(), Tz * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
+  // small host inputs and outputs go through pinned memory (asynchronous copies; the call
+  // synchronises before it returns, so the area is free again at the next call)
+  const size_t o_sv = (Tz * 4 + 15) / 16 * 16, o_err = o_sv + (Tz * sizeof(BatchSolve) + 15) / 16 * 16;
+  const size_t stage_bytes = o_err + Tz * 4;
+  if (W.stage_cap < stage_bytes) {
+    if (W.stage) (void)hipHostFree(W.stage);
+    W.stage = nullptr;
+    W.stage_cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.stage), stage_bytes, hipHostMallocDefault));
+    W.stage_cap = stage_bytes;
+  }
+  std::memcpy(W.stage, A.ks, Tz * 4);
+  std::memcpy(W.stage + o_sv, sv.data(), Tz * sizeof(BatchSolve));
+  uint32_t* terr = reinterpret_cast<uint32_t*>(W.stage + o_err);
+  HIPCHK(hipMemcpyAsync(W.ks.p, W.stage, Tz * 4, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(W.sv.p, W.stage + o_sv, Tz * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
 
   SolveSet Q{};
   Q.T = T;
@@ -614,9 +644,7 @@ int run_fit(const FitArgs& A) {
   }
   if (o.precision != IHT_FP64 && o.polish_iter > 0) HIPCHK(solve_polish(Q, o.tol, o.polish_iter, st));
   HIPCHK(solve_output(Q, A.support, A.beta_S, A.beta_cov, kmax, nc, st));
-  std::vector<uint32_t> terr(Tz);
-  HIPCHK(hipMemcpy2DAsync(terr.data(), 4, J.small + kTopkErrorWord, (size_t)kTopkRowWords * 4, 4, Tz, hipMemcpyDeviceToHost,
-                          st));
+  HIPCHK(hipMemcpy2DAsync(terr, 4, J.small + kTopkErrorWord, (size_t)kTopkRowWords * 4, 4, Tz, hipMemcpyDeviceToHost, st));
   if (int rc = read_states()) return rc;
   int worst = IHT_OK;
   for (int32_t t = 0; t < T; ++t) {

@@ -1135,6 +1135,23 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
   }
 }
 
+// Subject mask of a stats handle: mask[i] = bit i of the tile bits (given), or every subject i < n
+// (bits written too).
+__global__ void k_subject_mask(int32_t have_bits, uint32_t* __restrict__ bits, double* __restrict__ mask, int64_t n,
+                               int64_t n_pad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  if (have_bits) {
+    mask[i] = (bits[i / kTileSubjects] >> (i % kTileSubjects)) & 1u ? 1.0 : 0.0;
+    return;
+  }
+  mask[i] = i < n ? 1.0 : 0.0;
+  if (i % kTileSubjects == 0) {
+    const int64_t left = n - i;  // subjects of this tile
+    bits[i / kTileSubjects] = left >= kTileSubjects ? 0xFFFFFFFFu : (left > 0 ? (1u << left) - 1u : 0u);
+  }
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ x, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0u;
@@ -1321,6 +1338,12 @@ hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_topk_collect, grid, dim3(1024), 0, st, J, p, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, double* mask, hipStream_t st) {
+  hipLaunchKernelGGL(k_subject_mask, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, st, (int32_t)have_bits, bits, mask,
+                     L.n, L.n_pad);
   return hipGetLastError();
 }
 

@@ -121,6 +121,8 @@ hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L,
 
 hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
                         hipStream_t st);
+// The subject set's FP64 mask [n_pad] from its bits [ntiles] (have_bits), or both for every subject.
+hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, double* mask, hipStream_t st);
 
 // g = X_st^T r over the subject set (mask, nT): a centring kernel (mean and R = sum of the centred
 // residual into fs, centred residual into `work`), the pass kernel, and a finalize kernel when the
