@@ -36,13 +36,13 @@ def pass_traffic():
     """HBM bytes per FP64 pass launch at n=5000, p=500,000 from the committed counter summary, or None when
     the pass source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "k_pass_c2_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_1608_01398_amd", "csrc", "iht_device.hip")
+    src = os.path.join(ROOT, "paper_1608_01398_amd", "csrc", "iht_pass.hip")
     try:
         txt = open(path).read()
         cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    m = re.search(r"iht_device\.hip sha256 ([0-9a-f]{64})", txt)
+    m = re.search(r"iht_pass\.hip sha256 ([0-9a-f]{64})", txt)
     t = re.search(r"traffic_bytes_per_launch_fp64: (\d+)", txt)
     if not m or not t or m.group(1) != cur:
         return None

@@ -1,4 +1,4 @@
-// iht_internal.h -- device layout, work buffers and launchers shared by the library's two sources.
+// iht_internal.h -- device layout, work buffers and launchers shared by the library's sources.
 #pragma once
 #include <hip/hip_runtime.h>
 
