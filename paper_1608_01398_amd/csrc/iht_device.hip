@@ -579,13 +579,38 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
   tk = shk[0];
 #pragma unroll
   for (int i = 1; i < 4; ++i) tk = shk[i] < tk ? shk[i] : tk;
+  // Appends this wave's `in` lanes to the row's candidate list: one atomic add per wave.
+  auto append = [&](bool in, uint64_t key, int64_t j) {
+    const uint64_t m = __ballot(in);
+    if (m == 0ull) return;
+    uint32_t at = 0u;
+    if (lane == __ffsll((long long)m) - 1) at = atomicAdd(&src.tw.counters[4], (uint32_t)__popcll(m));
+    at = __shfl(at, __ffsll((long long)m) - 1, 64);
+    const uint32_t pos = at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (in && (int64_t)pos < J.cap) {  // the count starts at 0 and cannot pass p <= cap
+      src.tw.cand_key[pos] = key;
+      src.tw.cand_idx[pos] = (int32_t)j;
+    }
+  };
+  // With beta (w = beta + mu g), prev is the support of beta, ascending: beta is zero elsewhere, so
+  // there w = mu g exactly and only g is read; the support's own entries are appended once, by the
+  // row's first block, and skipped by the scan.
+  const bool on_support = src.beta != nullptr;
+  bool bad = false;
+  if (on_support && blockIdx.x == 0) {
+    for (int q0 = 0; q0 < src.k; q0 += 256) {
+      const int q = q0 + tid;
+      const double v = q < src.k ? src.at(prev[q]) : 0.0;
+      bad |= !isfinite(v);
+      append(q < src.k, abs_key(v), q < src.k ? prev[q] : 0);
+    }
+  }
   const int64_t base = (int64_t)blockIdx.x * kSmallChunk;
   uint64_t key[kLocalEPT];
-  bool bad = false;
 #pragma unroll
   for (int e = 0; e < kLocalEPT; ++e) {
     const int64_t j = base + (int64_t)e * 256 + tid;
-    const double v = j < p ? src.at(j) : 0.0;
+    const double v = j < p ? (on_support ? __dmul_rn(src.mu, src.g[j]) : src.at(j)) : 0.0;
     bad |= !isfinite(v);
     key[e] = abs_key(v);
   }
@@ -593,17 +618,19 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
 #pragma unroll
   for (int e = 0; e < kLocalEPT; ++e) {
     const int64_t j = base + (int64_t)e * 256 + tid;
-    const bool in = j < p && key[e] >= tk;
-    const uint64_t m = __ballot(in);
-    if (m == 0ull) continue;
-    uint32_t at = 0u;
-    if (lane == __ffsll((long long)m) - 1) at = atomicAdd(&src.tw.counters[4], (uint32_t)__popcll(m));
-    at = __shfl(at, __ffsll((long long)m) - 1, 64);
-    const uint32_t pos = at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (in && (int64_t)pos < J.cap) {  // the count starts at 0 and cannot pass p <= cap
-      src.tw.cand_key[pos] = key[e];
-      src.tw.cand_idx[pos] = (int32_t)j;
+    bool in = j < p && key[e] >= tk;
+    if (in && on_support) {  // rare: only entries at or above the bound search the support
+      int lo = 0, hi = src.k;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (prev[mid] < j)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      in = !(lo < src.k && prev[lo] == j);
     }
+    append(in, key[e], j);
   }
 }
 

@@ -94,7 +94,8 @@ constexpr int64_t kTopkErrorWord = kTopkBins0 + 8 + 3;  // state[3] of a row
 // keeping k_t = ks ? ks[t] : k0 entries; rows whose FitState is outside `phase` are skipped.
 // With `prev` (k_t distinct indices per row, stride ldprev, e.g. the current support), the smallest
 // |w| over them bounds the k_t-th largest from below, and one filtering pass keeps the entries at or
-// above it as the candidates.
+// above it as the candidates. With both beta and prev, prev must be the support of beta (beta zero
+// elsewhere), ascending.
 struct TopkJob {
   const double* beta;
   const double* g;
