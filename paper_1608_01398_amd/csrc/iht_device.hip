@@ -708,7 +708,30 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
   if (tid == 0) nsel = 0u;
   for (int q = tid; q < kLocalMaxK; q += 1024) sel[q] = 0;
   __syncthreads();
-  if (total <= 1024 * (int64_t)kFinalEPT) {
+  if (total <= 1024) {
+    // short lists (a warm-started projection): the exact rank of each candidate in the total order
+    // (|w| descending, index ascending) against the others in LDS; the k of rank < k are the result
+    uint64_t* ck = reinterpret_cast<uint64_t*>(hist);  // the histogram's 8 KB hold the 1024 keys
+    __shared__ int32_t cidx[1024];
+    if (tid < total) {
+      ck[tid] = src.tw.cand_key[tid];
+      cidx[tid] = src.tw.cand_idx[tid];
+    }
+    __syncthreads();
+    if (tid < total && cidx[tid] >= 0) {
+      const uint64_t kq = ck[tid];
+      const int32_t iq = cidx[tid];
+      int rank = 0;
+      for (int q2 = 0; q2 < (int)total; ++q2) {
+        const int32_t i2 = cidx[q2];
+        rank += (i2 >= 0 && key_before(ck[q2], i2, kq, iq)) ? 1 : 0;
+      }
+      if (rank < k) {
+        const uint32_t pos = atomicAdd(&nsel, 1u);
+        if (pos < (uint32_t)kLocalMaxK) sel[pos] = iq;
+      }
+    }
+  } else if (total <= 1024 * (int64_t)kFinalEPT) {
     uint64_t key[kFinalEPT];
     int32_t idx[kFinalEPT];
 #pragma unroll
