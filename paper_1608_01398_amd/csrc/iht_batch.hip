@@ -127,13 +127,25 @@ constexpr uint32_t kDoseBytes = 0x02010000u;
 constexpr uint32_t kMissBytes = 0x00000100u;
 constexpr int kRbStride = 48;  // bytes per slot row of a staged digit plane (32 + 16: conflict-free)
 
-constexpr int kBlockSnps = 256;  // 4 waves x 64 SNPs
+// One 32-SNP group per wave: 6 accumulator tiles (96 registers) leave 128 registers per wave, so
+// two 8-wave blocks (16 waves) share a CU; two groups per wave (192 accumulator registers, 8 waves
+// per CU) measured 16 % slower on the 108-slot pass.
+#ifndef IHT_BATCH_GROUPS
+#define IHT_BATCH_GROUPS 1
+#endif
+constexpr int kGroups = IHT_BATCH_GROUPS;              // 32-SNP groups per wave (accumulators: 6 per group)
+constexpr int kBlockSnps = 256;                        // per block
+constexpr int kBlockWaves = kBlockSnps / (32 * kGroups);
+constexpr int kBlockThreads = 64 * kBlockWaves;
+#ifndef IHT_BATCH_MINBLOCKS
+#define IHT_BATCH_MINBLOCKS 2
+#endif
 constexpr int kBlockSolves = 32;
 
 // Block (bx, by): SNPs [256 bx, 256 bx + 256) x slots [32 by, 32 by + 32). Wave w: SNPs
-// [256 bx + 64 w, +64) as two groups of 32 rows, each with a dosage and a missing-flag operand,
-// times the 3 digit column tiles: 12 accumulator tiles of 32x32 int32.
-__global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
+// [256 bx + 32 kGroups w, + 32 kGroups) as kGroups groups of 32 rows, each with a dosage and a
+// missing-flag operand, times the 3 digit column tiles: 6 kGroups accumulator tiles of 32x32 int32.
+__global__ __launch_bounds__(kBlockThreads, IHT_BATCH_MINBLOCKS) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
                                                   const int8_t* __restrict__ R8, int32_t T, int32_t T_pad,
                                                   const BatchSolve* __restrict__ sv, const int32_t* __restrict__ slots,
                                                   const int32_t* __restrict__ count, const double* __restrict__ scale,
@@ -146,7 +158,7 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
   const int kh = lane >> 5;  // k-half: subjects 16 kh .. 16 kh + 15 of the tile
   const int col = lane & 31;
 
-  const int64_t j0 = (int64_t)blockIdx.x * kBlockSnps + 64 * w;
+  const int64_t j0 = (int64_t)blockIdx.x * kBlockSnps + 32 * kGroups * w;
   const int64_t jA = j0 + col, jB = j0 + 32 + col;  // this lane's SNP in group 0 / group 1
   const int tb = blockIdx.y * kBlockSolves;
   // un-rotation selector: group g of the tile sits in segment byte (g - j) mod 8; this lane needs
@@ -170,15 +182,15 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
     return tiled[(int64_t)t * p_pad + jj];
   };
 
-  v16i acc[2][2][kDigits];  // [snp group][dose|miss][digit]
+  v16i acc[kGroups][2][kDigits];  // [snp group][dose|miss][digit]
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < kGroups; ++h)
 #pragma unroll
     for (int o = 0; o < 2; ++o)
 #pragma unroll
       for (int d = 0; d < kDigits; ++d) acc[h][o][d] = v16i{};
 
-  uint2 segA = load_seg(0, jA), segB = load_seg(0, jB);
+  uint2 segA = load_seg(0, jA), segB = kGroups > 1 ? load_seg(0, jB) : segA;
   stage_r(0, 0);
   __syncthreads();
   for (int t = 0; t < ntiles; ++t) {
@@ -186,14 +198,14 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
     uint2 nA = segA, nB = segB;
     if (t + 1 < ntiles) {
       nA = load_seg(t + 1, jA);
-      nB = load_seg(t + 1, jB);
+      if (kGroups > 1) nB = load_seg(t + 1, jB);
       stage_r(t + 1, buf ^ 1);
     }
     // A operands: 4 packed bytes (16 subjects) of each SNP; code plane q (the q-th code of every
     // byte) gives the dosage and flag bytes of dword q
-    v4i op[2][2];
+    v4i op[kGroups][2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kGroups; ++h) {
       const uint2 sg = h ? segB : segA;
       const uint32_t g4 = __builtin_amdgcn_perm(sg.y, sg.x, sel);
 #pragma unroll
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
     for (int d = 0; d < kDigits; ++d) {
       const v4i bop = *reinterpret_cast<const v4i*>(&rb[buf][d * (kBlockSolves * kRbStride) + col * kRbStride + kh * 16]);
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < kGroups; ++h)
 #pragma unroll
         for (int o = 0; o < 2; ++o) acc[h][o][d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(op[h][o], bop, acc[h][o][d], 0, 0, 0);
     }
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(256, 2) void k_gradB(const uint2* __restrict__ tile
   const double* v = sv[t].v;
   const double i1 = 1.0 / kBase, i2 = 1.0 / (kBase * kBase);
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < kGroups; ++h)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int64_t j = j0 + 32 * h + 8 * (r / 4) + 4 * kh + (r % 4);
@@ -251,7 +263,7 @@ hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const do
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 grid((unsigned)((L.p + kBlockSnps - 1) / kBlockSnps), (unsigned)(T_pad / kBlockSolves));
-  hipLaunchKernelGGL(k_gradB, grid, dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad, (int32_t)L.ntiles,
+  hipLaunchKernelGGL(k_gradB, grid, dim3(kBlockThreads), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad, (int32_t)L.ntiles,
                      R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
   return hipGetLastError();
 }
