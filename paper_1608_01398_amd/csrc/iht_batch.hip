@@ -134,7 +134,10 @@ constexpr int kRbStride = 48;  // bytes per slot row of a staged digit plane (32
 #define IHT_BATCH_GROUPS 1
 #endif
 constexpr int kGroups = IHT_BATCH_GROUPS;              // 32-SNP groups per wave (accumulators: 6 per group)
-constexpr int kBlockSnps = 256;                        // per block
+#ifndef IHT_BATCH_SNPS
+#define IHT_BATCH_SNPS 256
+#endif
+constexpr int kBlockSnps = IHT_BATCH_SNPS;             // per block
 constexpr int kBlockWaves = kBlockSnps / (32 * kGroups);
 constexpr int kBlockThreads = 64 * kBlockWaves;
 #ifndef IHT_BATCH_MINBLOCKS
