@@ -274,6 +274,16 @@ def test_fit_small_k_and_ragged(k):
     assert_fit_parity(got, ref)
 
 
+@pytest.mark.parametrize("k", [100, 600])
+def test_fit_large_k(k):
+    """k = 100 projects through the warm-started filter with 2048-entry cold chunks; k = 600 > 512
+    takes the histogram projection in every iteration."""
+    prob = synth.make_problem("c1", seed=11, n=2000, p=6000)
+    say(f"fit large k={k}")
+    got, ref = run_both(prob, k)
+    assert_fit_parity(got, ref)
+
+
 def test_fit_backtracking_ld_instance():
     rng = np.random.default_rng(5)
     n, p = 600, 3000
