@@ -125,6 +125,7 @@ def main():
     value = passes * pass_bytes / elapsed / 1e9
     gpu_support = res["support"].cpu().numpy()
     gpu_beta = res["beta_S"].cpu().numpy()
+    gpu_loss = float(res["loss_trace"][-1].item())
 
     # Dominant kernel: the gradient pass, timed alone with events on the stream it is launched on.
     stats = iht.Stats(geno)
@@ -132,17 +133,22 @@ def main():
     g = torch.empty(p, dtype=torch.float64, device="cuda")
     for _ in range(3):
         iht.gradient(geno, stats, r, prec, out=g)
+    torch.cuda.synchronize()
+    g0_gpu = g.cpu().numpy().copy()  # the gradient at beta = 0 (r = y), for the oracle comparison
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.pass_reps):
+    # one event between consecutive calls: the mean over the back-to-back run and each call's time
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.pass_reps + 1)]
+    ev[0].record(stream)
+    for i in range(args.pass_reps):
         iht.gradient(geno, stats, r, prec, out=g)
-    e1.record(stream)
-    e1.synchronize()
-    pass_ms = e0.elapsed_time(e1) / args.pass_reps
+        ev[i + 1].record(stream)
+    ev[-1].synchronize()
+    pass_ms = ev[0].elapsed_time(ev[-1]) / args.pass_reps
+    per_call_us = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(args.pass_reps)])
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9
-    log(f"gradient pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak)")
+    log(f"gradient pass: {pass_ms * 1e3:.1f} us, {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.1%} of HBM peak); "
+        f"per call p10/p50/p90 {np.percentile(per_call_us, 10):.1f}/{np.percentile(per_call_us, 50):.1f}/"
+        f"{np.percentile(per_call_us, 90):.1f} us")
 
     out = {
         "metric": METRIC,
@@ -175,7 +181,10 @@ def main():
             "traffic": pass_traffic() if (prec == iht.FP64 and cfg == "c2") else None,
             "traffic_unit": "HBM bytes per call (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launch_us": round(pass_ms * 1e3, 2),
+            "launch_us_p10_p50_p90": [round(float(np.percentile(per_call_us, q)), 2) for q in (10, 50, 90)],
             "algorithmic_bytes_per_launch": pass_bytes,
+            # residual read, u and v read, g written: not credited to the pass
+            "aux_bytes_per_launch": 8 * n + 24 * p,
         },
     }
 
@@ -199,9 +208,17 @@ def main():
         }
         same = bool(np.array_equal(gpu_support, ref["support"]))
         brel = float(np.abs(gpu_beta - ref["beta_S"]).max() / np.abs(ref["beta_S"]).max()) if same else None
-        out["parity"] = {"support_equal": same, "beta_max_rel_err": brel,
-                         "iterations_gpu": int(iters[-1]), "iterations_oracle": int(ref["n_iter"])}
-        log(f"oracle: {ct:.1f}s, {cval:.2f} GB/s; support equal {same}, beta rel err {brel}")
+        lrel = float(abs(gpu_loss - ref["loss_trace"][-1]) / abs(ref["loss_trace"][-1]))
+        # the gradient at beta = 0 (r = y), against the oracle's own stats and pass
+        ou, ov = oracle.stats(prob["bed"], n)
+        g_ref = oracle.gradient(prob["bed"], n, ou, ov, prob["y"])
+        grel = float(np.linalg.norm(g0_gpu - g_ref) / np.linalg.norm(g_ref))
+        out["parity"] = {"support_equal": same, "beta_max_rel_err": brel, "loss_rel_diff": lrel,
+                         "gradient_rel_l2_err_at_beta0": grel,
+                         "iterations_gpu": int(iters[-1]), "iterations_oracle": int(ref["n_iter"]),
+                         "delta_iterations": int(iters[-1]) - int(ref["n_iter"])}
+        log(f"oracle: {ct:.1f}s, {cval:.2f} GB/s; support equal {same}, beta rel err {brel}, loss rel diff {lrel:.2e}, "
+            f"gradient rel L2 err {grel:.2e}")
         if "batched" in out:
             smp = out["batched"]["_sample"]
             t = time.perf_counter()
@@ -266,6 +283,14 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
     torch.cuda.synchronize()
     plain = time.perf_counter() - t0
     log(f"plain FP64 loop: {T} solves in {plain * 1e3:.1f} ms")
+    iht.fit(geno, stats[0], Y[0], ks[0], precision=iht.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(T):
+        iht.fit(geno, stats[t], Y[t], ks[t], precision=iht.FP32)
+    torch.cuda.synchronize()
+    plain32 = time.perf_counter() - t0
+    log(f"plain FP32 loop: {T} solves in {plain32 * 1e3:.1f} ms")
     # the matrix-core pass alone, all 108 solves (HIP events on the launch stream)
     R = torch.randn((T, n), dtype=torch.float64, device="cuda")
     G = torch.empty((T, p), dtype=torch.float64, device="cuda")
@@ -298,6 +323,8 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
         "plain_fp64_solve_latency_ms_p50": round(float(np.percentile(np.asarray(lat) * 1e3, 50)), 2),
         "plain_fp64_solve_latency_ms_p99": round(float(np.percentile(np.asarray(lat) * 1e3, 99)), 2),
         "speedup_vs_plain_fp64_loop": round(plain / bt, 2),
+        "plain_fp32_loop_solves_per_s": round(T / plain32, 2),
+        "speedup_vs_plain_fp32_loop": round(plain32 / bt, 2),
         "iterations_mean": round(float(iters.mean()), 2),
         "statuses": [int(x) for x in np.asarray(res["statuses"])],
         "roofline": {
