@@ -28,6 +28,9 @@
  *   R10 covariates and intercept are unpenalised, always in the model, never projected.
  *   R11 g = A^T r = -grad f; the update is beta + mu g.
  *   R12 a subject subset is solved as the problem restricted to those rows, with its own u, v.
+ *   R17 cross-validation: the caller assigns every subject to one of q folds; the held-out MSE is
+ *      the mean of (y - prediction)^2 over the fold, predicted with the training fold's u, v; the
+ *      model size of least mean MSE wins (the first in the given order on an exact tie).
  *
  * Plain sequential sums everywhere, compiled with -O2 -ffp-contract=off. OpenMP splits only
  * independent per-SNP work (each SNP's sum keeps its own sequential order), as in the paper's
@@ -401,5 +404,79 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
 done:
     free(T); free(u); free(v); free(beta); free(betap); free(g); free(w); free(dlt); free(r); free(tmp);
     free(S); free(Sp); free(U);
+    return rc;
+}
+
+/* ---- q-fold cross-validation over a path of model sizes (Methods, Model selection) ----
+ * For fold f the training set is the subjects whose fold is not f: a subset solve (reading R12)
+ * with its own u, v. For every k in ks the fitted model predicts the subjects of fold f,
+ * standardised with the training u, v (a missing dosage is mean-imputed, i.e. 0 after
+ * standardising: reading R7), and their mean squared error goes to mse[ki * q + f].
+ * Reading R17: k_best is the k of least mean MSE over the folds (mean = sequential sum over f / q),
+ * the first in ks on an exact tie; the refit on every subject is a plain fit with that k. */
+int iht_ref_cv(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, const uint8_t *folds, int32_t q,
+               const double *y, const float *Z, int32_t cz, int32_t intercept, const int32_t *ks, int32_t r, double tol,
+               int32_t max_iter, int32_t max_backtrack, double c, double shrink, double *mse, int32_t *k_best) {
+    if (!bed || !folds || !y || !ks || !mse || !k_best || n < 1 || p < 1 || q < 2 || r < 1 || cz < 0 ||
+        (cz > 0 && !Z) || max_iter < 1)
+        return REF_EINVAL;
+    int32_t kmax = 0;
+    for (int32_t a = 0; a < r; ++a) {
+        if (ks[a] < 1 || ks[a] > p) return REF_EINVAL;
+        if (ks[a] > kmax) kmax = ks[a];
+    }
+    int64_t *count = (int64_t *)calloc((size_t)q, sizeof(int64_t));
+    if (!count) return REF_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        if (folds[i] >= q) { free(count); return REF_EINVAL; }
+        count[folds[i]]++;
+    }
+    for (int32_t f = 0; f < q; ++f)
+        if (count[f] == 0 || count[f] == n) { free(count); return REF_EINVAL; }  /* empty test or training set */
+    const int32_t nc = cz + (intercept ? 1 : 0);
+    uint8_t *subset = (uint8_t *)malloc((size_t)n);
+    double *u = (double *)malloc(sizeof(double) * (size_t)p);
+    double *v = (double *)malloc(sizeof(double) * (size_t)p);
+    int64_t *sup = (int64_t *)malloc(sizeof(int64_t) * (size_t)kmax);
+    double *bS = (double *)malloc(sizeof(double) * (size_t)kmax);
+    double *bc = (double *)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    double *trace = (double *)malloc(sizeof(double) * (size_t)(max_iter + 1));
+    double *mu = (double *)malloc(sizeof(double) * (size_t)max_iter);
+    int rc = REF_OK;
+    if (!subset || !u || !v || !sup || !bS || !bc || !trace || !mu) { rc = REF_ENOMEM; goto done; }
+    for (int32_t f = 0; f < q; ++f) {
+        for (int64_t i = 0; i < n; ++i) subset[i] = folds[i] != f;
+        rc = iht_ref_stats(bed, n, p, row_bytes, subset, u, v);
+        if (rc) goto done;
+        for (int32_t a = 0; a < r; ++a) {
+            int32_t nit = 0;
+            rc = iht_ref_fit(bed, n, p, row_bytes, subset, y, Z, cz, intercept, ks[a], tol, max_iter, max_backtrack, c,
+                             shrink, sup, bS, bc, trace, &nit, mu);
+            if (rc < 0) goto done;
+            double ss = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (folds[i] != f) continue;
+                double pred = 0.0;
+                for (int32_t t = 0; t < ks[a]; ++t) pred += xst(bed, row_bytes, sup[t], i, u, v) * bS[t];
+                for (int32_t cc = 0; cc < cz; ++cc) pred += (double)Z[(int64_t)cc * n + i] * bc[cc];
+                if (intercept) pred += bc[cz];
+                const double d = y[i] - pred;
+                ss += d * d;
+            }
+            mse[(int64_t)a * q + f] = ss / (double)count[f];
+        }
+    }
+    rc = REF_OK;
+    {
+        double best = 0.0;
+        for (int32_t a = 0; a < r; ++a) {
+            double s = 0.0;
+            for (int32_t f = 0; f < q; ++f) s += mse[(int64_t)a * q + f];
+            s /= (double)q;
+            if (a == 0 || s < best) { best = s; *k_best = ks[a]; }
+        }
+    }
+done:
+    free(count); free(subset); free(u); free(v); free(sup); free(bS); free(bc); free(trace); free(mu);
     return rc;
 }

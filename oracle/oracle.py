@@ -51,8 +51,9 @@ def lib():
         L.iht_ref_gradient.argtypes = [P, I64, I64, I64, P, P, P, P, P]
         L.iht_ref_project.argtypes = [P, I64, I32, P, P]
         L.iht_ref_fit.argtypes = [P, I64, I64, I64, P, P, P, I32, I32, I32, D, I32, I32, D, D, P, P, P, P, P, P]
+        L.iht_ref_cv.argtypes = [P, I64, I64, I64, P, I32, P, P, I32, I32, P, I32, D, I32, I32, D, D, P, P]
         for f in (L.iht_ref_decode, L.iht_ref_stats, L.iht_ref_standardize, L.iht_ref_gradient, L.iht_ref_project,
-                  L.iht_ref_fit):
+                  L.iht_ref_fit, L.iht_ref_cv):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -164,3 +165,30 @@ def fit(bed, n, y, k, Z=None, intercept=True, subset=None, **opts):
     it = nit.value
     return dict(status=rc, support=sup, beta_S=bS, beta_cov=bc[:nc], loss_trace=trace[:it + 1], n_iter=it,
                 mu_trace=mu[:it])
+
+
+def cv(bed, n, y, ks, folds, q, Z=None, intercept=True, **opts):
+    """q-fold cross-validation over the model sizes ks (Methods, "Model selection"), then the refit
+    on every subject with the chosen k. folds: [n] fold index of each subject (0..q-1).
+
+    Returns dict(mse [len(ks), q] held-out mean squared errors, k_best, refit = fit(...)).
+    """
+    o = dict(DEFAULTS)
+    o.update(opts)
+    bed_c, p, rb = _bed(bed)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    folds = np.ascontiguousarray(folds, dtype=np.uint8)
+    assert y.shape == (n,) and folds.shape == (n,)
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    cz = 0
+    if Z is not None:
+        Z = np.ascontiguousarray(Z, dtype=np.float32)
+        cz = Z.shape[0]
+    mse = np.empty((len(ks), q))
+    kb = ctypes.c_int32(0)
+    rc = lib().iht_ref_cv(_p(bed_c), n, p, rb, _p(folds), q, _p(y), _p(Z), cz, 1 if intercept else 0, _p(ks), len(ks),
+                          o["tol"], o["max_iter"], o["max_backtrack"], o["c"], o["shrink"], _p(mse), ctypes.byref(kb))
+    if rc < 0:
+        raise ValueError(f"iht_ref_cv: {rc}")
+    refit = fit(bed, n, y, kb.value, Z=Z, intercept=intercept, **opts)
+    return dict(mse=mse, k_best=kb.value, refit=refit)

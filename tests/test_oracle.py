@@ -11,6 +11,9 @@ sign or index, a transposed operand, the wrong variance denominator) fails at le
   - fit ........................................ lstsq on the support at the fixed point,
                                                  Hadamard closed form, brute-force best subset,
                                                  monotone loss, subset == extracted rows
+  - cross-validation ........................... held-out MSE recomputed from the decoder and the
+                                                 NumPy u, v; a noise-free sparse model has ~0
+                                                 held-out MSE from its true size on
 """
 import itertools
 import math
@@ -390,3 +393,70 @@ def test_backtracking_budget_exhaustion_reports_stalled():
             assert np.all(np.diff(tr) <= 1e-12 * tr[0])
             break
     assert found
+
+
+# ------------------------------------------------------------------ cross-validation (Model selection)
+
+def _numpy_heldout_mse(bed, n, y, folds, f, sup, beta_S, beta_cov):
+    """MSE of fold f from first principles: dosages from the decoder pinned above, training u, v by
+    the NumPy definition (nanmean; population std of the mean-imputed column), missing -> 0."""
+    dose = oracle.decode(bed, n).astype(np.float64)  # [p, n], -1 = missing
+    train = folds != f
+    d = dose[sup][:, train]
+    obs = d >= 0
+    u = np.where(obs, d, 0.0).sum(1) / obs.sum(1)
+    imp = np.where(obs, d, u[:, None])
+    sd = imp.std(axis=1)
+    v = np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 0.0)
+    test = folds == f
+    dt = dose[sup][:, test]
+    xs = np.where(dt >= 0, v[:, None] * (dt - u[:, None]), 0.0)
+    pred = beta_S @ xs + beta_cov[-1]
+    return float(np.mean((y[test] - pred) ** 2))
+
+
+def test_cv_heldout_mse_from_first_principles():
+    n, p, q = 240, 400, 3
+    bed, qf = synth.make_genotypes(n, p, 21)
+    y, *_ = synth.make_trait(bed, n, qf, 4, (0.4, 0.8), 21)
+    folds = np.random.default_rng(2).permutation(np.arange(n) % q).astype(np.uint8)
+    ks = [2, 4, 6]
+    res = oracle.cv(bed, n, y, ks, folds, q)
+    for a, k in enumerate(ks):
+        for f in range(q):
+            fit = oracle.fit(bed, n, y, k, subset=(folds != f).astype(np.uint8))
+            ref = _numpy_heldout_mse(bed, n, y, folds, f, fit["support"], fit["beta_S"], fit["beta_cov"])
+            assert abs(res["mse"][a, f] - ref) <= 1e-12 * ref, (k, f, res["mse"][a, f], ref)
+    best = ks[int(np.argmin(res["mse"].mean(1)))]
+    assert res["k_best"] == best
+    assert np.array_equal(res["refit"]["support"], oracle.fit(bed, n, y, best)["support"])
+
+
+def test_cv_noise_free_sparse_model_selects_its_size():
+    """y exactly k_true standardised columns plus an intercept, no missing dosages: a model with the
+    true support predicts held-out subjects exactly (another subset's u, v only rescale the columns
+    and shift the intercept), so the held-out MSE is ~0 from k_true on and clearly not below it."""
+    n, p, q, kt = 300, 200, 4, 3
+    bed, qf = synth.make_genotypes(n, p, 33, miss=0.0)
+    rng = np.random.default_rng(3)
+    cols = np.sort(rng.choice(p, kt, replace=False))
+    dose = oracle.decode(bed, n).astype(np.float64)[cols]
+    b = rng.uniform(0.8, 1.2, kt) * rng.choice([-1, 1], kt)
+    y = 2.0 + (dose - dose.mean(1, keepdims=True)).T @ b
+    folds = rng.permutation(np.arange(n) % q).astype(np.uint8)
+    res = oracle.cv(bed, n, y, [1, 2, 3, 4, 5], folds, q, tol=1e-14, max_iter=500)
+    scale = float(np.var(y))
+    assert np.all(res["mse"][:2] > 1e-3 * scale)
+    assert np.all(res["mse"][2:] < 1e-20 * scale)
+    assert res["k_best"] >= kt
+    assert np.array_equal(np.intersect1d(res["refit"]["support"], cols), cols)
+
+
+def test_cv_rejects_bad_folds():
+    n, p = 60, 50
+    bed, qf = synth.make_genotypes(n, p, 5)
+    y = np.random.default_rng(0).standard_normal(n)
+    good = (np.arange(n) % 3).astype(np.uint8)
+    for folds, q in ((good, 1), ((good + 3).astype(np.uint8), 3), (np.zeros(n, np.uint8), 3)):
+        with pytest.raises(ValueError):
+            oracle.cv(bed, n, y, [1, 2], folds, q)
