@@ -209,6 +209,30 @@ int iht_fit_batch(const iht_geno *g, const iht_stats *const *stats, int32_t T, c
                   int32_t cz, int32_t intercept, const int32_t *ks, const iht_opts *opts, int64_t *support, double *beta_S,
                   double *beta_cov, double *loss_trace, int32_t *n_iter, int32_t *status, void *stream);
 
+/*
+ * q-fold cross-validation over a path of model sizes (Methods, "Model selection"). Subject i is
+ * held out in fold folds[i]. For each fold f and each ks[a], IHT is fitted on the other subjects,
+ * with the standardisation (u_j, v_j) of those subjects only; the held-out mean squared error is
+ * mse[a][f] = (1/|fold f|) sum_{i in fold f} (y_i - x_st,i beta - z_i beta_cov)^2, the held-out
+ * genotypes standardised with the training u_j, v_j (a missing genotype counts as 0). The chosen size
+ * is the first ks[a] of least mean over the folds; the model of that size is refitted on every
+ * subject and returned as by iht_fit.
+ *   y, Z, cz, intercept, opts   as in iht_fit (y and Z device memory).
+ *   folds      host uint8 [n], each < q; every fold and its complement non-empty.
+ *   q          2 <= q <= 64 folds.
+ *   ks         host int32 [r], 1 <= ks[a] <= min(p, IHT_MAX_K); 1 <= q * r <= 65535.
+ *   mse        host FP64 [r][q] output.
+ *   k_best     host int32 output: the chosen model size.
+ *   support, beta_S, beta_cov, loss_trace, n_iter   the refit's outputs, as in iht_fit with k = *k_best
+ *              (support and beta_S need max ks[a] entries).
+ * The q * r training fits run as one batch (iht_fit_batch). Returns the refit's status, or an error
+ * (IHT_EINVAL, IHT_ENONFINITE, IHT_ENOMEM, IHT_EDEVICE); warnings of the training fits are not
+ * reported. Synchronises the stream.
+ */
+int iht_cv(const iht_geno *g, const double *y, const float *Z, int32_t cz, int32_t intercept, const uint8_t *folds, int32_t q,
+           const int32_t *ks, int32_t r, const iht_opts *opts, double *mse, int32_t *k_best, int64_t *support, double *beta_S,
+           double *beta_cov, double *loss_trace, int32_t *n_iter, void *stream);
+
 const char *iht_status_str(int status);
 const char *iht_last_error(void);
 

@@ -718,4 +718,123 @@ int iht_fit_batch(const iht_geno* g, const iht_stats* const* stats, int32_t T, c
   return rc;
 }
 
+
+int iht_cv(const iht_geno* g, const double* y, const float* Z, int32_t cz, int32_t intercept, const uint8_t* folds, int32_t q,
+           const int32_t* ks, int32_t r, const iht_opts* opts, double* mse, int32_t* k_best, int64_t* support, double* beta_S,
+           double* beta_cov, double* loss_trace, int32_t* n_iter, void* stream) {
+  iht_opts o;
+  iht_opts_default(&o);
+  if (opts) o = *opts;
+  if (!g || !y || !folds || !ks || !mse || !k_best || !support || !beta_S || !loss_trace || !n_iter)
+    return fail(IHT_EINVAL, "iht_cv: NULL argument");
+  const Layout& L = g->L;
+  if (q < 2 || q > 64 || r < 1 || (int64_t)q * r > 65535) return fail(IHT_EINVAL, "iht_cv: q or r out of range");
+  const int32_t icpt = intercept ? 1 : 0;
+  const int32_t nc = cz + icpt;
+  if (cz < 0 || (cz > 0 && !Z) || nc > kMaxUnpenalized) return fail(IHT_EINVAL, "iht_cv: bad covariates");
+  if (nc > 0 && !beta_cov) return fail(IHT_EINVAL, "iht_cv: beta_cov is NULL");
+  int32_t kmax = 0;
+  for (int32_t a = 0; a < r; ++a) {
+    if (ks[a] < 1 || ks[a] > L.p || ks[a] > IHT_MAX_K) return fail(IHT_EINVAL, "iht_cv: k out of range");
+    kmax = std::max(kmax, ks[a]);
+  }
+  if (int rc = check_opts(o, "iht_cv")) return rc;
+  std::vector<int64_t> count(q, 0);
+  for (int64_t i = 0; i < L.n; ++i) {
+    if (folds[i] >= q) return fail(IHT_EINVAL, "iht_cv: fold index >= q");
+    count[folds[i]]++;
+  }
+  for (int32_t f = 0; f < q; ++f)
+    if (count[f] == 0 || count[f] == L.n) return fail(IHT_EINVAL, "iht_cv: every fold and its complement must be non-empty");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  *n_iter = 0;
+
+  // training statistics of each fold (the subjects outside it) and of the whole set
+  std::vector<iht_stats*> fstats(q, nullptr);
+  iht_stats* full = nullptr;
+  auto release = [&]() {
+    for (iht_stats* s : fstats) iht_stats_destroy(s);
+    iht_stats_destroy(full);
+  };
+  std::vector<uint8_t> sub(L.n);
+  for (int32_t f = 0; f < q; ++f) {
+    for (int64_t i = 0; i < L.n; ++i) sub[i] = folds[i] != f ? 1 : 0;
+    if (int rc = iht_stats_create(g, sub.data(), stream, &fstats[f])) {
+      release();
+      return rc;
+    }
+  }
+  if (int rc = iht_stats_create(g, nullptr, stream, &full)) {
+    release();
+    return rc;
+  }
+
+  // the q x r training solves (solve f * r + a: fold f held out, model size ks[a]) in one batch, all
+  // reading the same trait (row stride 0)
+  const int32_t T = q * r;
+  const size_t Tz = (size_t)T;
+  std::vector<const iht_stats*> stats(Tz);
+  std::vector<int32_t> kss(Tz);
+  std::vector<BatchSolve> sv(Tz);
+  for (int32_t f = 0; f < q; ++f)
+    for (int32_t a = 0; a < r; ++a) {
+      const int32_t t = f * r + a;
+      stats[t] = fstats[f];
+      kss[t] = ks[a];
+      sv[t] = BatchSolve{fstats[f]->u, fstats[f]->v, fstats[f]->mask, fstats[f]->nT};
+    }
+  const int32_t nblk = (int32_t)((L.n + 255) / 256);
+  DevBuf d_sup, d_bS, d_bc, d_trace, d_folds, d_count, d_ks_solve, d_ks_path, d_part, d_mse, d_kb, d_sv;
+  std::vector<int32_t> it_t(Tz), st_t(Tz);
+  int rc = IHT_OK;
+  do {
+    hipError_t e;
+    if ((e = d_sup.ensure(Tz * kmax * 8)) != hipSuccess || (e = d_bS.ensure(Tz * kmax * 8)) != hipSuccess ||
+        (e = d_bc.ensure(Tz * std::max(nc, 1) * 8)) != hipSuccess ||
+        (e = d_trace.ensure(Tz * (size_t)(o.max_iter + 1) * 8)) != hipSuccess || (e = d_folds.ensure(L.n)) != hipSuccess ||
+        (e = d_count.ensure((size_t)q * 8)) != hipSuccess || (e = d_ks_solve.ensure(Tz * 4)) != hipSuccess ||
+        (e = d_ks_path.ensure((size_t)r * 4)) != hipSuccess || (e = d_part.ensure(Tz * nblk * 8)) != hipSuccess ||
+        (e = d_mse.ensure((size_t)r * q * 8)) != hipSuccess || (e = d_kb.ensure(4)) != hipSuccess ||
+        (e = d_sv.ensure(Tz * sizeof(BatchSolve))) != hipSuccess) {
+      rc = hip_fail(e, "hipMalloc(cv)");
+      break;
+    }
+    FitArgs A{g, stats.data(), T, y, 0, Unpen{Z, cz, icpt}, kss.data(), o, d_sup.as<int64_t>(), d_bS.as<double>(),
+              nc ? d_bc.as<double>() : nullptr, d_trace.as<double>(), it_t.data(), st_t.data(), st};
+    rc = run_fit(A);
+    if (rc < 0) break;
+    // held-out errors, the MSE table and the chosen size (pageable sources: synchronous copies)
+    if ((e = hipMemcpy(d_folds.p, folds, L.n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_count.p, count.data(), (size_t)q * 8, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_ks_solve.p, kss.data(), Tz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_ks_path.p, ks, (size_t)r * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(d_sv.p, sv.data(), Tz * sizeof(BatchSolve), hipMemcpyHostToDevice)) != hipSuccess) {
+      rc = hip_fail(e, "hipMemcpy(cv)");
+      break;
+    }
+    if ((e = cv_heldout_mse(g->tiled.as<uint8_t>(), L, d_folds.as<uint8_t>(), q, r, d_sv.as<BatchSolve>(),
+                            d_ks_solve.as<int32_t>(), d_ks_path.as<int32_t>(), d_sup.as<int64_t>(), d_bS.as<double>(), kmax,
+                            d_bc.as<double>(), std::max(nc, 1), Unpen{Z, cz, icpt}, y, d_count.as<int64_t>(),
+                            d_part.as<double>(), d_mse.as<double>(), d_kb.as<int32_t>(), st)) != hipSuccess) {
+      rc = hip_fail(e, "cv launch");
+      break;
+    }
+    if ((e = hipMemcpyAsync(mse, d_mse.p, (size_t)r * q * 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(k_best, d_kb.p, 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      rc = hip_fail(e, "cv results");
+      break;
+    }
+    // the refit on every subject with the chosen size
+    int32_t status = IHT_OK;
+    const iht_stats* s1[1] = {full};
+    FitArgs B{g, s1, 1, y, L.n, Unpen{Z, cz, icpt}, k_best, o, support, beta_S, nc ? beta_cov : nullptr, loss_trace, n_iter,
+              &status, st};
+    rc = run_fit(B);
+  } while (0);
+  release();
+  if (rc == IHT_ENONFINITE) return fail(IHT_ENONFINITE, "iht_cv: non-finite y or Z");
+  return rc;
+}
+
 }  // extern "C"

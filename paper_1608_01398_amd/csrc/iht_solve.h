@@ -60,6 +60,14 @@ hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
 hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStream_t st);
 hipError_t solve_output(const SolveSet& Q, int64_t* support, double* beta_S, double* beta_cov, int64_t ldk, int64_t ldc,
                         hipStream_t st);
+// Held-out mean squared errors of q x r cross-validation solves (solve f * r + a: fold f held out,
+// model size ks_path[a]; ks_solve[t] = its k), mse [r][q], and the k of least mean MSE. part holds
+// ceil(n / 256) doubles per solve; fold_count [q] the size of each fold.
+hipError_t cv_heldout_mse(const uint8_t* tiled, const Layout& L, const uint8_t* folds, int32_t q, int32_t r,
+                          const BatchSolve* sv, const int32_t* ks_solve, const int32_t* ks_path, const int64_t* support,
+                          const double* beta_S, int64_t ldk, const double* beta_cov, int64_t ldc, const Unpen& U,
+                          const double* y, const int64_t* fold_count, double* part, double* mse, int32_t* k_best,
+                          hipStream_t st);
 // slots[0 .. *count) = the solves in `phase`, ascending.
 hipError_t solve_slots(const FitState* fs, int32_t T, int32_t phase, int32_t* slots, int32_t* count, hipStream_t st);
 

@@ -854,3 +854,88 @@ hipError_t solve_slots(const FitState* fs, int32_t T, int32_t phase, int32_t* sl
 }
 
 }  // namespace iht
+
+// ---------------------------------------------------------------------------- cross-validation
+
+namespace iht {
+namespace {
+
+// Held-out squared errors (Methods, "Model selection"): solve t = f * r + a was fitted on the
+// subjects outside fold f; every subject i of fold f is predicted with the solve's model,
+// standardised with its training u, v (a missing dosage is mean-imputed, i.e. 0 after
+// standardising), and (y_i - prediction)^2 is summed per block in a fixed order.
+__global__ __launch_bounds__(256) void k_cv_sqerr(const uint8_t* __restrict__ tiled, int64_t n, int64_t p_pad,
+                                                  const uint8_t* __restrict__ folds, int32_t r, const BatchSolve* __restrict__ sv,
+                                                  const int32_t* __restrict__ ks, const int64_t* __restrict__ support,
+                                                  const double* __restrict__ beta_S, int64_t ldk,
+                                                  const double* __restrict__ beta_cov, int64_t ldc, Unpen U,
+                                                  const double* __restrict__ y, double* __restrict__ part) {
+  const int t = blockIdx.y;
+  const int f = t / r;
+  const int k = ks[t % r];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double e2 = 0.0;
+  if (i < n && folds[i] == f) {
+    const double* u = sv[t].u;
+    const double* v = sv[t].v;
+    const int64_t tile = i / kTileSubjects;
+    const int grp = (int)((i % kTileSubjects) >> 2);
+    double pred = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const int64_t j = support[(int64_t)t * ldk + q];
+      const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
+      const int code = (tiled[(tile * p_pad + j) * kSegBytes + b] >> (2 * (i & 3))) & 3;
+      const double x = (code == 1) ? 0.0 : v[j] * ((code == 0 ? 0.0 : (double)(code - 1)) - u[j]);
+      pred += x * beta_S[(int64_t)t * ldk + q];
+    }
+    for (int c = 0; c < U.cz + U.icpt; ++c) pred += ucol(U, n, c, i) * beta_cov[(int64_t)t * ldc + c];
+    const double d = y[i] - pred;
+    e2 = d * d;
+  }
+  __shared__ double sh[40];
+  e2 = ssum(e2, sh);
+  if (threadIdx.x == 0) part[(int64_t)t * gridDim.x + blockIdx.x] = e2;
+}
+
+// mse[a * q + f] = (sum of fold f's block partials of solve f * r + a, in block order) / |fold f|;
+// then k_best = the k of least mean MSE over the folds (the first in ks on an exact tie).
+__global__ __launch_bounds__(64) void k_cv_finish(const double* __restrict__ part, int32_t nblk, int32_t q, int32_t r,
+                                                  const int64_t* __restrict__ fold_count, const int32_t* __restrict__ ks,
+                                                  double* __restrict__ mse, int32_t* __restrict__ k_best) {
+  if (threadIdx.x != 0) return;
+  for (int f = 0; f < q; ++f)
+    for (int a = 0; a < r; ++a) {
+      const double* P = part + (int64_t)(f * r + a) * nblk;
+      double s = 0.0;
+      for (int b = 0; b < nblk; ++b) s += P[b];
+      mse[(int64_t)a * q + f] = s / (double)fold_count[f];
+    }
+  double best = 0.0;
+  for (int a = 0; a < r; ++a) {
+    double s = 0.0;
+    for (int f = 0; f < q; ++f) s += mse[(int64_t)a * q + f];
+    s /= (double)q;
+    if (a == 0 || s < best) {
+      best = s;
+      *k_best = ks[a];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t cv_heldout_mse(const uint8_t* tiled, const Layout& L, const uint8_t* folds, int32_t q, int32_t r,
+                          const BatchSolve* sv, const int32_t* ks_solve, const int32_t* ks_path, const int64_t* support,
+                          const double* beta_S, int64_t ldk, const double* beta_cov, int64_t ldc, const Unpen& U,
+                          const double* y, const int64_t* fold_count, double* part, double* mse, int32_t* k_best,
+                          hipStream_t st) {
+  const int32_t nblk = (int32_t)((L.n + 255) / 256);
+  hipLaunchKernelGGL(k_cv_sqerr, dim3((unsigned)nblk, (unsigned)(q * r)), dim3(256), 0, st, tiled, L.n, L.p_pad, folds, r, sv,
+                     ks_solve, support, beta_S, ldk, beta_cov, ldc, U, y, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cv_finish, dim3(1), dim3(64), 0, st, part, nblk, q, r, fold_count, ks_path, mse, k_best);
+  return hipGetLastError();
+}
+
+}  // namespace iht

@@ -22,7 +22,7 @@ MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
-           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_status_str", "iht_last_error")
+           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -65,9 +65,11 @@ def load():
     L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
     L.iht_fit_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, I64, P, I32, I32, P, ctypes.POINTER(Opts),
                                 P, P, P, P, P, P, P]
+    L.iht_cv.argtypes = [P, P, P, I32, I32, P, I32, P, I32, ctypes.POINTER(Opts), P, ctypes.POINTER(I32), P, P, P, P,
+                         ctypes.POINTER(I32), P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
               "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_project_hint", "iht_fit",
-              "iht_fit_batch"):
+              "iht_fit_batch", "iht_cv"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -302,3 +304,44 @@ def fit_batch(geno: Geno, stats, Y, ks, Z=None, intercept: bool = True, **opts):
     if rc < 0 and rc != ENONFINITE:
         _check(rc)
     return dict(status=rc, statuses=st, support=sup, beta_S=bS, beta_cov=bc[:, :nc], loss_trace=trace, n_iter=nit)
+
+
+def cv(geno: Geno, y, ks, folds, q: int, Z=None, intercept: bool = True, **opts):
+    """q-fold cross-validation over the model sizes ks, then the refit at the chosen size (iht_cv).
+
+    y: float64 CUDA [n]; folds: host uint8 [n] (fold of each subject, < q); Z as in fit. Returns
+    dict(mse (numpy [len(ks), q]), k_best, refit=dict as returned by fit).
+    """
+    torch = _torch()
+    o = default_opts(**opts)
+    yp = _dev(y, torch.float64, (geno.n,), "y")
+    cz = 0
+    zp = None
+    if Z is not None:
+        cz = Z.shape[0]
+        zp = _dev(Z, torch.float32, (cz, geno.n), "Z")
+    nc = cz + (1 if intercept else 0)
+    folds = np.ascontiguousarray(folds, dtype=np.uint8)
+    if folds.shape != (geno.n,):
+        raise ValueError(f"folds must have shape ({geno.n},)")
+    ks_arr = np.ascontiguousarray(ks, dtype=np.int32)
+    r = ks_arr.size
+    kmax = int(ks_arr.max()) if r else 1
+    dev = y.device
+    mse = np.zeros((r, q), dtype=np.float64)
+    kb = ctypes.c_int32(0)
+    sup = torch.empty(kmax, dtype=torch.int64, device=dev)
+    bS = torch.empty(kmax, dtype=torch.float64, device=dev)
+    bc = torch.empty(max(nc, 1), dtype=torch.float64, device=dev)
+    trace = torch.full((o.max_iter + 1,), float("nan"), dtype=torch.float64, device=dev)
+    nit = ctypes.c_int32(0)
+    rc = load().iht_cv(geno._h, yp, zp, cz, 1 if intercept else 0, folds.ctypes.data_as(ctypes.c_void_p), q,
+                       ks_arr.ctypes.data_as(ctypes.c_void_p), r, ctypes.byref(o),
+                       mse.ctypes.data_as(ctypes.c_void_p), ctypes.byref(kb), ctypes.c_void_p(sup.data_ptr()),
+                       ctypes.c_void_p(bS.data_ptr()), ctypes.c_void_p(bc.data_ptr()) if nc else None,
+                       ctypes.c_void_p(trace.data_ptr()), ctypes.byref(nit), _stream())
+    _check(rc, allow_warnings=True)
+    k = kb.value
+    it = nit.value
+    refit = dict(status=rc, support=sup[:k], beta_S=bS[:k], beta_cov=bc[:nc], loss_trace=trace[:it + 1], n_iter=it)
+    return dict(mse=mse, k_best=k, refit=refit)

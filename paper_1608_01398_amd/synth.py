@@ -147,6 +147,11 @@ def make_subset(n: int, size: int, seed: int) -> np.ndarray:
     return m
 
 
+def make_folds(n: int, q: int, seed: int) -> np.ndarray:
+    """Seeded balanced partition of n subjects into q folds: uint8 [n] fold index of each subject."""
+    return np.random.default_rng(seed).permutation(np.arange(n) % q).astype(np.uint8)
+
+
 def mask_to_bits(mask: np.ndarray) -> np.ndarray:
     """0/1 per-subject mask -> packed little-endian bit array (bit i%8 of byte i//8)."""
     return np.packbits(np.asarray(mask, dtype=np.uint8), bitorder="little")

@@ -327,6 +327,79 @@ def test_fit_deterministic():
         assert torch.equal(a[key], b[key])
 
 
+# ------------------------------------------------------------------ cross-validation
+
+def assert_cv_parity(got, ref, q):
+    assert got["k_best"] == ref["k_best"], (got["k_best"], ref["k_best"], got["mse"].mean(1), ref["mse"].mean(1))
+    np.testing.assert_allclose(got["mse"], ref["mse"], rtol=1e-9)
+    refit = {key: (val.cpu().numpy() if hasattr(val, "cpu") else val) for key, val in got["refit"].items()}
+    assert_fit_parity(refit, ref["refit"])
+
+
+@pytest.mark.parametrize("n,p,q,ks", [(1000, 5000, 5, list(range(1, 13))), (1001, 8193, 3, [1, 4, 9, 20]),
+                                      (333, 700, 2, [2, 3])])
+def test_cv_parity(n, p, q, ks):
+    """Held-out MSE table within 1e-9, the same chosen size, and the refit to the fit bar."""
+    prob = synth.make_problem("c1", seed=21, n=n, p=p)
+    folds = synth.make_folds(n, q, seed=22)
+    say(f"cv n={n} p={p} q={q} ks={ks}")
+    g = iht.Geno(prob["bed"], n)
+    got = iht.cv(g, dev(prob["y"]), ks, folds, q)
+    ref = oracle.cv(prob["bed"], n, prob["y"], ks, folds, q)
+    assert_cv_parity(got, ref, q)
+
+
+def test_cv_covariates_and_unbalanced_folds():
+    prob = synth.make_problem("c5", seed=23, n=1200, p=6000)
+    n = prob["n"]
+    folds = np.where(np.arange(n) < 100, 0, np.where(np.arange(n) < 700, 1, 2)).astype(np.uint8)
+    folds = folds[np.random.default_rng(24).permutation(n)]
+    ks = [4, 8, 12, 16]
+    say("cv covariates + unbalanced folds")
+    g = iht.Geno(prob["bed"], n)
+    got = iht.cv(g, dev(prob["y"]), ks, folds, 3, Z=dev(prob["Z"], torch.float32))
+    ref = oracle.cv(prob["bed"], n, prob["y"], ks, folds, 3, Z=prob["Z"])
+    assert_cv_parity(got, ref, 3)
+
+
+def test_cv_mixed_precision_same_choice():
+    """The matrix-core training fits (with their FP64 refinement) choose the same size and refit."""
+    prob = synth.make_problem("c1", seed=25, n=2000, p=6000)
+    n = prob["n"]
+    folds = synth.make_folds(n, 4, seed=26)
+    ks = list(range(2, 13))
+    say("cv mixed")
+    g = iht.Geno(prob["bed"], n)
+    got = iht.cv(g, dev(prob["y"]), ks, folds, 4, precision=iht.MIXED_I8)
+    ref = oracle.cv(prob["bed"], n, prob["y"], ks, folds, 4)
+    assert got["k_best"] == ref["k_best"]
+    np.testing.assert_allclose(got["mse"], ref["mse"], rtol=1e-6)
+    assert np.array_equal(got["refit"]["support"].cpu().numpy(), ref["refit"]["support"])
+
+
+def test_cv_rejects_bad_arguments():
+    prob = synth.make_problem("c1", seed=27, n=200, p=500)
+    n = prob["n"]
+    g = iht.Geno(prob["bed"], n)
+    y = dev(prob["y"])
+    ok = synth.make_folds(n, 3, seed=1)
+    bad = [(ok, 1, [1, 2]),                             # q < 2
+           (np.where(ok == 2, 1, ok), 3, [1, 2]),       # fold 2 empty
+           (np.zeros(n, np.uint8), 2, [1, 2]),          # fold 0 is every subject
+           (ok + 1, 3, [1, 2]),                         # fold index >= q
+           (ok, 3, [0, 2]),                             # k < 1
+           (ok, 3, [1, 501])]                           # k > p
+    for folds, q, ks in bad:
+        with pytest.raises(iht.IHTError) as e:
+            iht.cv(g, y, ks, folds, q)
+        assert e.value.code == iht.EINVAL
+    y2 = prob["y"].copy()
+    y2[5] = np.nan
+    with pytest.raises(iht.IHTError) as e:
+        iht.cv(g, dev(y2), [1, 2], ok, 3)
+    assert e.value.code == iht.ENONFINITE
+
+
 # ------------------------------------------------------------------ batched gradient (matrix cores)
 
 def fold_masks(n, q, seed):
