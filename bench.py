@@ -190,6 +190,7 @@ def main():
 
     if not args.no_batched and not args.small:
         out["batched"] = bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes)
+        out["cv"] = bench_cv(args, torch, iht, synth, prob, geno, y)
 
     if not args.no_cpu_baseline:
         from oracle import oracle
@@ -337,6 +338,47 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
                         support=res["support"][19, :solves[19][2]].cpu().numpy(),
                         beta_S=res["beta_S"][19, :solves[19][2]].cpu().numpy()),
     }
+
+
+def bench_cv(args, torch, iht, synth, prob, geno, y):
+    """Model selection as the paper runs it: 5-fold cross-validation over k = 1..20 (training stats,
+    100 training fits as one batch, held-out MSE, refit at the chosen k), timed end to end per
+    precision; the refit scored by precision, recall and estimated heritability against the
+    generator's causal SNPs."""
+    n = prob["n"]
+    q, ks = 5, list(range(1, 21))
+    folds = synth.make_folds(n, q, args.seed)
+    full = iht.Stats(geno)
+    causal = np.asarray(prob["causal"], dtype=np.int64)
+    vy = float(np.var(prob["y"]))
+    # h2 = Var(X_st beta) / Var(y) (Results, "Simulation"); the true model standardised by the sample
+    g_true = iht.predict(geno, full, torch.from_numpy(causal).cuda(),
+                         torch.from_numpy(np.asarray(prob["beta_true"], dtype=np.float64)).cuda())
+    h2_true = float(torch.var(g_true, unbiased=False).item()) / vy
+    res = {"workload": f"{q}-fold CV over k=1..{ks[-1]} on the resident n={n} x p={prob['p']} matrix, then the refit",
+           "folds": q, "path": [ks[0], ks[-1]], "h2_true": round(h2_true, 4)}
+    for name, prec in (("mixed_i8", iht.MIXED_I8), ("fp64", iht.FP64)):
+        iht.cv(geno, y, ks, folds, q, precision=prec)  # warm-up
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.batch_steps):
+            t0 = time.perf_counter()
+            cvr = iht.cv(geno, y, ks, folds, q, precision=prec)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        ct = float(np.median(times))
+        sup = cvr["refit"]["support"].cpu().numpy()
+        hit = int(np.intersect1d(sup, causal).size)
+        pred = iht.predict(geno, full, cvr["refit"]["support"], cvr["refit"]["beta_S"])
+        h2 = float(torch.var(pred, unbiased=False).item()) / vy
+        res[name] = {"ms": round(ct * 1e3, 2), "training_fits_per_s": round(q * len(ks) / ct, 1),
+                     "k_best": cvr["k_best"], "precision": round(hit / len(sup), 4),
+                     "recall": round(hit / len(causal), 4), "h2_est": round(h2, 4),
+                     "mean_mse": [round(float(x), 5) for x in cvr["mse"].mean(1)]}
+        log(f"cv {name}: {ct * 1e3:.1f} ms (median of {len(times)}), k_best {cvr['k_best']}, "
+            f"precision {hit}/{len(sup)}, recall {hit}/{len(causal)}, h2 est {h2:.3f} (true {h2_true:.3f})")
+    res["same_choice"] = res["mixed_i8"]["k_best"] == res["fp64"]["k_best"]
+    return res
 
 
 if __name__ == "__main__":

@@ -233,6 +233,25 @@ int iht_cv(const iht_geno *g, const double *y, const float *Z, int32_t cz, int32
            const int32_t *ks, int32_t r, const iht_opts *opts, double *mse, int32_t *k_best, int64_t *support, double *beta_S,
            double *beta_cov, double *loss_trace, int32_t *n_iter, void *stream);
 
+/*
+ * Prediction of every subject by a fitted model: out_i = sum_q x_st(i, support[q]) beta_S[q] +
+ * sum_c z_ic beta_cov[c] (+ beta_cov[cz] if intercept), with x_st standardised by the u_j, v_j of s
+ * (the X_st beta product of Methods, "Bandwidth optimization of IHT"; a missing dosage is
+ * mean-imputed, i.e. 0). The genetic part (cz = 0, intercept = 0) gives the estimated heritability
+ * Var(X beta*) / Var(y) of Results, "Simulation"; the subjects of a held-out fold give the MSE of
+ * Methods, "Model selection".
+ *   s          stats of this matrix whose u, v standardise the columns (e.g. the fit's training set).
+ *   support    device int64 [k], entries in [0, p) (any order; repeats add up).
+ *   beta_S     device FP64 [k].
+ *   k          0 <= k <= p.
+ *   Z, cz, intercept   as in iht_fit; beta_cov device FP64 [cz + intercept], or NULL if empty.
+ *   out        device FP64 [n] output, every subject (inside s's subject set or not).
+ * Errors: IHT_EINVAL (also for a support entry outside [0, p), found on the device; out is then
+ * undefined), IHT_ENOMEM, IHT_EDEVICE. Synchronises the stream.
+ */
+int iht_predict(const iht_geno *g, const iht_stats *s, const int64_t *support, const double *beta_S, int32_t k,
+                const float *Z, int32_t cz, int32_t intercept, const double *beta_cov, double *out, void *stream);
+
 const char *iht_status_str(int status);
 const char *iht_last_error(void);
 

@@ -407,6 +407,27 @@ done:
     return rc;
 }
 
+/* ---- prediction by a fitted model (Methods, Bandwidth optimization of IHT: the product X_st beta) ----
+ * out[i] = sum_t x_st(i, support[t]) beta_S[t] + sum_c Z[c][i] beta_cov[c] (+ beta_cov[cz] if intercept)
+ * for every subject, with the given u, v; a missing dosage contributes 0 (reading R7). */
+int iht_ref_predict(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, const double *u, const double *v,
+                    const int64_t *support, const double *beta_S, int32_t k, const float *Z, int32_t cz, int32_t intercept,
+                    const double *beta_cov, double *out) {
+    if (!bed || !u || !v || !out || n < 1 || p < 1 || k < 0 || (k > 0 && (!support || !beta_S)) || cz < 0 ||
+        (cz > 0 && !Z) || ((cz > 0 || intercept) && !beta_cov))
+        return REF_EINVAL;
+    for (int32_t t = 0; t < k; ++t)
+        if (support[t] < 0 || support[t] >= p) return REF_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int32_t t = 0; t < k; ++t) s += xst(bed, row_bytes, support[t], i, u, v) * beta_S[t];
+        for (int32_t c = 0; c < cz; ++c) s += (double)Z[(int64_t)c * n + i] * beta_cov[c];
+        if (intercept) s += beta_cov[cz];
+        out[i] = s;
+    }
+    return REF_OK;
+}
+
 /* ---- q-fold cross-validation over a path of model sizes (Methods, Model selection) ----
  * For fold f the training set is the subjects whose fold is not f: a subset solve (reading R12)
  * with its own u, v. For every k in ks the fitted model predicts the subjects of fold f,

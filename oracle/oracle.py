@@ -52,8 +52,9 @@ def lib():
         L.iht_ref_project.argtypes = [P, I64, I32, P, P]
         L.iht_ref_fit.argtypes = [P, I64, I64, I64, P, P, P, I32, I32, I32, D, I32, I32, D, D, P, P, P, P, P, P]
         L.iht_ref_cv.argtypes = [P, I64, I64, I64, P, I32, P, P, I32, I32, P, I32, D, I32, I32, D, D, P, P]
+        L.iht_ref_predict.argtypes = [P, I64, I64, I64, P, P, P, P, I32, P, I32, I32, P, P]
         for f in (L.iht_ref_decode, L.iht_ref_stats, L.iht_ref_standardize, L.iht_ref_gradient, L.iht_ref_project,
-                  L.iht_ref_fit, L.iht_ref_cv):
+                  L.iht_ref_fit, L.iht_ref_cv, L.iht_ref_predict):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -192,3 +193,24 @@ def cv(bed, n, y, ks, folds, q, Z=None, intercept=True, **opts):
         raise ValueError(f"iht_ref_cv: {rc}")
     refit = fit(bed, n, y, kb.value, Z=Z, intercept=intercept, **opts)
     return dict(mse=mse, k_best=kb.value, refit=refit)
+
+
+def predict(bed, n, u, v, support, beta_S, Z=None, intercept=False, beta_cov=None):
+    """Prediction of every subject by a fitted model (the X_st beta product of Methods, "Bandwidth
+    optimization of IHT"), standardised with u, v; plus covariates and intercept if given."""
+    bed_c, p, rb = _bed(bed)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    sup = np.ascontiguousarray(support, dtype=np.int64)
+    b = np.ascontiguousarray(beta_S, dtype=np.float64)
+    cz = 0
+    if Z is not None:
+        Z = np.ascontiguousarray(Z, dtype=np.float32)
+        cz = Z.shape[0]
+    bc = None if beta_cov is None else np.ascontiguousarray(beta_cov, dtype=np.float64)
+    out = np.empty(n)
+    rc = lib().iht_ref_predict(_p(bed_c), n, p, rb, _p(u), _p(v), _p(sup), _p(b), sup.size, _p(Z), cz,
+                               1 if intercept else 0, _p(bc), _p(out))
+    if rc < 0:
+        raise ValueError(f"iht_ref_predict: {rc}")
+    return out

@@ -131,6 +131,7 @@ struct iht_geno {
   DevBuf partial, state;
   SolveWork fit;
   DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
+  DevBuf pred_err;                                      // iht_predict's error word
 };
 
 struct iht_stats {
@@ -835,6 +836,29 @@ int iht_cv(const iht_geno* g, const double* y, const float* Z, int32_t cz, int32
   release();
   if (rc == IHT_ENONFINITE) return fail(IHT_ENONFINITE, "iht_cv: non-finite y or Z");
   return rc;
+}
+
+int iht_predict(const iht_geno* g, const iht_stats* s, const int64_t* support, const double* beta_S, int32_t k,
+                const float* Z, int32_t cz, int32_t intercept, const double* beta_cov, double* out, void* stream) {
+  if (!g || !s || !out || (k > 0 && (!support || !beta_S))) return fail(IHT_EINVAL, "iht_predict: NULL argument");
+  if (s->geno != g) return fail(IHT_EINVAL, "iht_predict: stats belong to another genotype handle");
+  const Layout& L = g->L;
+  if (k < 0 || k > L.p) return fail(IHT_EINVAL, "iht_predict: k out of range");
+  const int32_t icpt = intercept ? 1 : 0;
+  const int32_t nc = cz + icpt;
+  if (cz < 0 || (cz > 0 && !Z) || nc > kMaxUnpenalized || (nc > 0 && !beta_cov))
+    return fail(IHT_EINVAL, "iht_predict: bad covariates");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  iht_geno* G = const_cast<iht_geno*>(g);
+  HIPCHK(G->pred_err.ensure(4));
+  HIPCHK(launch_zero_u32(G->pred_err.as<uint32_t>(), 1, st));
+  HIPCHK(launch_predict(g->tiled.as<uint8_t>(), L, support, beta_S, k, s->u, s->v, Unpen{Z, cz, icpt}, beta_cov, out,
+                        G->pred_err.as<uint32_t>(), st));
+  uint32_t err = 0;
+  HIPCHK(hipMemcpyAsync(&err, G->pred_err.p, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (err) return fail(IHT_EINVAL, "iht_predict: support index outside [0, p)");
+  return IHT_OK;
 }
 
 }  // extern "C"

@@ -68,6 +68,11 @@ hipError_t cv_heldout_mse(const uint8_t* tiled, const Layout& L, const uint8_t* 
                           const double* beta_S, int64_t ldk, const double* beta_cov, int64_t ldc, const Unpen& U,
                           const double* y, const int64_t* fold_count, double* part, double* mse, int32_t* k_best,
                           hipStream_t st);
+// out [n] = X_st,S beta_S + A_C beta_cov for every subject, standardised with u, v; *err |= 1 if a
+// support entry lies outside [0, p) (the entry is skipped). err must be cleared beforehand.
+hipError_t launch_predict(const uint8_t* tiled, const Layout& L, const int64_t* support, const double* beta_S, int32_t k,
+                          const double* u, const double* v, const Unpen& U, const double* beta_cov, double* out,
+                          uint32_t* err, hipStream_t st);
 // slots[0 .. *count) = the solves in `phase`, ascending.
 hipError_t solve_slots(const FitState* fs, int32_t T, int32_t phase, int32_t* slots, int32_t* count, hipStream_t st);
 

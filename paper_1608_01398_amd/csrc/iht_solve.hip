@@ -855,16 +855,55 @@ hipError_t solve_slots(const FitState* fs, int32_t T, int32_t phase, int32_t* sl
 
 }  // namespace iht
 
-// ---------------------------------------------------------------------------- cross-validation
+// ---------------------------------------------------------------------------- prediction and cross-validation
 
 namespace iht {
 namespace {
 
+// Prediction of subject i by a fitted model: sum_q x_st(i, sup[q]) b[q] with the standardisation u,
+// v (a missing dosage is mean-imputed, i.e. 0 after standardising; entries of sup outside [0, p)
+// are skipped and reported through *bad), plus the unpenalised columns times bc.
+__device__ __forceinline__ double predict_subject(const uint8_t* __restrict__ tiled, int64_t n, int64_t p, int64_t p_pad,
+                                                  int64_t i, const int64_t* __restrict__ sup,
+                                                  const double* __restrict__ b, int32_t k, const double* __restrict__ u,
+                                                  const double* __restrict__ v, const Unpen& U,
+                                                  const double* __restrict__ bc, bool* bad) {
+  const int64_t tile = i / kTileSubjects;
+  const int grp = (int)((i % kTileSubjects) >> 2);
+  const int sh = 2 * (int)(i & 3);
+  double pred = 0.0;
+  for (int32_t q = 0; q < k; ++q) {
+    const int64_t j = sup[q];
+    if (j < 0 || j >= p) {
+      *bad = true;
+      continue;
+    }
+    const int bt = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
+    const int code = (tiled[(tile * p_pad + j) * kSegBytes + bt] >> sh) & 3;
+    const double x = (code == 1) ? 0.0 : v[j] * ((code == 0 ? 0.0 : (double)(code - 1)) - u[j]);
+    pred += x * b[q];
+  }
+  for (int c = 0; c < U.cz + U.icpt; ++c) pred += ucol(U, n, c, i) * bc[c];
+  return pred;
+}
+
+// out[i] = prediction of every subject i < n; err bit 0 is set if the support held an index outside [0, p).
+__global__ __launch_bounds__(256) void k_predict(const uint8_t* __restrict__ tiled, int64_t n, int64_t p, int64_t p_pad,
+                                                 const int64_t* __restrict__ sup, const double* __restrict__ b, int32_t k,
+                                                 const double* __restrict__ u, const double* __restrict__ v, Unpen U,
+                                                 const double* __restrict__ bc, double* __restrict__ out,
+                                                 uint32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  bool bad = false;
+  out[i] = predict_subject(tiled, n, p, p_pad, i, sup, b, k, u, v, U, bc, &bad);
+  if (bad) atomicOr(err, 1u);
+}
+
 // Held-out squared errors (Methods, "Model selection"): solve t = f * r + a was fitted on the
 // subjects outside fold f; every subject i of fold f is predicted with the solve's model,
-// standardised with its training u, v (a missing dosage is mean-imputed, i.e. 0 after
-// standardising), and (y_i - prediction)^2 is summed per block in a fixed order.
-__global__ __launch_bounds__(256) void k_cv_sqerr(const uint8_t* __restrict__ tiled, int64_t n, int64_t p_pad,
+// standardised with its training u, v, and (y_i - prediction)^2 is summed per block in a fixed order.
+__global__ __launch_bounds__(256) void k_cv_sqerr(const uint8_t* __restrict__ tiled, int64_t n, int64_t p, int64_t p_pad,
                                                   const uint8_t* __restrict__ folds, int32_t r, const BatchSolve* __restrict__ sv,
                                                   const int32_t* __restrict__ ks, const int64_t* __restrict__ support,
                                                   const double* __restrict__ beta_S, int64_t ldk,
@@ -872,24 +911,12 @@ __global__ __launch_bounds__(256) void k_cv_sqerr(const uint8_t* __restrict__ ti
                                                   const double* __restrict__ y, double* __restrict__ part) {
   const int t = blockIdx.y;
   const int f = t / r;
-  const int k = ks[t % r];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double e2 = 0.0;
   if (i < n && folds[i] == f) {
-    const double* u = sv[t].u;
-    const double* v = sv[t].v;
-    const int64_t tile = i / kTileSubjects;
-    const int grp = (int)((i % kTileSubjects) >> 2);
-    double pred = 0.0;
-    for (int q = 0; q < k; ++q) {
-      const int64_t j = support[(int64_t)t * ldk + q];
-      const int b = (grp - (int)(j & (kSegBytes - 1))) & (kSegBytes - 1);
-      const int code = (tiled[(tile * p_pad + j) * kSegBytes + b] >> (2 * (i & 3))) & 3;
-      const double x = (code == 1) ? 0.0 : v[j] * ((code == 0 ? 0.0 : (double)(code - 1)) - u[j]);
-      pred += x * beta_S[(int64_t)t * ldk + q];
-    }
-    for (int c = 0; c < U.cz + U.icpt; ++c) pred += ucol(U, n, c, i) * beta_cov[(int64_t)t * ldc + c];
-    const double d = y[i] - pred;
+    bool bad = false;  // the supports come from the solver: always inside [0, p)
+    const double d = y[i] - predict_subject(tiled, n, p, p_pad, i, support + (int64_t)t * ldk, beta_S + (int64_t)t * ldk,
+                                            ks[t], sv[t].u, sv[t].v, U, beta_cov + (int64_t)t * ldc, &bad);
     e2 = d * d;
   }
   __shared__ double sh[40];
@@ -930,11 +957,19 @@ hipError_t cv_heldout_mse(const uint8_t* tiled, const Layout& L, const uint8_t* 
                           const double* y, const int64_t* fold_count, double* part, double* mse, int32_t* k_best,
                           hipStream_t st) {
   const int32_t nblk = (int32_t)((L.n + 255) / 256);
-  hipLaunchKernelGGL(k_cv_sqerr, dim3((unsigned)nblk, (unsigned)(q * r)), dim3(256), 0, st, tiled, L.n, L.p_pad, folds, r, sv,
+  hipLaunchKernelGGL(k_cv_sqerr, dim3((unsigned)nblk, (unsigned)(q * r)), dim3(256), 0, st, tiled, L.n, L.p, L.p_pad, folds, r, sv,
                      ks_solve, support, beta_S, ldk, beta_cov, ldc, U, y, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cv_finish, dim3(1), dim3(64), 0, st, part, nblk, q, r, fold_count, ks_path, mse, k_best);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(const uint8_t* tiled, const Layout& L, const int64_t* support, const double* beta_S, int32_t k,
+                          const double* u, const double* v, const Unpen& U, const double* beta_cov, double* out,
+                          uint32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_predict, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, tiled, L.n, L.p, L.p_pad, support,
+                     beta_S, k, u, v, U, beta_cov, out, err);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
-           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_status_str", "iht_last_error")
+           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -67,9 +67,10 @@ def load():
                                 P, P, P, P, P, P, P]
     L.iht_cv.argtypes = [P, P, P, I32, I32, P, I32, P, I32, ctypes.POINTER(Opts), P, ctypes.POINTER(I32), P, P, P, P,
                          ctypes.POINTER(I32), P]
+    L.iht_predict.argtypes = [P, P, P, P, I32, P, I32, I32, P, P, P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
               "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_project_hint", "iht_fit",
-              "iht_fit_batch", "iht_cv"):
+              "iht_fit_batch", "iht_cv", "iht_predict"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -345,3 +346,26 @@ def cv(geno: Geno, y, ks, folds, q: int, Z=None, intercept: bool = True, **opts)
     it = nit.value
     refit = dict(status=rc, support=sup[:k], beta_S=bS[:k], beta_cov=bc[:nc], loss_trace=trace[:it + 1], n_iter=it)
     return dict(mse=mse, k_best=k, refit=refit)
+
+
+def predict(geno: Geno, stats: Stats, support, beta_S, Z=None, intercept: bool = False, beta_cov=None):
+    """Prediction of every subject, X_st[:, support] beta_S (+ covariates), standardised with stats (iht_predict).
+
+    support: int64 CUDA [k]; beta_S: float64 CUDA [k]; Z: float32 CUDA [c, n] or None; beta_cov: float64
+    CUDA [c + intercept] when covariates or the intercept are used. Returns float64 CUDA [n].
+    """
+    torch = _torch()
+    k = int(support.numel())
+    sp = _dev(support, torch.int64, (k,), "support") if k else None
+    bp = _dev(beta_S, torch.float64, (k,), "beta_S") if k else None
+    cz = 0
+    zp = None
+    if Z is not None:
+        cz = Z.shape[0]
+        zp = _dev(Z, torch.float32, (cz, geno.n), "Z")
+    nc = cz + (1 if intercept else 0)
+    cp = _dev(beta_cov, torch.float64, (nc,), "beta_cov") if nc else None
+    out = torch.empty(geno.n, dtype=torch.float64, device=support.device)
+    _check(load().iht_predict(geno._h, stats._h, sp, bp, k, zp, cz, 1 if intercept else 0, cp,
+                              ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out

@@ -327,6 +327,57 @@ def test_fit_deterministic():
         assert torch.equal(a[key], b[key])
 
 
+# ------------------------------------------------------------------ prediction
+
+@pytest.mark.parametrize("n,p,k,subset", [(1, 5, 3, None), (1001, 8193, 20, 700), (5000, 20_000, 300, None)])
+def test_predict_parity(n, p, k, subset):
+    say(f"predict n={n} p={p} k={k}")
+    bed, _ = synth.make_genotypes(n, p, seed=n + k)
+    m = synth.make_subset(n, subset, 8) if subset else None
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g, m)
+    u, v = oracle.stats(bed, n, m)
+    rng = np.random.default_rng(k)
+    sup = rng.choice(p, k, replace=False).astype(np.int64)
+    b = rng.standard_normal(k)
+    got = iht.predict(g, s, dev(sup, torch.int64), dev(b)).cpu().numpy()
+    ref = oracle.predict(bed, n, u, v, sup, b)
+    assert np.abs(got - ref).max() <= 1e-12 * max(np.abs(ref).max(), 1e-300)
+
+
+def test_predict_covariates_intercept_and_empty_support():
+    n, p = 777, 3000
+    bed, _ = synth.make_genotypes(n, p, seed=55)
+    Z = synth.make_covariates(n, 3, 55)
+    bc = np.array([0.25, -2.0, 1.0, 4.5])
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    u, v = oracle.stats(bed, n)
+    sup = np.array([2999, 0, 1500], dtype=np.int64)
+    b = np.array([1.0, -0.5, 2.0])
+    got = iht.predict(g, s, dev(sup, torch.int64), dev(b), Z=dev(Z, torch.float32), intercept=True,
+                      beta_cov=dev(bc)).cpu().numpy()
+    ref = oracle.predict(bed, n, u, v, sup, b, Z=Z, intercept=True, beta_cov=bc)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    empty = torch.empty(0, dtype=torch.int64, device="cuda")
+    got0 = iht.predict(g, s, empty, torch.empty(0, dtype=torch.float64, device="cuda"), intercept=True,
+                       beta_cov=dev(bc[3:])).cpu().numpy()
+    assert np.all(got0 == 4.5)
+
+
+def test_predict_rejects_out_of_range_support():
+    n, p = 100, 500
+    bed, _ = synth.make_genotypes(n, p, seed=56)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    for bad in ([0, p], [-1, 3]):
+        with pytest.raises(iht.IHTError) as e:
+            iht.predict(g, s, dev(np.array(bad, np.int64), torch.int64), dev(np.ones(2)))
+        assert e.value.code == iht.EINVAL
+    ok = iht.predict(g, s, dev(np.array([1, 2], np.int64), torch.int64), dev(np.ones(2)))
+    assert torch.isfinite(ok).all()
+
+
 # ------------------------------------------------------------------ cross-validation
 
 def assert_cv_parity(got, ref, q):

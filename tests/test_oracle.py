@@ -395,6 +395,59 @@ def test_backtracking_budget_exhaustion_reports_stalled():
     assert found
 
 
+# ------------------------------------------------------------------ prediction X_st beta (+ covariates)
+
+def test_predict_from_first_principles():
+    """Every subject, standardised with a subset's u, v (NumPy definition), covariates and intercept."""
+    n, p, k = 150, 90, 7
+    bed, _ = synth.make_genotypes(n, p, 41)
+    m = synth.make_subset(n, 100, 4)
+    u, v = oracle.stats(bed, n, m)
+    rng = np.random.default_rng(41)
+    sup = rng.choice(p, k, replace=False)  # any order
+    b = rng.standard_normal(k)
+    Z = synth.make_covariates(n, 2, 41)
+    bc = np.array([0.5, -1.5, 3.0])
+    dose = oracle.decode(bed, n).astype(np.float64)[sup]
+    obs = dose >= 0
+    tr = m.astype(bool)
+    uu = np.where(obs[:, tr], dose[:, tr], 0.0).sum(1) / obs[:, tr].sum(1)
+    imp = np.where(obs[:, tr], dose[:, tr], uu[:, None])
+    vv = 1.0 / imp.std(axis=1)
+    xs = np.where(obs, vv[:, None] * (dose - uu[:, None]), 0.0)
+    ref = b @ xs + Z.astype(np.float64).T @ bc[:2] + bc[2]
+    got = oracle.predict(bed, n, u, v, sup, b, Z=Z, intercept=True, beta_cov=bc)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_predict_genetic_part_has_zero_mean_over_its_subset():
+    """Standardised columns have mean 0 over the subjects that defined u (missing entries -> 0), so
+    the genetic prediction sums to 0 there; a monomorphic column (v = 0) contributes nothing."""
+    n, p = 333, 40
+    bed, _ = synth.make_genotypes(n, p, 42)
+    codes = synth.unpack_codes(bed, n)
+    codes[5] = synth.CODE_HET
+    bed = synth.pack_codes(codes)
+    m = synth.make_subset(n, 200, 7)
+    u, v = oracle.stats(bed, n, m)
+    sup = np.arange(p)
+    b = np.random.default_rng(1).standard_normal(p)
+    got = oracle.predict(bed, n, u, v, sup, b)
+    scale = np.abs(got).max()
+    assert abs(got[m.astype(bool)].sum()) <= 1e-12 * n * scale
+    only5 = oracle.predict(bed, n, u, v, [5], [7.0])
+    assert np.all(only5 == 0.0)
+
+
+def test_predict_rejects_bad_support():
+    n, p = 40, 30
+    bed, _ = synth.make_genotypes(n, p, 43)
+    u, v = oracle.stats(bed, n)
+    for sup in ([p], [-1], [0, p + 5]):
+        with pytest.raises(ValueError):
+            oracle.predict(bed, n, u, v, sup, np.ones(len(sup)))
+
+
 # ------------------------------------------------------------------ cross-validation (Model selection)
 
 def _numpy_heldout_mse(bed, n, y, folds, f, sup, beta_S, beta_cov):
