@@ -252,6 +252,70 @@ int iht_cv(const iht_geno *g, const double *y, const float *Z, int32_t cz, int32
 int iht_predict(const iht_geno *g, const iht_stats *s, const int64_t *support, const double *beta_S, int32_t k,
                 const float *Z, int32_t cz, int32_t intercept, const double *beta_cov, double *out, void *stream);
 
+/*
+ * Solve server with continuous batching (the request loop of many traits, subject subsets and
+ * model sizes over one resident matrix; the traits, folds and sizes of Methods, "Model selection",
+ * arriving over time). A server owns `slots` solve slots and a pool of per-subject-set statistics
+ * blocks, all allocated at creation inside hbm_budget bytes of device memory, so serving allocates
+ * nothing. Requests queue in submission order; iht_server_step admits the queued requests that
+ * fit (free slots for all their traits and a free statistics block) while the admitted ones
+ * iterate, advances every iterating solve by one turn of the solve loop (up to two iterations),
+ * and writes the solves that finished into their request's outputs. Each solve is exactly the
+ * iht_fit of its (subject set, trait, k) with the server's covariates and options, bitwise the same
+ * alone and in any mix of requests. Single-threaded: calls on one server must not overlap.
+ *
+ * iht_server_create
+ *   slots      1 <= slots <= 65535 solves in flight at once.
+ *   kmax       largest model size a request may ask for (1 <= kmax <= min(p, IHT_MAX_K)).
+ *   hbm_budget device bytes the server may hold: the slot state (p doubles of beta and gradient,
+ *              12 p bytes of top-k candidates and 16 kmax n bytes of support columns per slot, ...)
+ *              plus as many statistics blocks (16 p + 8 n bytes each) as fit, at most `slots`.
+ *              IHT_ENOMEM if not even one block fits beside the slot state.
+ *   Z, cz, intercept   covariates shared by every solve (device memory, as in iht_fit; must stay
+ *              valid for the server's life).
+ *   opts       as in iht_fit (max_iter >= 1); stream: the stream every launch goes to.
+ * iht_server_submit
+ *   subset     host uint8 [n] of 0/1 (NULL = every subject): the request's subject set.
+ *   Y          device FP64 traits, trait j at Y + j*ldy (ldy >= n); read when the request is
+ *              admitted, so it must stay valid until then.
+ *   T, ks      1 <= T <= slots traits; host int32 [T] model sizes, 1 <= ks[j] <= kmax;
+ *              kr = max ks[j].
+ *   support, beta_S   device [T][kr] outputs (rows as in iht_fit_batch, -1 / 0 past ks[j]).
+ *   beta_cov   device [T][cz + intercept] output, or NULL if empty.
+ *   loss_trace device [T][max_iter + 1] output: entries 0 .. n_iter[j] written.
+ *   n_iter, status   host int32 [T] outputs (IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED, IHT_ENONFINITE
+ *              per trait). Every output must stay valid until the request is done.
+ *   id         host int64 output: the request's id (0, 1, 2, ... in submission order).
+ * iht_server_step
+ *   completed  host int32 output: requests that finished in this step (their outputs are written
+ *              when the call returns). Synchronises the stream.
+ * iht_server_poll: *done = 1 once request `id` has finished, else 0.
+ * iht_server_info: occupancy and footprint.
+ * Errors: IHT_EINVAL (arguments; also an unknown id), IHT_ENOMEM, IHT_EDEVICE (after which the
+ * server must be destroyed). iht_server_destroy waits for the stream and frees everything.
+ */
+typedef struct iht_server iht_server;
+typedef struct {
+  int32_t slots;        /* solve slots                                  */
+  int32_t slots_busy;   /* slots holding an admitted solve              */
+  int32_t stats_blocks; /* statistics blocks (requests admitted at once) */
+  int64_t queued;       /* requests waiting for admission               */
+  int64_t running;      /* requests admitted and not finished           */
+  int64_t completed;    /* requests finished                            */
+  int64_t turns;        /* turns of the solve loop run so far           */
+  int64_t device_bytes; /* device memory the server holds               */
+} iht_server_info_t;
+
+int iht_server_create(const iht_geno *g, int32_t slots, int32_t kmax, int64_t hbm_budget, const float *Z, int32_t cz,
+                      int32_t intercept, const iht_opts *opts, void *stream, iht_server **out);
+int iht_server_submit(iht_server *s, const uint8_t *subset, const double *Y, int64_t ldy, int32_t T, const int32_t *ks,
+                      int64_t *support, double *beta_S, double *beta_cov, double *loss_trace, int32_t *n_iter,
+                      int32_t *status, int64_t *id);
+int iht_server_step(iht_server *s, int32_t *completed);
+int iht_server_poll(const iht_server *s, int64_t id, int32_t *done);
+int iht_server_info(const iht_server *s, iht_server_info_t *info);
+int iht_server_destroy(iht_server *s);
+
 const char *iht_status_str(int status);
 const char *iht_last_error(void);
 

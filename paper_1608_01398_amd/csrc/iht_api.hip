@@ -13,137 +13,9 @@
 #include <string>
 #include <vector>
 
-#include "iht.h"
-#include "iht_batch.h"
-#include "iht_internal.h"
-#include "iht_solve.h"
+#include "iht_host.h"
 
 using namespace iht;
-
-namespace {
-
-thread_local std::string g_last_error;
-
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-int hip_fail(hipError_t e, const char* what) {
-  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
-  return e == hipErrorOutOfMemory ? IHT_ENOMEM : IHT_EDEVICE;
-}
-
-#define HIPCHK(expr)                                  \
-  do {                                                \
-    hipError_t e_ = (expr);                           \
-    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-  } while (0)
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  // grows to at least b bytes (contents are lost when it grows); *fresh tells whether it did
-  hipError_t ensure(size_t b, bool* fresh = nullptr) {
-    if (fresh) *fresh = false;
-    if (b <= bytes && p) return hipSuccess;
-    release();
-    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
-    if (e == hipSuccess) {
-      bytes = b;
-      if (fresh) *fresh = true;
-    }
-    return e;
-  }
-  template <class T>
-  T* as() const {
-    return reinterpret_cast<T*>(p);
-  }
-};
-
-Layout make_layout(int64_t n, int64_t p) {
-  Layout L;
-  L.n = n;
-  L.p = p;
-  L.ntiles = (n + kTileSubjects - 1) / kTileSubjects;
-  L.n_pad = L.ntiles * kTileSubjects;
-  L.p_pad = (p + kSnpAlign - 1) / kSnpAlign * kSnpAlign;
-  return L;
-}
-
-// Device work area for `rows` top-k problems over p entries. The per-row counters and histogram
-// start zeroed and are self-resetting; the error words are cleared before each use.
-struct TopkArea {
-  DevBuf small;  // rows x kTopkRowWords
-  DevBuf cand;   // rows x cap x (8 + 4) bytes
-  int64_t cap = 0;
-  int32_t rows = 0;
-  int ensure(int64_t p, int32_t nrows, hipStream_t st) {
-    if (nrows > rows || !small.p) {
-      bool fresh = false;
-      const size_t words = (size_t)nrows * kTopkRowWords;
-      HIPCHK(small.ensure(words * 4, &fresh));
-      if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)words, st));
-      rows = nrows;
-    }
-    const int64_t want = std::max<int64_t>(p, 16384);  // also holds the two-pass candidates
-    if (want > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
-      cap = std::max(cap, want);
-      HIPCHK(cand.ensure((size_t)rows * (size_t)cap * (sizeof(uint64_t) + sizeof(int32_t))));
-    }
-    return IHT_OK;
-  }
-  uint64_t* cand_key() const { return cand.as<uint64_t>(); }
-  int32_t* cand_idx() const { return reinterpret_cast<int32_t*>(cand.as<char>() + (size_t)rows * (size_t)cap * sizeof(uint64_t)); }
-};
-
-}  // namespace
-
-// Device state of a set of solves (grown on demand, reused by later fits on the same genotype
-// handle), plus the pinned host copy of their FitStates.
-namespace {
-struct SolveWork {
-  DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv;
-  DevBuf r8, scale, rsum, slots, count;
-  TopkArea topk;
-  FitState* host = nullptr;  // pinned: the solves' FitStates as last read
-  int32_t host_cap = 0;
-  char* stage = nullptr;  // pinned: ks, the BatchSolves and the top-k error words of a call
-  size_t stage_cap = 0;
-  ~SolveWork() {
-    if (host) (void)hipHostFree(host);
-    if (stage) (void)hipHostFree(stage);
-  }
-};
-}  // namespace
-
-struct iht_geno {
-  int device = 0;
-  Layout L{};
-  DevBuf tiled;
-  // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
-  DevBuf partial, state;
-  SolveWork fit;
-  DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
-  DevBuf pred_err;                                      // iht_predict's error word
-};
-
-struct iht_stats {
-  const iht_geno* geno = nullptr;
-  int64_t nT = 0;
-  // one allocation: u [p], v [p], the FP64 subject mask [n_pad], then the subject bits [ntiles]
-  DevBuf buf;
-  double* u = nullptr;
-  double* v = nullptr;
-  double* mask = nullptr;
-  uint32_t* mask_bits = nullptr;
-};
 
 extern "C" {
 
@@ -159,7 +31,7 @@ void iht_opts_default(iht_opts* o) {
   o->polish_iter = 200;
 }
 
-const char* iht_last_error(void) { return g_last_error.c_str(); }
+const char* iht_last_error(void) { return last_error_text().c_str(); }
 
 const char* iht_status_str(int s) {
   switch (s) {
@@ -366,7 +238,7 @@ static int project(const char* who, const double* w, int64_t p, int32_t k, const
   if (!Ap) return fail(IHT_ENOMEM, std::string(who) + ": work area");
   TopkArea& A = *Ap;
   if (int rc = A.ensure(p, 1, st)) return rc;
-  HIPCHK(launch_topk_clear_errors(A.small.as<uint32_t>(), 1, st));
+  HIPCHK(launch_topk_clear_errors(A.small.as<uint32_t>(), 1, nullptr, st));
   DevBuf vals;
   HIPCHK(vals.ensure((size_t)k * 8));
   TopkJob J{};
@@ -437,226 +309,37 @@ struct FitArgs {
   hipStream_t st;
 };
 
-int check_opts(const iht_opts& o, const char* who) {
-  if (o.max_iter < 0 || o.max_backtrack < 0 || !(o.c > 0.0 && o.c < 1.0) || !(o.shrink > 0.0 && o.shrink < 1.0) ||
-      !(o.tol >= 0.0) || !(o.mixed_tol >= 0.0) || o.polish_iter < 0 ||
-      (o.precision != IHT_FP64 && o.precision != IHT_FP32 && o.precision != IHT_MIXED_I8))
-    return fail(IHT_EINVAL, std::string(who) + ": bad options");
-  return IHT_OK;
-}
-
 int run_fit(const FitArgs& A) {
   const iht_geno* g = A.g;
-  const Layout& L = g->L;
   const int32_t T = A.T;
-  const iht_opts& o = A.o;
-  hipStream_t st = A.st;
-  SolveWork& W = const_cast<iht_geno*>(g)->fit;
   int32_t kmax = 0;
   for (int32_t t = 0; t < T; ++t) kmax = std::max(kmax, A.ks[t]);
   const int32_t nc = A.U.cz + A.U.icpt;
-  const size_t Tz = (size_t)T, kz = (size_t)kmax;
-
-  std::vector<BatchSolve> sv(Tz);
-  for (int32_t t = 0; t < T; ++t)
+  std::vector<BatchSolve> sv((size_t)T);
+  std::vector<OutRow> rows((size_t)T);
+  for (int32_t t = 0; t < T; ++t) {
     sv[t] = BatchSolve{A.stats[t]->u, A.stats[t]->v, A.stats[t]->mask, A.stats[t]->nT};
-
-  HIPCHK(W.beta.ensure(Tz * L.p * 8));
-  HIPCHK(W.g.ensure(Tz * L.p * 8));
-  HIPCHK(W.partial.ensure(gradient_work_bytes(L)));
-  HIPCHK(W.r.ensure(Tz * L.n_pad * 8));
-  HIPCHK(W.rc.ensure(Tz * L.n_pad * 8));
-  HIPCHK(W.S.ensure(Tz * kz * 8));
-  HIPCHK(W.Sp.ensure(Tz * kz * 8));
-  HIPCHK(W.betap.ensure(Tz * kz * 8));
-  HIPCHK(W.X.ensure(Tz * 2 * kz * L.n_pad * 8));
-  HIPCHK(W.bc.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.bcp.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.gc.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.fs.ensure(Tz * sizeof(FitState)));
-  const int32_t nb = solve_subject_blocks(L.n), pst = solve_partial_stride(nc);
-  HIPCHK(W.part.ensure(Tz * (size_t)nb * (size_t)pst * 8));
-  HIPCHK(W.pmu.ensure(Tz * (size_t)nb * 8));
-  HIPCHK(W.ysum.ensure(Tz * kYsumStride * 8));
-  HIPCHK(W.pw.ensure(Tz * 3 * (kz + kMaxUnpenalized) * 8));
-  HIPCHK(W.ks.ensure(Tz * 4));
-  HIPCHK(W.sv.ensure(Tz * sizeof(BatchSolve)));
-  if (int rc = W.topk.ensure(L.p, T, st)) return rc;
-  const bool mixed = o.precision == IHT_MIXED_I8;
-  if (mixed) {
-    HIPCHK(W.r8.ensure(batch_r8_bytes(L, T)));
-    HIPCHK(W.scale.ensure((size_t)batch_t_pad(T) * 8));
-    HIPCHK(W.rsum.ensure((size_t)batch_t_pad(T) * 8));
-    HIPCHK(W.slots.ensure(Tz * 4));
-    HIPCHK(W.count.ensure(4));
+    rows[t] = OutRow{A.support + (size_t)t * kmax, A.beta_S + (size_t)t * kmax,
+                     A.beta_cov ? A.beta_cov + (size_t)t * nc : nullptr, nullptr, kmax};
   }
-  if (W.host_cap < T) {
-    if (W.host) (void)hipHostFree(W.host);
-    W.host = nullptr;
-    W.host_cap = 0;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.host), Tz * sizeof(FitState), hipHostMallocDefault));
-    W.host_cap = T;
-  }
-  // small host inputs and outputs go through pinned memory (asynchronous copies; the call
-  // synchronises before it returns, so the area is free again at the next call)
-  const size_t o_sv = (Tz * 4 + 15) / 16 * 16, o_err = o_sv + (Tz * sizeof(BatchSolve) + 15) / 16 * 16;
-  const size_t stage_bytes = o_err + Tz * 4;
-  if (W.stage_cap < stage_bytes) {
-    if (W.stage) (void)hipHostFree(W.stage);
-    W.stage = nullptr;
-    W.stage_cap = 0;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&W.stage), stage_bytes, hipHostMallocDefault));
-    W.stage_cap = stage_bytes;
-  }
-  std::memcpy(W.stage, A.ks, Tz * 4);
-  std::memcpy(W.stage + o_sv, sv.data(), Tz * sizeof(BatchSolve));
-  uint32_t* terr = reinterpret_cast<uint32_t*>(W.stage + o_err);
-  HIPCHK(hipMemcpyAsync(W.ks.p, W.stage, Tz * 4, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(W.sv.p, W.stage + o_sv, Tz * sizeof(BatchSolve), hipMemcpyHostToDevice, st));
-
-  SolveSet Q{};
-  Q.T = T;
-  Q.kmax = kmax;
-  Q.n = L.n;
-  Q.n_pad = L.n_pad;
-  Q.p = L.p;
-  Q.p_pad = L.p_pad;
-  Q.sv = W.sv.as<BatchSolve>();
-  Q.ks = W.ks.as<int32_t>();
-  Q.Y = A.Y;
-  Q.ldy = A.ldy;
-  Q.U = A.U;
-  Q.beta = W.beta.as<double>();
-  Q.g = W.g.as<double>();
-  Q.r = W.r.as<double>();
-  Q.rc = W.rc.as<double>();
-  Q.S = W.S.as<int64_t>();
-  Q.Sp = W.Sp.as<int64_t>();
-  Q.betap = W.betap.as<double>();
-  Q.X = W.X.as<double>();
-  Q.bc = W.bc.as<double>();
-  Q.bcp = W.bcp.as<double>();
-  Q.gc = W.gc.as<double>();
-  Q.fs = W.fs.as<FitState>();
-  Q.trace = A.trace;
-  Q.ldt = (int64_t)o.max_iter + 1;
-  Q.nb = nb;
-  Q.pst = pst;
-  Q.part = W.part.as<double>();
-  Q.pmu = W.pmu.as<double>();
-  Q.ysum = W.ysum.as<double>();
-  Q.pw = W.pw.as<double>();
-
-  TopkJob J{};
-  J.beta = Q.beta;
-  J.g = Q.g;
-  J.ld = L.p;
-  J.fs = Q.fs;
-  J.ks = Q.ks;
-  J.kmax = kmax;
-  J.ldo = kmax;
-  J.small = W.topk.small.as<uint32_t>();
-  J.cand_key = W.topk.cand_key();
-  J.cand_idx = W.topk.cand_idx();
-  J.cap = W.topk.cap;
-  const uint8_t* tiled = g->tiled.as<uint8_t>();
-  const double tol_main = o.precision == IHT_FP64 ? o.tol : std::max(o.tol, o.mixed_tol);
-  FitState* h = W.host;
-
-  // gradient of the solves in `phase` (kPhaseInit: every solve with finite inputs; kPhaseGo: those
-  // whose proposal was accepted)
-  auto gradient = [&](int32_t phase) -> int {
-    if (mixed) {
-      HIPCHK(solve_slots(Q.fs, T, phase, W.slots.as<int32_t>(), W.count.as<int32_t>(), st));
-      HIPCHK(launch_gradient_batch(tiled, L, Q.r, L.n_pad, T, Q.sv, W.slots.as<int32_t>(), W.count.as<int32_t>(),
-                                   W.r8.as<int8_t>(), W.scale.as<double>(), W.rsum.as<double>(), Q.g, L.p, st));
-      return IHT_OK;
-    }
-    for (int32_t t = 0; t < T; ++t)
-      HIPCHK(launch_gradient(tiled, L, Q.r + (size_t)t * L.n_pad, sv[t].mask, sv[t].nT, sv[t].u, sv[t].v, Q.fs + t,
-                             o.precision, Q.g + (size_t)t * L.p, W.partial.as<double>(),
-                             phase == kPhaseInit ? nullptr : &Q.fs[t].go, st, Q.rc + (size_t)t * L.n_pad));
-    return IHT_OK;
-  };
-  // proposal of the solves in `phase`: projection, then columns, backtracking test and (for the
-  // accepted ones) residual, loss and centred residual
-  auto propose = [&](int32_t phase) -> int {
-    J.phase = phase;
-    J.out = Q.Sp;
-    J.vals = Q.betap;
-    J.prev = Q.S;  // the current support bounds the new k-th largest |w| from below
-    J.ldprev = kmax;
-    HIPCHK(launch_topk(J, L.p, T, st));
-    HIPCHK(solve_decode(tiled, Q, 1, phase, st));
-    HIPCHK(solve_check_residual(Q, phase, o.c, o.max_backtrack, st));
-    return IHT_OK;
-  };
-  // gradient of the accepted proposals, commit, and the next step size
-  auto tail = [&]() -> int {
-    if (int rc = gradient(kPhaseGo)) return rc;
-    HIPCHK(solve_commit_mu(Q, 1, tol_main, o.max_iter, st));
-    return IHT_OK;
-  };
-  auto read_states = [&]() -> int {
-    HIPCHK(hipMemcpyAsync(h, Q.fs, Tz * sizeof(FitState), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return IHT_OK;
-  };
-  auto count_if = [&](auto pred) {
-    int32_t c = 0;
-    for (int32_t t = 0; t < T; ++t) c += pred(h[t]) ? 1 : 0;
-    return c;
-  };
-
-  // initial state: beta = 0, r = y on each subject set, g = A^T r, S = top-k |g| (mu = 1, beta = 0),
-  // then the first step size
-  HIPCHK(launch_topk_clear_errors(J.small, T, st));
-  HIPCHK(solve_init(Q, o.max_iter, st));
-  HIPCHK(solve_residual0(Q, st));
-  if (int rc = gradient(kPhaseInit)) return rc;
-  J.phase = kPhaseInit;
-  J.out = Q.S;
-  J.vals = nullptr;
-  J.prev = nullptr;
-  HIPCHK(launch_topk(J, L.p, T, st));
-  HIPCHK(solve_decode(tiled, Q, 0, kPhaseInit, st));
-  HIPCHK(solve_commit_mu(Q, 0, tol_main, o.max_iter, st));
-  if (int rc = read_states()) return rc;
-
-  // The first proposal, then turns of: halving rounds for the solves whose proposal was rejected,
-  // and kAhead speculative iterations (gradient, commit + next step size, next proposal) per read
-  // of the flags. Every kernel is gated per solve on the device flags, and a proposal step is
-  // idempotent for a solve waiting for a halving (same step size, same proposal, same rejection),
-  // so running ahead never changes a result; solves that finished skip the extra launches.
-  constexpr int kAhead = 2;
-  if (int rc = propose(kPhaseActive)) return rc;
-  if (int rc = read_states()) return rc;
-  for (int32_t turn = 0; turn <= o.max_iter && count_if([](const FitState& f) { return f.active != 0; }) > 0; ++turn) {
-    while (count_if([](const FitState& f) { return f.active != 0 && f.need_bt != 0; }) > 0) {
-      HIPCHK(solve_shrink(Q, o.shrink, st));
-      if (int rc = propose(kPhaseBacktrack)) return rc;
-      if (int rc = read_states()) return rc;
-    }
-    for (int a = 0; a < kAhead; ++a) {
-      if (int rc = tail()) return rc;
-      if (int rc = propose(kPhaseActive)) return rc;
-    }
-    if (int rc = read_states()) return rc;
-  }
-  if (o.precision != IHT_FP64 && o.polish_iter > 0) HIPCHK(solve_polish(Q, o.tol, o.polish_iter, st));
-  HIPCHK(solve_output(Q, A.support, A.beta_S, A.beta_cov, kmax, nc, st));
-  HIPCHK(hipMemcpy2DAsync(terr, 4, J.small + kTopkErrorWord, (size_t)kTopkRowWords * 4, 4, Tz, hipMemcpyDeviceToHost, st));
-  if (int rc = read_states()) return rc;
+  Engine E;
+  if (int rc = E.setup(g, &const_cast<iht_geno*>(g)->fit, T, kmax, A.U, A.Y, A.ldy, A.trace, A.o, A.st)) return rc;
+  if (int rc = E.admit(A.ks, sv.data(), nullptr)) return rc;
+  for (int32_t turn = 0; turn <= A.o.max_iter && E.count_active() > 0; ++turn)
+    if (int rc = E.turn()) return rc;
+  if (int rc = E.retire(nullptr, rows.data())) return rc;
   int worst = IHT_OK;
   for (int32_t t = 0; t < T; ++t) {
-    if (terr[t] && !h[t].nonfinite)
-      return fail(IHT_EDEVICE, "internal top-k error (solve " + std::to_string(t) + ", flags " + std::to_string(terr[t]) + ")");
-    A.n_iter[t] = h[t].iter;
-    A.status[t] = h[t].status;
-    if (h[t].status < 0)
-      worst = std::min(worst, h[t].status);
+    const FitState& f = E.state(t);
+    if (E.topk_error(t) && !f.nonfinite)
+      return fail(IHT_EDEVICE, "internal top-k error (solve " + std::to_string(t) + ", flags " +
+                                   std::to_string(E.topk_error(t)) + ")");
+    A.n_iter[t] = f.iter;
+    A.status[t] = f.status;
+    if (f.status < 0)
+      worst = std::min(worst, f.status);
     else if (worst >= 0)
-      worst = std::max(worst, h[t].status);
+      worst = std::max(worst, f.status);
   }
   return worst;
 }

@@ -807,9 +807,9 @@ __global__ void k_zero_u32(uint32_t* __restrict__ x, int64_t n) {
   if (i < n) x[i] = 0u;
 }
 
-__global__ void k_topk_clear_errors(uint32_t* __restrict__ small, int32_t rows) {
+__global__ void k_topk_clear_errors(uint32_t* __restrict__ small, int32_t rows, const int32_t* __restrict__ flags) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < rows) {  // words that kernels update with device-scope atomics are cleared with one
+  if (t < rows && (!flags || flags[t])) {  // words that kernels update with device-scope atomics are cleared with one
     (void)atomicExch(&small[t * kTopkRowWords + kTopkErrorWord], 0u);
     (void)atomicExch(&small[t * kTopkRowWords + kTopkBins0 + 4], 0u);  // filtered-candidate count
   }
@@ -903,8 +903,8 @@ hipError_t launch_zero_u32(uint32_t* x, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, hipStream_t st) {
-  hipLaunchKernelGGL(k_topk_clear_errors, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, small, rows);
+hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, const int32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_topk_clear_errors, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, small, rows, flags);
   return hipGetLastError();
 }
 

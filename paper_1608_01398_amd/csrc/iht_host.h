@@ -1,0 +1,227 @@
+// iht_host.h -- host runtime pieces shared by the entry points, the solve engine and the solve
+// server: error reporting, device buffers, the handle types, and the solve engine.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "iht.h"
+#include "iht_batch.h"
+#include "iht_internal.h"
+#include "iht_solve.h"
+
+namespace iht {
+
+// The message behind iht_last_error (one per host thread).
+inline std::string& last_error_text() {
+  static thread_local std::string s;
+  return s;
+}
+
+inline int fail(int code, const std::string& msg) {
+  last_error_text() = msg;
+  return code;
+}
+
+inline int hip_fail(hipError_t e, const char* what) {
+  last_error_text() = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? IHT_ENOMEM : IHT_EDEVICE;
+}
+
+#define HIPCHK(expr)                                       \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return ::iht::hip_fail(e_, #expr); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // grows to at least b bytes (contents are lost when it grows); *fresh tells whether it did
+  hipError_t ensure(size_t b, bool* fresh = nullptr) {
+    if (fresh) *fresh = false;
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, std::max<size_t>(b, 256));
+    if (e == hipSuccess) {
+      bytes = b;
+      if (fresh) *fresh = true;
+    }
+    return e;
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+// Pinned host memory, grown on demand (contents are lost when it grows).
+struct PinnedBuf {
+  char* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(b, 256), hipHostMallocDefault);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+};
+
+inline Layout make_layout(int64_t n, int64_t p) {
+  Layout L;
+  L.n = n;
+  L.p = p;
+  L.ntiles = (n + kTileSubjects - 1) / kTileSubjects;
+  L.n_pad = L.ntiles * kTileSubjects;
+  L.p_pad = (p + kSnpAlign - 1) / kSnpAlign * kSnpAlign;
+  return L;
+}
+
+// Device work area for `rows` top-k problems over p entries. The per-row counters and histogram
+// start zeroed and are self-resetting; the error words are cleared before each use.
+struct TopkArea {
+  DevBuf small;  // rows x kTopkRowWords
+  DevBuf cand;   // rows x cap x (8 + 4) bytes
+  int64_t cap = 0;
+  int32_t rows = 0;
+  int ensure(int64_t p, int32_t nrows, hipStream_t st) {
+    if (nrows > rows || !small.p) {
+      bool fresh = false;
+      const size_t words = (size_t)nrows * kTopkRowWords;
+      HIPCHK(small.ensure(words * 4, &fresh));
+      if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)words, st));
+      rows = nrows;
+    }
+    const int64_t want = std::max<int64_t>(p, 16384);  // also holds the two-pass candidates
+    if (want > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
+      cap = std::max(cap, want);
+      HIPCHK(cand.ensure((size_t)rows * (size_t)cap * (sizeof(uint64_t) + sizeof(int32_t))));
+    }
+    return IHT_OK;
+  }
+  uint64_t* cand_key() const { return cand.as<uint64_t>(); }
+  int32_t* cand_idx() const {
+    return reinterpret_cast<int32_t*>(cand.as<char>() + (size_t)rows * (size_t)cap * sizeof(uint64_t));
+  }
+};
+
+// Device state of a set of solve slots (grown on demand and reused), plus the pinned host areas
+// through which the engine exchanges the slots' small inputs and flags.
+struct SolveWork {
+  DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv, flags, rows;
+  DevBuf r8, scale, rsum, slots, count;
+  TopkArea topk;
+  PinnedBuf host;   // the slots' FitStates as last read
+  PinnedBuf stage;  // ks, subject sets, flags, output rows and top-k error words
+};
+
+int check_opts(const iht_opts& o, const char* who);
+
+// The solve loop of Methods, eq. (ihta) with the normalised step and the omega rule of "IHT step
+// sizes", over T slots sharing one genotype matrix. Every per-slot kernel is gated on the slot's
+// device flags, so slots at different points of their solve share each launch; a slot is admitted
+// (its initial state computed) without disturbing the others, advanced turn by turn, and retired
+// (refined and written out) on its own. All arithmetic runs in the device kernels; the host only
+// orders the launches and reads the slots' flags once per turn.
+//
+// A turn: halving rounds for the slots whose proposal was rejected, then kAhead speculative
+// iterations [gradient of the accepted proposals, commit + next step size, next proposal (top-k
+// warm-started by S), column decode, residual + backtracking test + decision]. A proposal step is
+// idempotent for a slot waiting for a halving (same step size, same proposal, same rejection), so
+// running ahead never changes a result; slots that finished skip the extra launches.
+class Engine {
+ public:
+  static constexpr int kAhead = 2;
+
+  // Device state of T slots with model sizes up to kmax (allocated in W). Slot t reads its trait
+  // at Y + t * ldy and keeps its loss trace at trace + t * (max_iter + 1).
+  int setup(const iht_geno* g, SolveWork* W, int32_t T, int32_t kmax, const Unpen& U, const double* Y, int64_t ldy,
+            double* trace, const iht_opts& o, hipStream_t st);
+  // Admits the slots with admit[t] != 0 (every slot if admit is NULL): ks and sv (host [T]) give
+  // every slot's model size and subject set; the admitted ones get beta = 0, the initial residual,
+  // gradient, support and step size, and their first proposal. The other slots are untouched.
+  // Ends with the states read.
+  int admit(const int32_t* ks, const BatchSolve* sv, const uint8_t* admit);
+  // One turn of every slot still iterating; ends with the states read.
+  int turn();
+  // Writes out the slots with flags[t] != 0 (every slot if NULL): the FP64 refinement after a
+  // reduced-precision solve, then the outputs into rows[t] (host [T]). Ends with the states and
+  // the top-k error words read.
+  int retire(const uint8_t* flags, const OutRow* rows);
+
+  const FitState& state(int32_t t) const { return h_[t]; }
+  uint32_t topk_error(int32_t t) const { return terr_[t]; }
+  int32_t count_active() const;
+  int32_t slots() const { return T_; }
+  int32_t kmax() const { return kmax_; }
+
+ private:
+  int gradient(int32_t phase);
+  int propose(int32_t phase);
+  int read_states();
+  int upload_flags(const uint8_t* flags, const int32_t** dev);
+
+  const iht_geno* g_ = nullptr;
+  SolveWork* W_ = nullptr;
+  Layout L_{};
+  iht_opts o_{};
+  hipStream_t st_ = nullptr;
+  int32_t T_ = 0, kmax_ = 0, nc_ = 0;
+  bool mixed_ = false;
+  double tol_main_ = 0.0;
+  SolveSet Q_{};
+  TopkJob J_{};
+  // pinned host views (inside W->host and W->stage)
+  FitState* h_ = nullptr;
+  int32_t* ks_h_ = nullptr;
+  BatchSolve* sv_h_ = nullptr;
+  int32_t* flags_h_ = nullptr;
+  OutRow* rows_h_ = nullptr;
+  uint32_t* terr_ = nullptr;
+  std::vector<uint8_t> launch_;  // slots that get a per-slot gradient launch (FP64 / FP32 passes)
+};
+
+}  // namespace iht
+
+struct iht_geno {
+  int device = 0;
+  iht::Layout L{};
+  iht::DevBuf tiled;
+  // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
+  iht::DevBuf partial, state;
+  iht::SolveWork fit;
+  iht::DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
+  iht::DevBuf pred_err;                                      // iht_predict's error word
+};
+
+struct iht_stats {
+  const iht_geno* geno = nullptr;
+  int64_t nT = 0;
+  // one allocation: u [p], v [p], the FP64 subject mask [n_pad], then the subject bits [ntiles]
+  iht::DevBuf buf;
+  double* u = nullptr;
+  double* v = nullptr;
+  double* mask = nullptr;
+  uint32_t* mask_bits = nullptr;
+};

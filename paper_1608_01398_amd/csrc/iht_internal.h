@@ -60,16 +60,29 @@ struct FitState {
   int32_t status;   // IHT_OK / IHT_NOT_CONVERGED / IHT_STALLED / IHT_ENONFINITE
   int32_t xcur;     // which of the solve's two column caches holds the columns of S
   int32_t polish_steps;
+  int32_t fresh;   // admitted, before its first proposal: the initial state is computed for it
+  int32_t retire;  // finished and being written out (refinement and outputs run for it)
 };
 
-// Launch phases of the per-solve kernels: every solve; solves with finite inputs (the initial
-// gradient and support); solves still iterating; those whose proposal needs a halving; those whose
-// proposal was accepted.
-enum : int32_t { kPhaseAll = 0, kPhaseActive = 1, kPhaseBacktrack = 2, kPhaseGo = 3, kPhaseInit = 4 };
+// Launch phases of the per-solve kernels: every solve; solves still iterating; those whose
+// proposal needs a halving; those whose proposal was accepted; newly admitted solves with finite
+// inputs (the initial residual, gradient and support); newly admitted solves still iterating (the
+// first step size and proposal); solves being written out.
+enum : int32_t {
+  kPhaseAll = 0,
+  kPhaseActive = 1,
+  kPhaseBacktrack = 2,
+  kPhaseGo = 3,
+  kPhaseInit = 4,
+  kPhaseFresh = 5,
+  kPhaseRetire = 6
+};
 
 __device__ __forceinline__ bool fs_selected(const FitState* fs, int32_t phase) {
   if (phase == kPhaseAll) return true;
-  if (phase == kPhaseInit) return fs->nonfinite == 0;
+  if (phase == kPhaseInit) return fs->fresh != 0 && fs->nonfinite == 0;
+  if (phase == kPhaseFresh) return fs->fresh != 0 && fs->active != 0;
+  if (phase == kPhaseRetire) return fs->retire != 0;
   if (phase == kPhaseActive) return fs->active != 0;
   if (phase == kPhaseBacktrack) return fs->active != 0 && fs->need_bt != 0;
   return fs->active != 0 && fs->go != 0;
@@ -136,8 +149,9 @@ size_t gradient_work_bytes(const Layout& L);
 
 // Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st);
-// Zero the error word and the filtered-candidate count of rows 0 .. rows-1 of a top-k work area.
-hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, hipStream_t st);
+// Zero the error word and the filtered-candidate count of the rows of a top-k work area with
+// flags[row] != 0 (rows 0 .. rows-1 if flags is NULL).
+hipError_t launch_topk_clear_errors(uint32_t* small, int32_t rows, const int32_t* flags, hipStream_t st);
 
 // Unpenalised columns: dense covariates and the intercept.
 struct Unpen {

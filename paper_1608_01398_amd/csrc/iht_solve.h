@@ -46,7 +46,19 @@ inline int32_t solve_subject_blocks(int64_t n) { return (int32_t)((n + kSubjBloc
 inline int32_t solve_partial_stride(int32_t nc) { return 5 + nc; }
 constexpr int kYsumStride = 1 + kMaxUnpenalized;
 
-hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st);
+// Where one solve's outputs go: support and beta_S [ld] (ld >= k), beta_cov [cz + intercept] or
+// NULL, the loss trace [max_iter + 1] or NULL (kept in place).
+struct OutRow {
+  int64_t* support;
+  double* beta_S;
+  double* beta_cov;
+  double* trace;
+  int64_t ld;
+};
+
+// initial state of the admitted solves (admit[t] != 0, device [T]; every solve if NULL): beta = 0,
+// control state, centring sums; marks them fresh
+hipError_t solve_init(const SolveSet& Q, int32_t max_iter, const int32_t* admit, hipStream_t st);
 // residual at beta = 0 (and its centred copy) of the solves with finite inputs
 hipError_t solve_residual0(const SolveSet& Q, hipStream_t st);
 // columns of S (which = 0, current cache) or S+ (which = 1, other cache) of the solves in `phase`
@@ -54,12 +66,15 @@ hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, 
 // backtracking test of the decoded proposal, and residual/loss/centred residual if it is taken
 hipError_t solve_check_residual(const SolveSet& Q, int32_t phase, double c, int32_t max_backtrack, hipStream_t st);
 // mode 1: commit accepted proposals, then the next step size of those still iterating;
-// mode 0: step size of every active solve
+// mode 0: first step size of the newly admitted solves
 hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t max_iter, hipStream_t st);
 hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
+// FP64 refinement of the solves marked retire that converged
 hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStream_t st);
-hipError_t solve_output(const SolveSet& Q, int64_t* support, double* beta_S, double* beta_cov, int64_t ldk, int64_t ldc,
-                        hipStream_t st);
+// outputs of the solves marked retire into rows[t] (device [T])
+hipError_t solve_output(const SolveSet& Q, const OutRow* rows, hipStream_t st);
+// fresh (field 0) or retire (field 1) flag := value on the solves with flags[t] != 0 (all if NULL)
+hipError_t solve_mark(const SolveSet& Q, const int32_t* flags, int32_t field, int32_t value, hipStream_t st);
 // Held-out mean squared errors of q x r cross-validation solves (solve f * r + a: fold f held out,
 // model size ks_path[a]; ks_solve[t] = its k), mse [r][q], and the k of least mean MSE. part holds
 // ceil(n / 256) doubles per solve; fold_count [q] the size of each fold.

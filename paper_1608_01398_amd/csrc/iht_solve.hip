@@ -157,13 +157,17 @@ __device__ __forceinline__ void apply_cols(const double* X, int64_t n_pad, const
 
 // beta = 0 (eq. ihta starts from the zero vector), non-finite y or covariates inside the subject
 // set flagged, mu = 1 so that the first projection of beta + mu g is the top-k of |g|.
-__global__ __launch_bounds__(256) void k_zero_beta(SolveSet Q) {
-  const int64_t total = (int64_t)Q.T * Q.p;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) Q.beta[e] = 0.0;
+// Only the admitted solves (admit[t] != 0; every solve if admit is NULL) are touched.
+__global__ __launch_bounds__(256) void k_zero_beta(SolveSet Q, const int32_t* __restrict__ admit) {
+  const int t = blockIdx.y;
+  if (admit && !admit[t]) return;
+  double* beta = Q.beta + (int64_t)t * Q.p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < Q.p; e += (int64_t)gridDim.x * 256) beta[e] = 0.0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter) {
+__global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter, const int32_t* __restrict__ admit) {
   const int t = blockIdx.x;
+  if (admit && !admit[t]) return;
   const double* mask = Q.sv[t].mask;
   const double* y = Q.Y + (int64_t)t * Q.ldy;
   for (int c = threadIdx.x; c < kMaxUnpenalized; c += kThreads) {
@@ -202,6 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter)
     z.nonfinite = bad;
     z.active = (bad || max_iter <= 0) ? 0 : 1;
     z.status = bad ? IHT_ENONFINITE : IHT_NOT_CONVERGED;
+    z.fresh = 1;
     Q.fs[t] = z;
   }
 }
@@ -511,14 +516,14 @@ __global__ __launch_bounds__(kMbThreads) void k_decide(SolveSet Q, int32_t phase
 }
 
 // Partial sums of the step-size denominator ||A_{S u C} g_{S u C}||^2 ("IHT step sizes", normalised
-// form) over each workgroup's subjects, on S (mode 0, first iteration, every active solve) or on S+
+// form) over each workgroup's subjects, on S (mode 0, first iteration of the newly admitted solves) or on S+
 // (mode 1, the solves whose proposal was taken). In mode 1 the first workgroup also commits the
 // proposal: the convergence test (S+ = S and ||beta+ - beta||_inf <= tol max(1, ||beta+||_inf); with
 // S+ = S the union of the supports is S itself, so the norms run over S+ and C), then beta <- beta+,
 // S <- S+, bc <- bcp. The control state changes in k_mu.
 __global__ __launch_bounds__(kMbThreads) void k_commit_den(SolveSet Q, int32_t mode, double tol) {
   const int t = blockIdx.y, b = blockIdx.x;
-  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseActive : kPhaseGo)) return;
+  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseFresh : kPhaseGo)) return;
   __shared__ Stage s;
   const View V = view(Q, t);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -589,7 +594,7 @@ __global__ __launch_bounds__(kMbThreads) void k_commit_den(SolveSet Q, int32_t m
 // the solve ends there (converged).
 __global__ __launch_bounds__(kMbThreads) void k_mu(SolveSet Q, int32_t mode, int32_t max_iter) {
   const int t = blockIdx.x;
-  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseActive : kPhaseGo)) return;
+  if (!fs_selected(Q.fs + t, mode == 0 ? kPhaseFresh : kPhaseGo)) return;
   __shared__ Stage s;
   const View V = view(Q, t);
   FitState* fs = V.fs;
@@ -712,7 +717,7 @@ __device__ double polish_Anorm(const SolveSet& Q, const View& V, const double* d
 // gradients on the normal equations, over the exactly decoded columns of S, until the step is
 // within tol max(1, ||x||_inf). The last loss-trace entry becomes the loss at the result.
 __global__ __launch_bounds__(kThreads) void k_polish(SolveSet Q, double tol, int32_t max_steps) {
-  if (Q.fs[blockIdx.x].status != IHT_OK) return;
+  if (!fs_selected(Q.fs + blockIdx.x, kPhaseRetire) || Q.fs[blockIdx.x].status != IHT_OK) return;
   const View V = view(Q, blockIdx.x);
   __shared__ double sh[40];
   const int k = V.k, m = V.k + V.nc;
@@ -761,17 +766,34 @@ __global__ __launch_bounds__(kThreads) void k_polish(SolveSet Q, double tol, int
 
 // ---------------------------------------------------------------------------- outputs and slots
 
-__global__ void k_output(SolveSet Q, int64_t* __restrict__ support, double* __restrict__ beta_S,
-                         double* __restrict__ beta_cov, int64_t ldk, int64_t ldc) {
+// Outputs of the solves being written out, into their rows (support ascending and beta_S padded
+// to ld with -1 / 0; beta_cov; the loss trace entries 0 .. iter when trace is not NULL).
+__global__ void k_output(SolveSet Q, const OutRow* __restrict__ rows) {
+  if (!fs_selected(Q.fs + blockIdx.x, kPhaseRetire)) return;
   const View V = view(Q, blockIdx.x);
+  const OutRow o = rows[blockIdx.x];
   const bool valid = V.fs->nonfinite == 0;  // a solve rejected at the start never had a support
-  for (int64_t q = threadIdx.x; q < ldk; q += blockDim.x) {
+  for (int64_t q = threadIdx.x; q < o.ld; q += blockDim.x) {
     const bool in = valid && q < V.k;
-    support[(int64_t)V.t * ldk + q] = in ? V.S[q] : -1;
-    beta_S[(int64_t)V.t * ldk + q] = in ? V.beta[V.S[q]] : 0.0;
+    o.support[q] = in ? V.S[q] : -1;
+    o.beta_S[q] = in ? V.beta[V.S[q]] : 0.0;
   }
-  if (beta_cov)
-    for (int q = threadIdx.x; q < V.nc; q += blockDim.x) beta_cov[(int64_t)V.t * ldc + q] = valid ? V.bc[q] : 0.0;
+  if (o.beta_cov)
+    for (int q = threadIdx.x; q < V.nc; q += blockDim.x) o.beta_cov[q] = valid ? V.bc[q] : 0.0;
+  if (o.trace)
+    for (int q = threadIdx.x; q <= V.fs->iter; q += blockDim.x) o.trace[q] = V.trace[q];
+}
+
+// fs[t].fresh (field 0) or fs[t].retire (field 1) = value for the solves with flags[t] != 0 (all
+// solves if flags is NULL).
+__global__ void k_mark(FitState* __restrict__ fs, int32_t T, const int32_t* __restrict__ flags, int32_t field,
+                       int32_t value) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T || (flags && !flags[t])) return;
+  if (field == 0)
+    fs[t].fresh = value;
+  else
+    fs[t].retire = value;
 }
 
 // One wave: the solves in `phase`, ascending, packed into slots[0 .. *count).
@@ -793,12 +815,12 @@ __global__ __launch_bounds__(64) void k_slots(const FitState* __restrict__ fs, i
 
 // ---------------------------------------------------------------------------- launchers
 
-hipError_t solve_init(const SolveSet& Q, int32_t max_iter, hipStream_t st) {
-  const int64_t total = (int64_t)Q.T * Q.p;
-  hipLaunchKernelGGL(k_zero_beta, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256), 0, st, Q);
+hipError_t solve_init(const SolveSet& Q, int32_t max_iter, const int32_t* admit, hipStream_t st) {
+  const unsigned bx = (unsigned)std::min<int64_t>((Q.p + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_zero_beta, dim3(bx, (unsigned)Q.T), dim3(256), 0, st, Q, admit);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_init, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, max_iter);
+  hipLaunchKernelGGL(k_init, dim3((unsigned)Q.T), dim3(kThreads), 0, st, Q, max_iter, admit);
   return hipGetLastError();
 }
 
@@ -842,9 +864,13 @@ hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStr
   return hipGetLastError();
 }
 
-hipError_t solve_output(const SolveSet& Q, int64_t* support, double* beta_S, double* beta_cov, int64_t ldk, int64_t ldc,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_output, dim3((unsigned)Q.T), dim3(256), 0, st, Q, support, beta_S, beta_cov, ldk, ldc);
+hipError_t solve_output(const SolveSet& Q, const OutRow* rows, hipStream_t st) {
+  hipLaunchKernelGGL(k_output, dim3((unsigned)Q.T), dim3(256), 0, st, Q, rows);
+  return hipGetLastError();
+}
+
+hipError_t solve_mark(const SolveSet& Q, const int32_t* flags, int32_t field, int32_t value, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark, dim3((unsigned)((Q.T + 255) / 256)), dim3(256), 0, st, Q.fs, Q.T, flags, field, value);
   return hipGetLastError();
 }
 

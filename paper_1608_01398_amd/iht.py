@@ -22,7 +22,8 @@ MAX_K = 4096
 
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
-           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_status_str", "iht_last_error")
+           "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
+           "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_status_str", "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -35,6 +36,12 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("slots_busy", ctypes.c_int32), ("stats_blocks", ctypes.c_int32),
+                ("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("turns", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -68,9 +75,16 @@ def load():
     L.iht_cv.argtypes = [P, P, P, I32, I32, P, I32, P, I32, ctypes.POINTER(Opts), P, ctypes.POINTER(I32), P, P, P, P,
                          ctypes.POINTER(I32), P]
     L.iht_predict.argtypes = [P, P, P, P, I32, P, I32, I32, P, P, P]
+    L.iht_server_create.argtypes = [P, I32, I32, I64, P, I32, I32, ctypes.POINTER(Opts), P, PP]
+    L.iht_server_submit.argtypes = [P, P, P, I64, I32, P, P, P, P, P, P, P, ctypes.POINTER(I64)]
+    L.iht_server_step.argtypes = [P, ctypes.POINTER(I32)]
+    L.iht_server_poll.argtypes = [P, I64, ctypes.POINTER(I32)]
+    L.iht_server_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
+    L.iht_server_destroy.argtypes = [P]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
               "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_project_hint", "iht_fit",
-              "iht_fit_batch", "iht_cv", "iht_predict"):
+              "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
+              "iht_server_poll", "iht_server_info", "iht_server_destroy"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -369,3 +383,107 @@ def predict(geno: Geno, stats: Stats, support, beta_S, Z=None, intercept: bool =
     _check(load().iht_predict(geno._h, stats._h, sp, bp, k, zp, cz, 1 if intercept else 0, cp,
                               ctypes.c_void_p(out.data_ptr()), _stream()))
     return out
+
+
+class Server:
+    """Solve server with continuous batching over one resident matrix (iht_server_*).
+
+    Requests (a subject subset, T traits, a model size per trait) are admitted between turns as slots
+    and statistics blocks free up; step() advances every admitted solve by one turn and writes out
+    the finished ones. Every result is the same alone and in any mix.
+    """
+
+    def __init__(self, geno: Geno, slots: int, kmax: int, hbm_budget: int, Z=None, intercept: bool = True,
+                 **opts):
+        torch = _torch()
+        self.geno = geno
+        self.o = default_opts(**opts)
+        self.kmax = int(kmax)
+        cz = 0
+        zp = None
+        self._Z = Z
+        if Z is not None:
+            cz = Z.shape[0]
+            zp = _dev(Z, torch.float32, (cz, geno.n), "Z")
+        self.nc = cz + (1 if intercept else 0)
+        self._h = ctypes.c_void_p()
+        _check(load().iht_server_create(geno._h, slots, kmax, int(hbm_budget), zp, cz, 1 if intercept else 0,
+                                        ctypes.byref(self.o), _stream(), ctypes.byref(self._h)))
+        self._pid = os.getpid()
+        self._req = {}
+
+    def submit(self, Y, ks, subset=None) -> int:
+        """Queue a request: Y float64 CUDA [T, n] (kept alive until done), ks [T], subset host 0/1 [n] or None."""
+        torch = _torch()
+        ks_arr = np.ascontiguousarray(ks, dtype=np.int32)
+        T = int(ks_arr.size)
+        yp = _dev(Y, torch.float64, (T, self.geno.n), "Y")
+        m = None
+        if subset is not None:
+            m = np.ascontiguousarray(subset, dtype=np.uint8)
+            if m.shape != (self.geno.n,):
+                raise ValueError("subset must have n entries")
+        kr = int(ks_arr.max())
+        dev = Y.device
+        out = dict(support=torch.empty((T, kr), dtype=torch.int64, device=dev),
+                   beta_S=torch.empty((T, kr), dtype=torch.float64, device=dev),
+                   beta_cov=torch.empty((T, max(self.nc, 1)), dtype=torch.float64, device=dev),
+                   loss_trace=torch.full((T, self.o.max_iter + 1), float("nan"), dtype=torch.float64, device=dev),
+                   n_iter=np.zeros(T, dtype=np.int32), statuses=np.zeros(T, dtype=np.int32))
+        rid = ctypes.c_int64(0)
+        _check(load().iht_server_submit(
+            self._h, None if m is None else m.ctypes.data_as(ctypes.c_void_p), yp, self.geno.n, T,
+            ks_arr.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(out["support"].data_ptr()),
+            ctypes.c_void_p(out["beta_S"].data_ptr()),
+            ctypes.c_void_p(out["beta_cov"].data_ptr()) if self.nc else None,
+            ctypes.c_void_p(out["loss_trace"].data_ptr()), out["n_iter"].ctypes.data_as(ctypes.c_void_p),
+            out["statuses"].ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))
+        self._req[rid.value] = (out, Y, ks_arr, m)  # keep inputs and outputs alive
+        return rid.value
+
+    def step(self) -> int:
+        """Admit what fits, run one turn, write out what finished. Returns the requests completed."""
+        c = ctypes.c_int32(0)
+        _check(load().iht_server_step(self._h, ctypes.byref(c)))
+        return c.value
+
+    def done(self, rid: int) -> bool:
+        d = ctypes.c_int32(0)
+        _check(load().iht_server_poll(self._h, rid, ctypes.byref(d)))
+        return bool(d.value)
+
+    def result(self, rid: int):
+        """The finished request's outputs (dict as fit_batch: support [T, kr], beta_S, beta_cov [T, nc],
+        loss_trace [T, max_iter+1], n_iter [T], statuses [T]); releases the server's reference."""
+        if not self.done(rid):
+            raise RuntimeError(f"request {rid} has not finished")
+        out, _, ks, _ = self._req.pop(rid)
+        res = dict(out)
+        res["beta_cov"] = out["beta_cov"][:, :self.nc]
+        res["ks"] = ks
+        return res
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(load().iht_server_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in ServerInfo._fields_}
+
+    def run_until_idle(self, max_steps: int = 100000):
+        """Step until nothing is queued or running."""
+        for _ in range(max_steps):
+            inf = self.info()
+            if inf["queued"] == 0 and inf["running"] == 0:
+                return
+            self.step()
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and getattr(self, "_pid", None) == os.getpid():
+            load().iht_server_destroy(self._h)
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

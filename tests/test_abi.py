@@ -65,6 +65,19 @@ def test_library_loads_and_answers_host_only_calls(lib_path):
     rc = L.iht_project(None, 10, 3, None, None, None)
     assert rc == iht.EINVAL
     assert L.iht_fit(None, None, None, None, 0, 1, 3, None, None, None, None, None, None, None) == iht.EINVAL
+    # the server entry points reject NULL handles before any device work
+    srv = ctypes.c_void_p()
+    assert L.iht_server_create(None, 4, 10, 1 << 30, None, 0, 1, None, None, ctypes.byref(srv)) == iht.EINVAL
+    assert srv.value is None
+    done = ctypes.c_int32(7)
+    assert L.iht_server_step(None, ctypes.byref(done)) == iht.EINVAL
+    assert L.iht_server_poll(None, 0, ctypes.byref(done)) == iht.EINVAL
+    info = iht.ServerInfo()
+    assert L.iht_server_info(None, ctypes.byref(info)) == iht.EINVAL
+    rid = ctypes.c_int64(0)
+    assert L.iht_server_submit(None, None, None, 0, 1, None, None, None, None, None, None, None,
+                               ctypes.byref(rid)) == iht.EINVAL
+    assert L.iht_server_destroy(None) == iht.OK
 
 
 def test_oracle_builds_and_is_not_linked_by_the_library(lib_path):
