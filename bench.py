@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="n=1000, p=10,000 workload (the oracle-sized case)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solves section")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section (n=10,000, p=1,000,000)")
+    ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch one fill and one device-to-device copy of the packed matrix's size, "
                          "the known-size kernels that scale the HBM byte counters")
@@ -191,6 +193,8 @@ def main():
     if not args.no_batched and not args.small:
         out["batched"] = bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes)
         out["cv"] = bench_cv(args, torch, iht, synth, prob, geno, y)
+    if not args.no_serving and not args.small:
+        out["serving"] = bench_serving(args, torch, iht, synth)
 
     if not args.no_cpu_baseline:
         from oracle import oracle
@@ -379,6 +383,129 @@ def bench_cv(args, torch, iht, synth, prob, geno, y):
             f"precision {hit}/{len(sup)}, recall {hit}/{len(causal)}, h2 est {h2:.3f} (true {h2_true:.3f})")
     res["same_choice"] = res["mixed_i8"]["k_best"] == res["fp64"]["k_best"]
     return res
+
+
+def request_stream(n, count, seed):
+    """Seeded serving requests: subject subsets of U{2000..n} subjects, 1..64 traits, k ~ U{5..50}."""
+    rng = np.random.default_rng([seed, 77])
+    reqs = []
+    for i in range(count):
+        T = int(rng.integers(1, 65))
+        reqs.append(dict(size=int(rng.integers(2000, n + 1)), T=T, ks=rng.integers(5, 51, T).astype(np.int32),
+                         row0=int(rng.integers(0, 64 - T + 1)), seed=1000 + i))
+    return reqs
+
+
+def serve(iht, torch, srv, reqs, subsets, pool, arrivals=None):
+    """Feeds the requests to the server (all at once, or at the given arrival times in seconds) and
+    steps it until every request is done; returns (wall seconds, per-request latencies, ids)."""
+    t0 = time.perf_counter()
+    pending = list(range(len(reqs)))
+    live = {}
+    lat = [None] * len(reqs)
+    ids = [None] * len(reqs)
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and (arrivals is None or arrivals[pending[0]] <= now):
+            i = pending.pop(0)
+            r = reqs[i]
+            ids[i] = srv.submit(pool[r["row0"]:r["row0"] + r["T"]], r["ks"], subsets[i])
+            live[ids[i]] = (i, t0 + (0.0 if arrivals is None else arrivals[i]))
+        if not live:
+            time.sleep(max(0.0, arrivals[pending[0]] - now))
+            continue
+        if srv.step():
+            t = time.perf_counter()
+            for rid in [rid for rid in live if srv.done(rid)]:
+                i, a = live.pop(rid)
+                lat[i] = t - a
+    return time.perf_counter() - t0, np.asarray(lat), ids
+
+
+def bench_serving(args, torch, iht, synth):
+    """Continuous-batching server on the n=10,000 x p=1,000,000 matrix (2.5 GB resident): requests
+    with their own subject subsets, 1..64 traits and k ~ U{5..50}, int8 matrix-core gradient with the
+    FP64 refinement. Saturated (every request queued at once) for solves/s, then a Poisson stream at
+    70% of that rate for latency; against a plain loop of FP64 iht_fit calls on sampled solves."""
+    t = time.time()
+    prob = synth.make_problem("c4", args.seed)
+    n, p = prob["n"], prob["p"]
+    geno = iht.Geno(prob["bed"], n)
+    pool = [prob["y"]] + [synth.make_trait(prob["bed"], n, prob["q"], 20, (0.1, 0.4), seed=5000 + e)[0]
+                          for e in range(63)]
+    pool = torch.from_numpy(np.stack(pool)).cuda()
+    reqs = request_stream(n, args.serve_requests, args.seed)
+    subsets = [synth.make_subset(n, r["size"], r["seed"]) if r["size"] < n else None for r in reqs]
+    traits = int(sum(r["T"] for r in reqs))
+    log(f"serving: c4 n={n} p={p} ({n * p / 4e9:.1f} GB packed) ready in {time.time() - t:.1f}s; "
+        f"{len(reqs)} requests, {traits} solves")
+    slots, kmax, budget = 256, 50, 24 << 30
+    srv = iht.Server(geno, slots=slots, kmax=kmax, hbm_budget=budget, precision=iht.MIXED_I8)
+    info0 = srv.info()
+    # warm-up: one small request
+    srv.submit(pool[:2], [10, 20], subsets[0])
+    srv.run_until_idle()
+    wall, lat_sat, ids = serve(iht, torch, srv, reqs, subsets, pool)
+    sat_rate = traits / wall
+    log(f"serving saturated: {traits} solves in {wall:.2f}s = {sat_rate:.0f} solves/s; request latency "
+        f"p50 {np.percentile(lat_sat, 50) * 1e3:.0f} ms p99 {np.percentile(lat_sat, 99) * 1e3:.0f} ms; "
+        f"{srv.info()['turns'] - info0['turns']} turns")
+    # the served results of a few solves against the same solves alone (bitwise)
+    same = True
+    checked = 0
+    for i in (0, len(reqs) // 2, len(reqs) - 1):
+        res = srv.result(ids[i])
+        r = reqs[i]
+        j = r["T"] - 1
+        st = iht.Stats(geno, subsets[i])
+        a = iht.fit(geno, st, pool[r["row0"] + j].contiguous(), int(r["ks"][j]), precision=iht.MIXED_I8)
+        k = int(r["ks"][j])
+        same &= bool(torch.equal(a["support"], res["support"][j, :k]) and torch.equal(a["beta_S"], res["beta_S"][j, :k])
+                     and a["n_iter"] == int(res["n_iter"][j]))
+        checked += 1
+    log(f"served = alone (bitwise) on {checked} sampled solves: {same}")
+    # Poisson arrivals at 70% of the saturated request rate
+    rate = 0.7 * len(reqs) / wall
+    arr = np.cumsum(np.random.default_rng([args.seed, 78]).exponential(1.0 / rate, len(reqs)))
+    wall_p, lat_p, _ = serve(iht, torch, srv, reqs, subsets, pool, arrivals=arr)
+    log(f"serving Poisson ({rate:.1f} requests/s): {traits / wall_p:.0f} solves/s; request latency p50 "
+        f"{np.percentile(lat_p, 50) * 1e3:.0f} ms p99 {np.percentile(lat_p, 99) * 1e3:.0f} ms")
+    info = srv.info()
+    srv.close()
+    # plain loop: FP64 iht_fit per solve (stats per request), on the first solves of the stream
+    sample, t_plain, done = 32, 0.0, 0
+    for i, r in enumerate(reqs):
+        if done >= sample:
+            break
+        t0 = time.perf_counter()
+        st = iht.Stats(geno, subsets[i])
+        for j in range(r["T"]):
+            if done >= sample:
+                break
+            iht.fit(geno, st, pool[r["row0"] + j].contiguous(), int(r["ks"][j]))
+            done += 1
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t0
+    plain_rate = done / t_plain
+    log(f"plain FP64 loop: {done} solves in {t_plain:.2f}s = {plain_rate:.1f} solves/s")
+    return {
+        "workload": f"continuous-batching server, n={n} x p={p} ({n * p / 4e9:.1f} GB packed) resident; "
+                    f"{len(reqs)} requests: subsets U{{2000..{n}}} subjects, 1..64 traits, k~U{{5..50}}; "
+                    f"{slots} slots, kmax {kmax}, budget {budget >> 30} GiB; int8 matrix-core gradient + FP64 polish",
+        "solves": traits,
+        "saturated_solves_per_s": round(sat_rate, 1),
+        "saturated_latency_ms_p50": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
+        "saturated_latency_ms_p99": round(float(np.percentile(lat_sat, 99)) * 1e3, 1),
+        "poisson_requests_per_s": round(rate, 2),
+        "poisson_solves_per_s": round(traits / wall_p, 1),
+        "latency_ms_p50": round(float(np.percentile(lat_p, 50)) * 1e3, 1),
+        "latency_ms_p99": round(float(np.percentile(lat_p, 99)) * 1e3, 1),
+        "plain_fp64_loop_solves_per_s": round(plain_rate, 2),
+        "speedup_vs_plain_fp64_loop": round(sat_rate / plain_rate, 1),
+        "served_equals_alone_bitwise_sampled": same,
+        "server_device_bytes": info["device_bytes"],
+        "stats_blocks": info["stats_blocks"],
+    }
 
 
 if __name__ == "__main__":
