@@ -552,9 +552,120 @@ __global__ __launch_bounds__(THREADS) void k_topk_local(TopkJob J, int64_t p) {
   for (int q = (int)nout + tid; q < J.kmax; q += THREADS) oi[q] = -1;
 }
 
+// Bound for the filter of a solver row (beta and prev = its ascending support): the k-th largest
+// key among the support's k entries and the first kBoundSlots - k entries of the row outside the
+// support. These are distinct indices, so the bound is at most the row's k-th largest key (each of
+// the k first, ties included, is at or above it) and at least the smallest key over the support.
+// The sample makes it tight when some support entries are small (k above the number of effects):
+// about k p / kBoundSlots entries of the row then pass the filter instead of nearly all of them.
+// Written to state[4] (low word) and state[5] (high word); 0 (no bound) if fewer than k valid
+// entries were seen. A row takes the sample only once one of its filters has let more than
+// kLooseCandidates entries through (state[6], set by k_topk_final, cleared with the error word);
+// until then the bound is the smallest key over the support, which costs k loads.
+constexpr int kBoundEPT = 8;
+constexpr int kBoundSlots = 1024 * kBoundEPT;
+constexpr uint32_t kLooseCandidates = 1024;
+static_assert(kBoundSlots > kLocalMaxK, "the sample must hold the support");
+
+__global__ __launch_bounds__(1024) void k_topk_bound(TopkJob J, int64_t p) {
+  TopkRow src;
+  if (!topk_row(J, blockIdx.x, src)) return;
+  __shared__ uint32_t hist[kSelBins];
+  __shared__ uint32_t sh[32];
+  __shared__ uint64_t shm[16];
+  __shared__ uint32_t total;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = src.k;
+  const int64_t* prev = J.prev + (int64_t)blockIdx.x * J.ldprev;
+  if (src.tw.state[6] == 0u) {
+    uint64_t tk = ~0ull;
+    for (int q = tid; q < k; q += 1024) {
+      const int64_t h = prev[q];
+      const uint64_t kq = (h >= 0 && h < p) ? abs_key(src.at(h)) : (uint64_t)0;  // out of range: no bound
+      tk = kq < tk ? kq : tk;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(tk, off, 64);
+      tk = o < tk ? o : tk;
+    }
+    if (lane == 0) shm[w] = tk;
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t m = shm[0];
+      for (int i = 1; i < 16; ++i) m = shm[i] < m ? shm[i] : m;
+      src.tw.state[4] = (uint32_t)m;
+      src.tw.state[5] = (uint32_t)(m >> 32);
+    }
+    return;
+  }
+  int32_t idx[kBoundEPT];
+  uint64_t key[kBoundEPT];
+  uint32_t nv = 0;
+#pragma unroll
+  for (int e = 0; e < kBoundEPT; ++e) {
+    const int i = e * 1024 + tid;
+    int64_t j;
+    bool ok;
+    double v = 0.0;
+    if (i < k) {
+      j = prev[i];
+      ok = j >= 0 && j < p;
+      if (ok) v = src.at(j);
+    } else {
+      j = i - k;
+      ok = j < p;
+      if (ok) {  // skip the support's own indices
+        int lo = 0, hi = k;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (prev[mid] < j)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        ok = !(lo < k && prev[lo] == j);
+        if (ok) v = __dmul_rn(src.mu, src.g[j]);  // beta is zero off the support
+      }
+    }
+    ok = ok && isfinite(v);
+    idx[e] = ok ? (int32_t)j : -1;
+    key[e] = abs_key(v);
+    nv += ok ? 1u : 0u;
+  }
+  const uint32_t all = block_suffix_sum<1024>(nv, sh);
+  if (tid == 0) total = all;
+  __syncthreads();
+  if (total < (uint32_t)k) {
+    if (tid == 0) {
+      src.tw.state[4] = 0u;
+      src.tw.state[5] = 0u;
+    }
+    return;
+  }
+  const uint32_t take = block_select<1024, kBoundEPT>(key, [&](int e) { return idx[e]; }, (uint32_t)k, hist, sh);
+  uint64_t mn = ~0ull;
+#pragma unroll
+  for (int e = 0; e < kBoundEPT; ++e)
+    if ((take >> e) & 1u) mn = key[e] < mn ? key[e] : mn;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(mn, off, 64);
+    mn = o < mn ? o : mn;
+  }
+  if (lane == 0) shm[w] = mn;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t m = shm[0];
+    for (int i = 1; i < 16; ++i) m = shm[i] < m ? shm[i] : m;
+    src.tw.state[4] = (uint32_t)m;
+    src.tw.state[5] = (uint32_t)(m >> 32);
+  }
+}
+
 // Pass 1 with a threshold (TopkJob::prev): the smallest key over the row's k distinct previous
 // indices is at most the k-th largest key, so every entry at or above it is a candidate (a superset
-// of the k first, ties included). Each wave appends its candidates to the row's list with one atomic add;
+// of the k first, ties included); for a solver row the tighter bound of k_topk_bound is used. Each wave appends its candidates to the row's list with one atomic add;
 // the order of the list does not matter to pass 2.
 __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
   TopkRow src;
@@ -564,21 +675,25 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
   const int64_t* prev = J.prev + (int64_t)blockIdx.y * J.ldprev;
   // (64-bit keys compared as integers throughout: no min() overload that could convert them)
   uint64_t tk = ~0ull;
-  for (int q = tid; q < src.k; q += 256) {
-    const int64_t h = prev[q];
-    const uint64_t kq = (h >= 0 && h < p) ? abs_key(src.at(h)) : (uint64_t)0;  // out of range: no bound
-    tk = kq < tk ? kq : tk;
-  }
+  if (J.use_bound) {
+    tk = (uint64_t)src.tw.state[4] | ((uint64_t)src.tw.state[5] << 32);
+  } else {
+    for (int q = tid; q < src.k; q += 256) {
+      const int64_t h = prev[q];
+      const uint64_t kq = (h >= 0 && h < p) ? abs_key(src.at(h)) : (uint64_t)0;  // out of range: no bound
+      tk = kq < tk ? kq : tk;
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t o = __shfl_xor(tk, off, 64);
-    tk = o < tk ? o : tk;
-  }
-  if (lane == 0) shk[w] = tk;
-  __syncthreads();
-  tk = shk[0];
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(tk, off, 64);
+      tk = o < tk ? o : tk;
+    }
+    if (lane == 0) shk[w] = tk;
+    __syncthreads();
+    tk = shk[0];
 #pragma unroll
-  for (int i = 1; i < 4; ++i) tk = shk[i] < tk ? shk[i] : tk;
+    for (int i = 1; i < 4; ++i) tk = shk[i] < tk ? shk[i] : tk;
+  }
   // Appends this wave's `in` lanes to the row's candidate list: one atomic add per wave.
   auto append = [&](bool in, uint64_t key, int64_t j) {
     const uint64_t m = __ballot(in);
@@ -700,6 +815,7 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
       const uint32_t c = atomicExch(&src.tw.counters[4], 0u);
       nsel = c;
       if ((int64_t)c < k) atomicOr(&src.tw.state[3], 4u);  // the bound came from repeated indices
+      if (c > kLooseCandidates) src.tw.state[6] = 1u;      // later bounds of this row use the sample
     }
     __syncthreads();
     total = min((int64_t)nsel, J.cap);
@@ -812,6 +928,7 @@ __global__ void k_topk_clear_errors(uint32_t* __restrict__ small, int32_t rows, 
   if (t < rows && (!flags || flags[t])) {  // words that kernels update with device-scope atomics are cleared with one
     (void)atomicExch(&small[t * kTopkRowWords + kTopkErrorWord], 0u);
     (void)atomicExch(&small[t * kTopkRowWords + kTopkBins0 + 4], 0u);  // filtered-candidate count
+    (void)atomicExch(&small[t * kTopkRowWords + kTopkBins0 + 8 + 6], 0u);  // the row's sampled-bound flag
   }
 }
 
@@ -859,10 +976,17 @@ hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st
   const int64_t nb_s = (p + kSmallChunk - 1) / kSmallChunk;
   const int64_t nb_l = (p + kLargeChunk - 1) / kLargeChunk;
   if (J.prev && J.kmax <= kLocalMaxK && J.cap >= p) {
-    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, J, p);
+    TopkJob Jf = J;
+    Jf.use_bound = J.beta != nullptr ? 1 : 0;  // solver rows: prev is beta's ascending support
+    if (Jf.use_bound) {
+      hipLaunchKernelGGL(k_topk_bound, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, Jf, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, 0);
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p, 0);
     return hipGetLastError();
   }
   if (J.kmax <= kLocalMaxK && nb_s * J.kmax <= cap2 && nb_s * J.kmax <= J.cap) {

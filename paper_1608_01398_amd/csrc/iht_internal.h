@@ -127,6 +127,7 @@ struct TopkJob {
   int64_t cap;  // candidate slots per row (>= p, >= 16384)
   const int64_t* prev;  // may be NULL
   int64_t ldprev;
+  int32_t use_bound;  // set by launch_topk: the filter reads the bound k_topk_bound left in the row
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
