@@ -331,6 +331,7 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
         "plain_fp32_loop_solves_per_s": round(T / plain32, 2),
         "speedup_vs_plain_fp32_loop": round(plain32 / bt, 2),
         "iterations_mean": round(float(iters.mean()), 2),
+        "pass_block_snps_autotuned": iht.batch_tuning(geno, T),
         "statuses": [int(x) for x in np.asarray(res["statuses"])],
         "roofline": {
             "bound": "mfma", "kernel": "k_gradB (int8 matrix-core pass, all 108 solves)",
@@ -504,6 +505,7 @@ def bench_serving(args, torch, iht, synth):
         "speedup_vs_plain_fp64_loop": round(sat_rate / plain_rate, 1),
         "served_equals_alone_bitwise_sampled": same,
         "server_device_bytes": info["device_bytes"],
+        "pass_block_snps_autotuned": iht.batch_tuning(geno, slots),
         "stats_blocks": info["stats_blocks"],
     }
 

@@ -544,4 +544,11 @@ int iht_predict(const iht_geno* g, const iht_stats* s, const int64_t* support, c
   return IHT_OK;
 }
 
+int iht_batch_tuning(const iht_geno* g, int32_t T, int32_t* snps_per_block) {
+  if (!g || !snps_per_block) return fail(IHT_EINVAL, "iht_batch_tuning: NULL argument");
+  if (T < 1 || T > 65535) return fail(IHT_EINVAL, "iht_batch_tuning: T out of range");
+  *snps_per_block = batch_tuned_snps(g->L, T);
+  return IHT_OK;
+}
+
 }  // extern "C"

@@ -14,6 +14,8 @@ struct BatchSolve {
 
 int32_t batch_t_pad(int32_t T);
 size_t batch_r8_bytes(const Layout& L, int32_t T);
+// SNPs per block of the matrix-core pass the autotuner chose for this matrix and T (0: not tuned yet).
+int32_t batch_tuned_snps(const Layout& L, int32_t T);
 
 // G[t * ldg + j] = (X_st^T R_t)_j, with R_t = R + t * ldr (entries outside the solve's subject set
 // ignored). Slot s < *count computes solve t = slots[s]; with slots == NULL and count == NULL the

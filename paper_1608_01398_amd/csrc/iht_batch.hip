@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "iht_batch.h"
 
@@ -128,31 +131,23 @@ constexpr uint32_t kMissBytes = 0x00000100u;
 constexpr int kRbStride = 48;  // bytes per slot row of a staged digit plane (32 + 16: conflict-free)
 
 // One 32-SNP group per wave: 6 accumulator tiles (96 registers) leave 128 registers per wave, so
-// two 8-wave blocks (16 waves) share a CU; two groups per wave (192 accumulator registers, 8 waves
-// per CU) measured 16 % slower on the 108-slot pass.
-#ifndef IHT_BATCH_GROUPS
-#define IHT_BATCH_GROUPS 1
-#endif
-constexpr int kGroups = IHT_BATCH_GROUPS;              // 32-SNP groups per wave (accumulators: 6 per group)
-#ifndef IHT_BATCH_SNPS
-#define IHT_BATCH_SNPS 256
-#endif
-constexpr int kBlockSnps = IHT_BATCH_SNPS;             // per block
-constexpr int kBlockWaves = kBlockSnps / (32 * kGroups);
-constexpr int kBlockThreads = 64 * kBlockWaves;
-#ifndef IHT_BATCH_MINBLOCKS
-#define IHT_BATCH_MINBLOCKS 2
-#endif
+// 16 waves share a CU; two groups per wave (192 accumulator registers, 8 waves per CU) measured
+// 16 % slower on the 108-slot pass.
+constexpr int kGroups = 1;  // 32-SNP groups per wave (accumulators: 6 per group)
 constexpr int kBlockSolves = 32;
 
 // Block (bx, by): SNPs [256 bx, 256 bx + 256) x slots [32 by, 32 by + 32). Wave w: SNPs
 // [256 bx + 32 kGroups w, + 32 kGroups) as kGroups groups of 32 rows, each with a dosage and a
 // missing-flag operand, times the 3 digit column tiles: 6 kGroups accumulator tiles of 32x32 int32.
-__global__ __launch_bounds__(kBlockThreads, IHT_BATCH_MINBLOCKS) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
+// The block shape (SNPs per block, blocks per CU) is a template parameter; the launcher picks it
+// per problem shape by timing (every shape computes the same exact sums).
+template <int kBlockSnps, int kMinBlocks>
+__global__ __launch_bounds__(64 * (kBlockSnps / (32 * kGroups)), kMinBlocks) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
                                                   const int8_t* __restrict__ R8, int32_t T, int32_t T_pad,
                                                   const BatchSolve* __restrict__ sv, const int32_t* __restrict__ slots,
                                                   const int32_t* __restrict__ count, const double* __restrict__ scale,
                                                   const double* __restrict__ rsum, double* __restrict__ G, int64_t ldg) {
+  constexpr int kBlockThreads = 64 * (kBlockSnps / (32 * kGroups));
   const int live = count ? *count : T;
   if ((int)blockIdx.y * kBlockSolves >= live) return;  // no live slot in this block (uniform)
   __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * kRbStride];  // 2 x 4.5 KB
@@ -257,6 +252,85 @@ int32_t batch_t_pad(int32_t T) { return (T + kBlockSolves - 1) / kBlockSolves * 
 
 size_t batch_r8_bytes(const Layout& L, int32_t T) { return (size_t)L.ntiles * kDigits * batch_t_pad(T) * 32; }
 
+namespace {
+
+// Block shapes of k_gradB the launcher chooses from: (SNPs per block, blocks per CU).
+struct GradBShape {
+  int snps;
+  void (*kernel)(const uint2*, int64_t, int64_t, int32_t, const int8_t*, int32_t, int32_t, const BatchSolve*,
+                 const int32_t*, const int32_t*, const double*, const double*, double*, int64_t);
+};
+const GradBShape kShapes[] = {{256, &k_gradB<256, 2>}, {128, &k_gradB<128, 4>}, {512, &k_gradB<512, 1>}};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+hipError_t launch_shape(int si, const uint8_t* tiled, const Layout& L, const int8_t* R8, int32_t T, int32_t T_pad,
+                        const BatchSolve* sv, const int32_t* slots, const int32_t* count, const double* scale,
+                        const double* rsum, double* G, int64_t ldg, hipStream_t st) {
+  const GradBShape& S = kShapes[si];
+  const dim3 grid((unsigned)((L.p + S.snps - 1) / S.snps), (unsigned)(T_pad / kBlockSolves));
+  hipLaunchKernelGGL(S.kernel, grid, dim3(64 * S.snps / (32 * kGroups)), 0, st, reinterpret_cast<const uint2*>(tiled), L.p,
+                     L.p_pad, (int32_t)L.ntiles, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
+  return hipGetLastError();
+}
+
+// Autotuner: the first launch for a (device, tiles, padded p, padded T) shape times every block
+// shape once on the call's own inputs (HIP events on the call's stream; each run writes the same
+// G) and keeps the fastest for the rest of the process. Not while the stream is being captured
+// into a graph: the first shape is used then, untimed.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int64_t, int32_t>, int> g_tuned;
+
+int tuned_shape(const uint8_t* tiled, const Layout& L, const int8_t* R8, int32_t T, int32_t T_pad, const BatchSolve* sv,
+                const int32_t* slots, const int32_t* count, const double* scale, const double* rsum, double* G,
+                int64_t ldg, hipStream_t st) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const auto key = std::make_tuple(dev, (int64_t)L.ntiles, L.p_pad, T_pad);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return 0;
+  }
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int si = 0; si < kNumShapes; ++si) {
+    // one untimed run (code load, caches), then one timed run
+    if (launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) != hipSuccess) continue;
+    float ms = 0.0f;
+    if (hipEventRecord(e0, st) != hipSuccess ||
+        launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) != hipSuccess ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      continue;
+    if (si == 0 || ms < best_ms) {
+      best = si;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
+}
+
+}  // namespace
+
+int32_t batch_tuned_snps(const Layout& L, int32_t T) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(dev, (int64_t)L.ntiles, L.p_pad, batch_t_pad(T)));
+  return it == g_tuned.end() ? 0 : kShapes[it->second].snps;
+}
+
 hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
                                  const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
                                  double* rsum, double* G, int64_t ldg, hipStream_t st) {
@@ -265,10 +339,8 @@ hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const do
                      scale, rsum);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const dim3 grid((unsigned)((L.p + kBlockSnps - 1) / kBlockSnps), (unsigned)(T_pad / kBlockSolves));
-  hipLaunchKernelGGL(k_gradB, grid, dim3(kBlockThreads), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad, (int32_t)L.ntiles,
-                     R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
-  return hipGetLastError();
+  const int si = tuned_shape(tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st);
+  return launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st);
 }
 
 }  // namespace iht

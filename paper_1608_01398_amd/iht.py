@@ -23,7 +23,8 @@ MAX_K = 4096
 EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create",
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
            "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
-           "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_status_str", "iht_last_error")
+           "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning", "iht_status_str",
+           "iht_last_error")
 
 
 class IHTError(RuntimeError):
@@ -81,10 +82,11 @@ def load():
     L.iht_server_poll.argtypes = [P, I64, ctypes.POINTER(I32)]
     L.iht_server_info.argtypes = [P, ctypes.POINTER(ServerInfo)]
     L.iht_server_destroy.argtypes = [P]
+    L.iht_batch_tuning.argtypes = [P, I32, ctypes.POINTER(I32)]
     for f in ("iht_geno_create", "iht_geno_destroy", "iht_geno_shape", "iht_stats_create", "iht_stats_destroy",
               "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project", "iht_project_hint", "iht_fit",
               "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
-              "iht_server_poll", "iht_server_info", "iht_server_destroy"):
+              "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning"):
         getattr(L, f).restype = ctypes.c_int
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
@@ -383,6 +385,13 @@ def predict(geno: Geno, stats: Stats, support, beta_S, Z=None, intercept: bool =
     _check(load().iht_predict(geno._h, stats._h, sp, bp, k, zp, cz, 1 if intercept else 0, cp,
                               ctypes.c_void_p(out.data_ptr()), _stream()))
     return out
+
+
+def batch_tuning(geno: Geno, T: int) -> int:
+    """SNPs per workgroup the autotuner chose for the matrix-core pass over T solves (0: not tuned yet)."""
+    v = ctypes.c_int32(0)
+    _check(load().iht_batch_tuning(geno._h, T, ctypes.byref(v)))
+    return v.value
 
 
 class Server:

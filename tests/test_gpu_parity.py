@@ -498,3 +498,25 @@ def test_gradient_batch_rows_match_single_solve_inputs():
     u, v = oracle.stats(bed, n)
     for t in (0, 2):
         assert rel(got[t], oracle.gradient(bed, n, u, v, R[t])) <= 2e-6
+
+
+def test_gradient_batch_block_shape_tuning_changes_no_result():
+    """The first pass for a (matrix, T) shape times every block shape on the same inputs; each later
+    pass uses the chosen one. A row's result is bitwise the same through the tuning call, the tuned
+    calls and a batch of another size (another tuning key) that holds the same row."""
+    n, p = 1500, 40_000
+    bed, _ = synth.make_genotypes(n, p, seed=12)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    R = dev(np.random.default_rng(12).standard_normal((70, n)))
+    assert iht.batch_tuning(g, 70) == 0
+    first = iht.gradient_batch(g, [s] * 70, R).cpu().numpy()
+    chosen = iht.batch_tuning(g, 70)
+    say(f"tuned block shape for T=70: {chosen} SNPs per workgroup")
+    assert chosen in (128, 256, 512)
+    again = iht.gradient_batch(g, [s] * 70, R).cpu().numpy()
+    assert np.array_equal(first, again)
+    small = iht.gradient_batch(g, [s] * 5, R[:5].contiguous()).cpu().numpy()
+    assert np.array_equal(small, first[:5])
+    with pytest.raises(iht.IHTError):
+        iht.batch_tuning(g, 0)
