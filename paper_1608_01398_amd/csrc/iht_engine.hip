@@ -22,6 +22,11 @@ int check_opts(const iht_opts& o, const char* who) {
   return IHT_OK;
 }
 
+Engine::~Engine() {
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  if (cap_st_) (void)hipStreamDestroy(cap_st_);
+}
+
 int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, const Unpen& U, const double* Y,
                   int64_t ldy, double* trace, const iht_opts& o, hipStream_t st) {
   g_ = g;
@@ -35,6 +40,8 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
   kmax_ = kmax;
   nc_ = U.cz + U.icpt;
   mixed_ = o.precision == IHT_MIXED_I8;
+  if (exec_) (void)hipGraphExecDestroy(exec_);
+  exec_ = nullptr;
   tol_main_ = o.precision == IHT_FP64 ? o.tol : std::max(o.tol, o.mixed_tol);
   const size_t Tz = (size_t)T, kz = (size_t)kmax;
 
@@ -235,13 +242,52 @@ int Engine::turn() {
     if (int rc = propose(kPhaseBacktrack)) return rc;
     if (int rc = read_states()) return rc;
   }
+  if (graphs_ && mixed_) {
+    if (!exec_)
+      if (int rc = capture()) return rc;
+    HIPCHK(hipGraphLaunch(exec_, st_));
+  } else if (int rc = ahead()) {
+    return rc;
+  }
+  if (int rc = read_states()) return rc;
+  for (int32_t t = 0; t < T_; ++t) launch_[t] = h_[t].active != 0 ? 1 : 0;
+  return IHT_OK;
+}
+
+// The speculative iterations of a turn: gradient of the accepted proposals, commit + next step
+// size, next proposal; every launch gated per slot on the device flags.
+int Engine::ahead() {
   for (int a = 0; a < kAhead; ++a) {
     if (int rc = gradient(kPhaseGo)) return rc;
     HIPCHK(solve_commit_mu(Q_, 1, tol_main_, o_.max_iter, st_));
     if (int rc = propose(kPhaseActive)) return rc;
   }
-  if (int rc = read_states()) return rc;
-  for (int32_t t = 0; t < T_; ++t) launch_[t] = h_[t].active != 0 ? 1 : 0;
+  return IHT_OK;
+}
+
+// Records ahead() into exec_ on the private stream (nothing runs while recording). The sequence
+// holds kernel launches only (no memory set or copy nodes); their arguments are the engine's
+// fixed buffers and the per-slot flags they read on the device.
+int Engine::capture() {
+  if (!cap_st_) HIPCHK(hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking));
+  hipStream_t user = st_;
+  st_ = cap_st_;
+  HIPCHK(hipStreamBeginCapture(cap_st_, hipStreamCaptureModeThreadLocal));
+  const int rc = ahead();
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cap_st_, &graph);
+  st_ = user;
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+  const hipError_t ei = hipGraphInstantiate(&exec_, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    exec_ = nullptr;
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
   return IHT_OK;
 }
 

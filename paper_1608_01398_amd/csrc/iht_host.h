@@ -154,6 +154,16 @@ class Engine {
  public:
   static constexpr int kAhead = 2;
 
+  Engine() = default;
+  Engine(const Engine&) = delete;
+  Engine& operator=(const Engine&) = delete;
+  ~Engine();
+  // Replay the speculative part of each turn from a HIP graph (matrix-core gradient only: its
+  // launch sequence does not depend on which slots are iterating). Captured at the first turn on a
+  // private stream, replayed on the engine's stream; for engines that run many turns with the same
+  // buffers (the solve server).
+  void use_graphs(bool on) { graphs_ = on; }
+
   // Device state of T slots with model sizes up to kmax (allocated in W). Slot t reads its trait
   // at Y + t * ldy and keeps its loss trace at trace + t * (max_iter + 1).
   int setup(const iht_geno* g, SolveWork* W, int32_t T, int32_t kmax, const Unpen& U, const double* Y, int64_t ldy,
@@ -179,6 +189,8 @@ class Engine {
  private:
   int gradient(int32_t phase);
   int propose(int32_t phase);
+  int ahead();
+  int capture();
   int read_states();
   int upload_flags(const uint8_t* flags, const int32_t** dev);
 
@@ -200,6 +212,9 @@ class Engine {
   OutRow* rows_h_ = nullptr;
   uint32_t* terr_ = nullptr;
   std::vector<uint8_t> launch_;  // slots that get a per-slot gradient launch (FP64 / FP32 passes)
+  bool graphs_ = false;
+  hipStream_t cap_st_ = nullptr;     // private stream the graph is captured on
+  hipGraphExec_t exec_ = nullptr;    // the kAhead iterations of a turn
 };
 
 }  // namespace iht

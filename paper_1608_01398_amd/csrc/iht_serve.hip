@@ -19,6 +19,11 @@
 
 using namespace iht;
 
+// The server replays each turn's speculative iterations from a HIP graph (int8 matrix-core path).
+#ifndef IHT_SERVER_GRAPHS
+#define IHT_SERVER_GRAPHS 1
+#endif
+
 namespace {
 
 struct Request {
@@ -224,6 +229,7 @@ int iht_server_create(const iht_geno* g, int32_t slots, int32_t kmax, int64_t hb
     return bail(hip_fail(e, "hipMalloc(server slots)"));
   if (int rc = S->E.setup(g, &S->W, slots, kmax, S->U, S->Y.as<double>(), L.n, S->trace.as<double>(), o, S->st))
     return bail(rc);
+  S->E.use_graphs(IHT_SERVER_GRAPHS != 0);
   const int64_t slot_bytes = work_bytes(S->W) + (int64_t)S->Y.bytes + (int64_t)S->trace.bytes;
   const int64_t block_bytes = (int64_t)stats_block_bytes(L);
   if (hbm_budget < slot_bytes + block_bytes)
