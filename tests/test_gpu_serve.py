@@ -68,7 +68,7 @@ def assert_same(res, j, ref):
     assert torch.equal(res["loss_trace"][j, :it + 1], ref["loss_trace"])
 
 
-@pytest.mark.parametrize("precision", [iht.FP64, iht.MIXED_I8])
+@pytest.mark.parametrize("precision", [iht.FP64, iht.FP32, iht.MIXED_I8])
 def test_served_equals_alone_with_staggered_arrivals(prob, precision):
     """Requests arrive between steps while others iterate; one waits for slots; all equal alone."""
     say(f"serve staggered precision={precision}")
@@ -186,4 +186,24 @@ def test_server_rejects_bad_requests(prob):
         srv.done(99)
     assert e.value.code == iht.EINVAL
     assert srv.info()["queued"] == 0
+    srv.close()
+
+
+def test_server_idle_steps_and_info(prob):
+    """Steps with nothing queued do nothing; the counters follow a request through the server."""
+    srv = iht.Server(prob["geno"], slots=8, kmax=10, hbm_budget=8 << 30)
+    assert srv.step() == 0
+    inf = srv.info()
+    assert (inf["queued"], inf["running"], inf["completed"], inf["slots_busy"], inf["turns"]) == (0, 0, 0, 0, 0)
+    assert inf["slots"] == 8 and inf["stats_blocks"] == 8 and inf["device_bytes"] > 0
+    rid = srv.submit(dev(prob["traits"][:3]), [4, 6, 8])
+    assert srv.info()["queued"] == 1 and not srv.done(rid)
+    srv.step()
+    inf = srv.info()
+    assert inf["queued"] == 0 and inf["slots_busy"] + 3 * inf["completed"] == 3
+    srv.run_until_idle()
+    inf = srv.info()
+    assert inf["completed"] == 1 and inf["slots_busy"] == 0 and inf["turns"] >= 1 and srv.done(rid)
+    res = srv.result(rid)
+    assert list(res["statuses"]) == [iht.OK] * 3
     srv.close()
