@@ -31,6 +31,12 @@
  *   R17 cross-validation: the caller assigns every subject to one of q folds; the held-out MSE is
  *      the mean of (y - prediction)^2 over the fold, predicted with the training fold's u, v; the
  *      model size of least mean MSE wins (the first in the given order on an exact tie).
+ *   R18 logistic IHT (Discussion names logistic regression as the extension; no algorithm given):
+ *      f = sum_T [log(1 + exp(eta_i)) - y_i eta_i], eta = A beta, so g = A^T (y - sigma(eta)) = -grad f
+ *      and the same gradient pass applies; step mu = ||g_{S u C}||^2 / sum_T w_i (A_{S u C} g)_i^2
+ *      with w = sigma(eta)(1 - sigma(eta)) at the current beta (the normalised step with the
+ *      curvature of f); a proposal is taken when f does not increase, else mu is halved (the omega
+ *      rule is a least-squares bound and is not used). y in [0, 1].
  *
  * Plain sequential sums everywhere, compiled with -O2 -ffp-contract=off. OpenMP splits only
  * independent per-SNP work (each SNP's sum keeps its own sequential order), as in the paper's
@@ -269,6 +275,24 @@ static int64_t support_union(const int64_t *a, const int64_t *b, int64_t k, int6
     return m;
 }
 
+/* Logistic pieces (reading R18): sigma(x) = 1 / (1 + e^-x) evaluated without overflow, and the
+ * per-subject loss log(1 + e^x) - y x = max(x, 0) + log1p(e^-|x|) - y x. */
+static double sigmoid(double x) {
+    if (x >= 0.0) return 1.0 / (1.0 + exp(-x));
+    double e = exp(x);
+    return e / (1.0 + e);
+}
+
+static double logistic_loss(const design *A, const double *y, const double *eta) {
+    double s = 0.0;
+    for (int64_t t = 0; t < A->nT; ++t) {
+        int64_t i = A->T[t];
+        double x = eta[i];
+        s += ((x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x)))) - y[i] * x;
+    }
+    return s;
+}
+
 /* w = beta + mu g on SNPs and unpenalised columns; S+ = top-k |w|; beta+ = w on S+, 0 elsewhere. */
 static int propose(const design *A, int64_t k, double mu, const double *beta, const double *g, const double *bc, const double *gc,
                    double *w, int64_t *Sp, double *betap, double *bcp) {
@@ -282,11 +306,13 @@ static int propose(const design *A, int64_t k, double mu, const double *beta, co
     return REF_OK;
 }
 
-int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, const uint8_t *subset, const double *y,
-                const float *Z, int32_t cz, int32_t intercept, int32_t k, double tol, int32_t max_iter, int32_t max_backtrack,
-                double c, double shrink, int64_t *support /* [k] */, double *beta_S /* [k] */, double *beta_cov /* [cz+icpt] */,
-                double *loss_trace /* [max_iter+1] */, int32_t *n_iter, double *mu_trace /* [max_iter] or NULL */) {
+/* family 0: least squares (eq. leastsquaresloss); family 1: logistic (reading R18). */
+int iht_ref_fit_family(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, const uint8_t *subset, const double *y,
+                       const float *Z, int32_t cz, int32_t intercept, int32_t k, double tol, int32_t max_iter,
+                       int32_t max_backtrack, double c, double shrink, int32_t family, int64_t *support, double *beta_S,
+                       double *beta_cov, double *loss_trace, int32_t *n_iter, double *mu_trace) {
     if (!bed || !y || !support || !beta_S || !loss_trace || !n_iter || n < 1 || p < 1 || row_bytes < (n + 3) / 4) return REF_EINVAL;
+    if (family != 0 && family != 1) return REF_EINVAL;
     if (k < 1 || k > p || cz < 0 || (cz > 0 && !Z) || max_iter < 0 || max_backtrack < 0) return REF_EINVAL;
     if (!(c > 0.0 && c < 1.0) || !(shrink > 0.0 && shrink < 1.0) || !(tol >= 0.0)) return REF_EINVAL;
     int32_t nc = cz + (intercept ? 1 : 0);
@@ -298,16 +324,20 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
     double *g = (double *)malloc(sizeof(double) * p), *w = (double *)malloc(sizeof(double) * p);
     double *dlt = (double *)calloc(p, sizeof(double));
     double *r = (double *)calloc(n, sizeof(double)), *tmp = (double *)calloc(n, sizeof(double));
+    double *eta = (double *)calloc(n, sizeof(double)); /* logistic: A beta at the current iterate */
     double bc[64] = {0}, bcp[64] = {0}, gc[64] = {0}, dc[64] = {0};
     int64_t *S = (int64_t *)malloc(sizeof(int64_t) * k), *Sp = (int64_t *)malloc(sizeof(int64_t) * k);
     int64_t *U = (int64_t *)malloc(sizeof(int64_t) * 2 * k);
     int rc = REF_OK;
-    if (!T || !u || !v || !beta || !betap || !g || !w || !dlt || !r || !tmp || !S || !Sp || !U || nc > 64) {
+    if (!T || !u || !v || !beta || !betap || !g || !w || !dlt || !r || !tmp || !eta || !S || !Sp || !U || nc > 64) {
         rc = REF_ENOMEM;
         goto done;
     }
     for (int64_t i = 0; i < n; ++i)
         if (!isfinite(y[i]) || (subset && !(subset[i] == 0 || subset[i] == 1))) { rc = REF_ENONFINITE; goto done; }
+    if (family == 1)
+        for (int64_t i = 0; i < n; ++i)
+            if ((!subset || subset[i]) && !(y[i] >= 0.0 && y[i] <= 1.0)) { rc = REF_EINVAL; goto done; }
     for (int64_t q = 0; q < (int64_t)cz * n; ++q)
         if (!isfinite(Z[q])) { rc = REF_ENONFINITE; goto done; }
 
@@ -317,9 +347,10 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
     if (rc) goto done;
     design A = {bed, row_bytes, n, p, T, nT, u, v, Z, cz, intercept ? 1 : 0};
 
-    /* Initialisation (reading R4): beta = 0, r = y, g = A^T r, S = top-k |g| (reading R1). */
-    for (int64_t t = 0; t < nT; ++t) r[T[t]] = y[T[t]];
-    loss_trace[0] = 0.5 * sumsq_T(&A, r);
+    /* Initialisation (reading R4): beta = 0, r = y (logistic: y - 1/2), g = A^T r, S = top-k |g|
+     * (reading R1). */
+    for (int64_t t = 0; t < nT; ++t) r[T[t]] = family ? y[T[t]] - sigmoid(0.0) : y[T[t]];
+    loss_trace[0] = family ? logistic_loss(&A, y, eta) : 0.5 * sumsq_T(&A, r);
     apply_At(&A, r, g, gc);
     rc = topk_abs(g, p, k, S);
     if (rc) goto done;
@@ -332,16 +363,36 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
         for (int64_t t = 0; t < k; ++t) num += g[S[t]] * g[S[t]];
         for (int32_t q = 0; q < nc; ++q) num += gc[q] * gc[q];
         apply_A(&A, S, k, g, gc, tmp);
-        double den = sumsq_T(&A, tmp);
+        double den = 0.0;
+        if (family) { /* curvature weights at the current beta (reading R18) */
+            for (int64_t t = 0; t < nT; ++t) {
+                double sg = sigmoid(eta[T[t]]);
+                den += (sg * (1.0 - sg)) * (tmp[T[t]] * tmp[T[t]]);
+            }
+        } else {
+            den = sumsq_T(&A, tmp);
+        }
         if (den == 0.0) { status = REF_OK; break; }
         double mu = num / den;
 
         rc = propose(&A, k, mu, beta, g, bc, gc, w, Sp, betap, bcp);
         if (rc) goto done;
 
-        /* Backtracking (reading R2): only when the support moves; accept when mu < omega. */
+        /* Backtracking (reading R2): only when the support moves; accept when mu < omega.
+         * Logistic (reading R18): accept when the loss does not increase. */
         int nbt = 0, stalled = 0;
-        while (!same_support(S, Sp, k)) {
+        double fplus = 0.0;
+        while (family) {
+            apply_A(&A, Sp, k, betap, bcp, tmp);
+            fplus = logistic_loss(&A, y, tmp);
+            if (fplus <= loss_trace[m]) break;
+            if (nbt == max_backtrack) { stalled = 1; break; }
+            mu = mu * shrink;
+            nbt++;
+            rc = propose(&A, k, mu, beta, g, bc, gc, w, Sp, betap, bcp);
+            if (rc) goto done;
+        }
+        while (!family && !same_support(S, Sp, k)) {
             int64_t nu = support_union(S, Sp, k, U);
             double dd = 0.0;
             for (int64_t q = 0; q < nu; ++q) {
@@ -366,10 +417,19 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
         if (stalled) { status = REF_STALLED; break; }
         if (mu_trace) mu_trace[m] = mu;
 
-        /* Residual, loss (eq. leastsquaresloss) and gradient (eq. normal_grad) at beta+. */
+        /* Residual, loss (eq. leastsquaresloss; logistic: reading R18) and gradient (eq. normal_grad)
+         * at beta+. */
         apply_A(&A, Sp, k, betap, bcp, tmp);
-        for (int64_t t = 0; t < nT; ++t) r[T[t]] = y[T[t]] - tmp[T[t]];
-        loss_trace[m + 1] = 0.5 * sumsq_T(&A, r);
+        if (family) {
+            for (int64_t t = 0; t < nT; ++t) {
+                eta[T[t]] = tmp[T[t]];
+                r[T[t]] = y[T[t]] - sigmoid(tmp[T[t]]);
+            }
+            loss_trace[m + 1] = fplus;
+        } else {
+            for (int64_t t = 0; t < nT; ++t) r[T[t]] = y[T[t]] - tmp[T[t]];
+            loss_trace[m + 1] = 0.5 * sumsq_T(&A, r);
+        }
         apply_At(&A, r, g, gc);
 
         /* Convergence (reading R5). */
@@ -402,9 +462,17 @@ int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, con
     for (int32_t q = 0; q < nc; ++q) beta_cov[q] = bc[q];
     rc = status;
 done:
-    free(T); free(u); free(v); free(beta); free(betap); free(g); free(w); free(dlt); free(r); free(tmp);
+    free(T); free(u); free(v); free(beta); free(betap); free(g); free(w); free(dlt); free(r); free(tmp); free(eta);
     free(S); free(Sp); free(U);
     return rc;
+}
+
+int iht_ref_fit(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, const uint8_t *subset, const double *y,
+                const float *Z, int32_t cz, int32_t intercept, int32_t k, double tol, int32_t max_iter, int32_t max_backtrack,
+                double c, double shrink, int64_t *support /* [k] */, double *beta_S /* [k] */, double *beta_cov /* [cz+icpt] */,
+                double *loss_trace /* [max_iter+1] */, int32_t *n_iter, double *mu_trace /* [max_iter] or NULL */) {
+    return iht_ref_fit_family(bed, n, p, row_bytes, subset, y, Z, cz, intercept, k, tol, max_iter, max_backtrack, c, shrink, 0,
+                              support, beta_S, beta_cov, loss_trace, n_iter, mu_trace);
 }
 
 /* ---- prediction by a fitted model (Methods, Bandwidth optimization of IHT: the product X_st beta) ----

@@ -51,10 +51,12 @@ def lib():
         L.iht_ref_gradient.argtypes = [P, I64, I64, I64, P, P, P, P, P]
         L.iht_ref_project.argtypes = [P, I64, I32, P, P]
         L.iht_ref_fit.argtypes = [P, I64, I64, I64, P, P, P, I32, I32, I32, D, I32, I32, D, D, P, P, P, P, P, P]
+        L.iht_ref_fit_family.argtypes = [P, I64, I64, I64, P, P, P, I32, I32, I32, D, I32, I32, D, D, I32, P, P, P, P, P,
+                                         P]
         L.iht_ref_cv.argtypes = [P, I64, I64, I64, P, I32, P, P, I32, I32, P, I32, D, I32, I32, D, D, P, P]
         L.iht_ref_predict.argtypes = [P, I64, I64, I64, P, P, P, P, I32, P, I32, I32, P, P]
         for f in (L.iht_ref_decode, L.iht_ref_stats, L.iht_ref_standardize, L.iht_ref_gradient, L.iht_ref_project,
-                  L.iht_ref_fit, L.iht_ref_cv, L.iht_ref_predict):
+                  L.iht_ref_fit, L.iht_ref_cv, L.iht_ref_predict, L.iht_ref_fit_family):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -135,8 +137,9 @@ def project(w, k):
     return sup, out
 
 
-def fit(bed, n, y, k, Z=None, intercept=True, subset=None, **opts):
-    """Plain FP64 IHT. Z: float32 covariates as a [c, n] array (column-major [n x c]).
+def fit(bed, n, y, k, Z=None, intercept=True, subset=None, family=0, **opts):
+    """Plain FP64 IHT. Z: float32 covariates as a [c, n] array (column-major [n x c]); family 0: least
+    squares, 1: logistic (y in [0, 1]).
 
     Returns a dict with status, support, beta_S, beta_cov, loss_trace[:n_iter+1], n_iter, mu_trace.
     """
@@ -158,9 +161,9 @@ def fit(bed, n, y, k, Z=None, intercept=True, subset=None, **opts):
     trace = np.full(o["max_iter"] + 1, np.nan)
     mu = np.full(max(o["max_iter"], 1), np.nan)
     nit = ctypes.c_int32(0)
-    rc = lib().iht_ref_fit(_p(bed), n, p, rb, _p(m), _p(y), _p(Z), cz, 1 if intercept else 0, k, o["tol"], o["max_iter"],
-                           o["max_backtrack"], o["c"], o["shrink"], _p(sup), _p(bS), _p(bc), _p(trace),
-                           ctypes.byref(nit), _p(mu))
+    rc = lib().iht_ref_fit_family(_p(bed), n, p, rb, _p(m), _p(y), _p(Z), cz, 1 if intercept else 0, k, o["tol"],
+                                  o["max_iter"], o["max_backtrack"], o["c"], o["shrink"], family, _p(sup), _p(bS), _p(bc),
+                                  _p(trace), ctypes.byref(nit), _p(mu))
     if rc < 0:
         raise ValueError(f"iht_ref_fit: {rc}")
     it = nit.value

@@ -513,3 +513,115 @@ def test_cv_rejects_bad_folds():
     for folds, q in ((good, 1), ((good + 3).astype(np.uint8), 3), (np.zeros(n, np.uint8), 3)):
         with pytest.raises(ValueError):
             oracle.cv(bed, n, y, [1, 2], folds, q)
+
+
+# ------------------------------------------------------------------ logistic IHT (reading R18)
+
+def _numpy_xst(bed, n, cols):
+    """Standardised columns [n, len(cols)] from the decoder and the NumPy u, v definition."""
+    dose = oracle.decode(bed, n).astype(np.float64)[np.asarray(cols)]
+    obs = dose >= 0
+    u = np.where(obs, dose, 0.0).sum(1) / obs.sum(1)
+    imp = np.where(obs, dose, u[:, None])
+    sd = imp.std(axis=1)
+    v = np.where(sd > 0, 1.0 / np.where(sd > 0, sd, 1.0), 0.0)
+    return np.where(obs, v[:, None] * (dose - u[:, None]), 0.0).T
+
+
+def _logistic_loss(X, y, b):
+    eta = X @ b
+    return float(np.sum(np.maximum(eta, 0.0) + np.log1p(np.exp(-np.abs(eta))) - y * eta))
+
+
+def _logistic_mle(X, y, iters=100):
+    b = np.zeros(X.shape[1])
+    for _ in range(iters):
+        pr = 1.0 / (1.0 + np.exp(-(X @ b)))
+        H = X.T @ (X * (pr * (1 - pr))[:, None])
+        step = np.linalg.solve(H, X.T @ (y - pr))
+        b = b + step
+        if np.abs(step).max() < 1e-14 * max(1.0, np.abs(b).max()):
+            break
+    return b
+
+
+def _logistic_problem(n, p, kt, seed, scale=1.0):
+    bed, qf = synth.make_genotypes(n, p, seed)
+    rng = np.random.default_rng(seed)
+    cols = np.sort(rng.choice(p, kt, replace=False))
+    b = scale * rng.uniform(0.8, 1.5, kt) * rng.choice([-1, 1], kt)
+    eta = _numpy_xst(bed, n, cols) @ b - 0.3
+    y = (rng.random(n) < 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    return bed, y, cols
+
+
+def test_logistic_loss_at_zero_and_after_one_step():
+    """f(0) = n log 2 (sigma(0) = 1/2); after one step the trace holds f at the returned model."""
+    n, p = 300, 40
+    bed, y, _ = _logistic_problem(n, p, 3, 51)
+    one = oracle.fit(bed, n, y, 3, family=1, max_iter=1)
+    assert abs(one["loss_trace"][0] - n * np.log(2.0)) <= 1e-12 * n
+    X = np.concatenate([_numpy_xst(bed, n, one["support"]), np.ones((n, 1))], axis=1)
+    b = np.concatenate([one["beta_S"], one["beta_cov"]])
+    assert abs(one["loss_trace"][1] - _logistic_loss(X, y, b)) <= 1e-12 * one["loss_trace"][1]
+    assert one["loss_trace"][1] <= one["loss_trace"][0]
+    # the first step size: the curvature-weighted normalised step at beta = 0 (all weights 1/4),
+    # up to halvings
+    Xall = _numpy_xst(bed, n, np.arange(p))
+    r0 = y - 0.5
+    g = Xall.T @ r0
+    gc = r0.sum()
+    S0 = np.sort(np.lexsort((np.arange(p), -np.abs(g)))[:3])
+    num = np.sum(g[S0] ** 2) + gc ** 2
+    den = np.sum(0.25 * (Xall[:, S0] @ g[S0] + gc) ** 2)
+    mu0 = num / den
+    ratio = one["mu_trace"][0] / mu0
+    j = round(-np.log2(ratio))
+    assert j >= 0 and abs(ratio - 0.5 ** j) <= 1e-12, (one["mu_trace"][0], mu0)
+
+
+def test_logistic_fixed_point_is_the_mle_on_its_support():
+    """Converged: the coefficients are the logistic maximum-likelihood fit on the support and the
+    intercept (the score X_S^T (y - sigma) vanishes), and the loss never increased."""
+    n, p, k = 500, 80, 4
+    bed, y, cols = _logistic_problem(n, p, k, 52)
+    res = oracle.fit(bed, n, y, k, family=1, tol=1e-13, max_iter=2000)
+    assert res["status"] == 0
+    X = np.concatenate([_numpy_xst(bed, n, res["support"]), np.ones((n, 1))], axis=1)
+    b = _logistic_mle(X, y)
+    got = np.concatenate([res["beta_S"], res["beta_cov"]])
+    np.testing.assert_allclose(got, b, rtol=1e-6, atol=1e-8)
+    tr = res["loss_trace"]
+    assert np.all(np.diff(tr) <= 1e-12 * tr[0])
+    assert set(res["support"]) == set(cols)
+
+
+def test_logistic_strong_signal_finds_the_best_subset():
+    """Brute force over all 2-subsets of 12 SNPs (logistic MLE of each): IHT with k = 2 returns the
+    subset of least negative log-likelihood."""
+    import itertools
+    n, p = 400, 12
+    bed, y, cols = _logistic_problem(n, p, 2, 53, scale=1.5)
+    Xall = _numpy_xst(bed, n, np.arange(p))
+    best, best_loss = None, np.inf
+    for sub in itertools.combinations(range(p), 2):
+        X = np.concatenate([Xall[:, list(sub)], np.ones((n, 1))], axis=1)
+        loss = _logistic_loss(X, y, _logistic_mle(X, y))
+        if loss < best_loss:
+            best, best_loss = sub, loss
+    res = oracle.fit(bed, n, y, 2, family=1, tol=1e-12, max_iter=1000)
+    assert tuple(res["support"]) == best
+    assert abs(res["loss_trace"][-1] - best_loss) <= 1e-9 * best_loss
+
+
+def test_logistic_rejects_y_outside_unit_interval():
+    n, p = 50, 20
+    bed, y, _ = _logistic_problem(n, p, 2, 54)
+    y2 = y.copy()
+    y2[3] = 2.0
+    with pytest.raises(ValueError):
+        oracle.fit(bed, n, y2, 2, family=1)
+    # outside the subject set it is ignored
+    sub = np.ones(n, np.uint8)
+    sub[3] = 0
+    assert oracle.fit(bed, n, y2, 2, family=1, subset=sub)["status"] >= 0
