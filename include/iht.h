@@ -53,6 +53,11 @@ extern "C" {
 #define IHT_MIXED_I8 2 /* fits only: one matrix-core pass per iteration for all solves (int8 genotype */
                        /* and residual-digit operands, exact int32 sums, FP64 combination)           */
 
+/* model family of a fit (iht_opts.family) */
+#define IHT_GAUSSIAN 0 /* least squares, f = 1/2 ||y - A beta||^2 (Methods, eq. leastsquaresloss)    */
+#define IHT_LOGISTIC 1 /* logistic regression, f = sum_T [log(1 + e^eta) - y eta], eta = A beta, y in */
+                       /* [0, 1] (the extension the Discussion names); IHT_FP64 only                 */
+
 /* iht_geno_create flags: where `bed` lives */
 #define IHT_HOST_PTR 0
 #define IHT_DEVICE_PTR 1
@@ -69,6 +74,12 @@ typedef struct iht_stats iht_stats; /* u, v [p] FP64 and the subject set T they 
  * stops at max(tol, mixed_tol); each converged solve is then refined in FP64 on its final support
  * to the least-squares fit on S and the unpenalised columns (the fixed point of the IHT map on a
  * fixed support), with at most polish_iter conjugate-gradient steps and the stopping rule at tol.
+ * IHT_LOGISTIC: the residual is y - sigma(eta), so the same gradient pass gives A^T r = -grad f; the
+ * step is mu = ||g_{S u C}||^2 / sum_T w_i (A_{S u C} g_{S u C})_i^2 with w = sigma(eta)(1 - sigma(eta))
+ * at the current beta, and a proposal is taken when f does not increase by more than 1e-12 |f| (the
+ * rounding of the loss sums; else mu is halved, at most
+ * max_backtrack times; c is not used). A y outside [0, 1] inside the subject set is reported as
+ * IHT_ENONFINITE. Only with IHT_FP64 (else IHT_EUNSUPPORTED); not in iht_cv.
  */
 typedef struct iht_opts {
     double tol;            /* stop when S+ = S and ||beta+ - beta||_inf <= tol*max(1,||beta+||_inf); default 1e-10 */
@@ -79,6 +90,7 @@ typedef struct iht_opts {
     int32_t precision;     /* IHT_FP64, IHT_FP32 or IHT_MIXED_I8; default IHT_FP64          */
     double mixed_tol;      /* iteration tolerance of the reduced precisions; default 1e-6   */
     int32_t polish_iter;   /* FP64 refinement steps after a reduced-precision solve; default 200 */
+    int32_t family;        /* IHT_GAUSSIAN (default) or IHT_LOGISTIC                        */
 } iht_opts;
 
 /* Fill *o with the defaults above. */

@@ -35,8 +35,9 @@
  *      f = sum_T [log(1 + exp(eta_i)) - y_i eta_i], eta = A beta, so g = A^T (y - sigma(eta)) = -grad f
  *      and the same gradient pass applies; step mu = ||g_{S u C}||^2 / sum_T w_i (A_{S u C} g)_i^2
  *      with w = sigma(eta)(1 - sigma(eta)) at the current beta (the normalised step with the
- *      curvature of f); a proposal is taken when f does not increase, else mu is halved (the omega
- *      rule is a least-squares bound and is not used). y in [0, 1].
+ *      curvature of f); a proposal is taken when f does not increase beyond 1e-12 |f| (the rounding
+ *      of the loss sums, so that a converged iterate is not rejected on rounding alone), else mu is
+ *      halved (the omega rule is a least-squares bound and is not used). y in [0, 1].
  *
  * Plain sequential sums everywhere, compiled with -O2 -ffp-contract=off. OpenMP splits only
  * independent per-SNP work (each SNP's sum keeps its own sequential order), as in the paper's
@@ -385,7 +386,7 @@ int iht_ref_fit_family(const uint8_t *bed, int64_t n, int64_t p, int64_t row_byt
         while (family) {
             apply_A(&A, Sp, k, betap, bcp, tmp);
             fplus = logistic_loss(&A, y, tmp);
-            if (fplus <= loss_trace[m]) break;
+            if (fplus <= loss_trace[m] + 1e-12 * fabs(loss_trace[m])) break;
             if (nbt == max_backtrack) { stalled = 1; break; }
             mu = mu * shrink;
             nbt++;

@@ -29,6 +29,7 @@ void iht_opts_default(iht_opts* o) {
   o->precision = IHT_FP64;
   o->mixed_tol = 1e-6;
   o->polish_iter = 200;
+  o->family = IHT_GAUSSIAN;
 }
 
 const char* iht_last_error(void) { return last_error_text().c_str(); }
@@ -423,6 +424,7 @@ int iht_cv(const iht_geno* g, const double* y, const float* Z, int32_t cz, int32
     kmax = std::max(kmax, ks[a]);
   }
   if (int rc = check_opts(o, "iht_cv")) return rc;
+  if (o.family != IHT_GAUSSIAN) return fail(IHT_EUNSUPPORTED, "iht_cv: least squares only (held-out MSE)");
   std::vector<int64_t> count(q, 0);
   for (int64_t i = 0; i < L.n; ++i) {
     if (folds[i] >= q) return fail(IHT_EINVAL, "iht_cv: fold index >= q");

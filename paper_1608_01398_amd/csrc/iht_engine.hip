@@ -17,8 +17,11 @@ size_t align16(size_t b) { return (b + 15) / 16 * 16; }
 int check_opts(const iht_opts& o, const char* who) {
   if (o.max_iter < 0 || o.max_backtrack < 0 || !(o.c > 0.0 && o.c < 1.0) || !(o.shrink > 0.0 && o.shrink < 1.0) ||
       !(o.tol >= 0.0) || !(o.mixed_tol >= 0.0) || o.polish_iter < 0 ||
-      (o.precision != IHT_FP64 && o.precision != IHT_FP32 && o.precision != IHT_MIXED_I8))
+      (o.precision != IHT_FP64 && o.precision != IHT_FP32 && o.precision != IHT_MIXED_I8) ||
+      (o.family != IHT_GAUSSIAN && o.family != IHT_LOGISTIC))
     return fail(IHT_EINVAL, std::string(who) + ": bad options");
+  if (o.family == IHT_LOGISTIC && o.precision != IHT_FP64)
+    return fail(IHT_EUNSUPPORTED, std::string(who) + ": the logistic family runs in IHT_FP64 only");
   return IHT_OK;
 }
 
@@ -122,6 +125,7 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
   Q.pmu = W.pmu.as<double>();
   Q.ysum = W.ysum.as<double>();
   Q.pw = W.pw.as<double>();
+  Q.family = o.family;
 
   TopkJob& J = J_;
   J = TopkJob{};

@@ -36,6 +36,7 @@ struct SolveSet {
   double* part;  // [T][nb][pst]
   double* pmu;   // [T][nb]
   double* ysum;  // [T][kYsumStride]: sum_T y, then sum_T A_c of the unpenalised columns
+  int32_t family;  // IHT_GAUSSIAN or IHT_LOGISTIC (all solves of the set)
 };
 
 // Subjects per workgroup of the subject-split steps (one per lane).

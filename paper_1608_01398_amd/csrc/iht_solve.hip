@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void k_init(SolveSet Q, int32_t max_iter,
   double sy = 0.0;
   for (int64_t i = threadIdx.x; i < Q.n; i += kThreads) {
     if (mask[i] == 0.0) continue;
-    if (!isfinite(y[i])) b = 1;
+    if (!isfinite(y[i]) || (Q.family == IHT_LOGISTIC && !(y[i] >= 0.0 && y[i] <= 1.0))) b = 1;
     sy += y[i];
     for (int c = 0; c < Q.U.cz; ++c)
       if (!isfinite(Q.U.Z[(int64_t)c * Q.n + i])) b = 1;
@@ -344,6 +344,17 @@ __device__ double sum_partials(const double* P0, int32_t nb, int32_t pst, int f,
   return bsum(x, s);
 }
 
+// Logistic family: sigma(x) = 1 / (1 + e^-x) without overflow, and the per-subject loss
+// log(1 + e^x) - y x = max(x, 0) + log1p(e^-|x|) - y x.
+__device__ __forceinline__ double sigmoid(double x) {
+  if (x >= 0.0) return 1.0 / (1.0 + exp(-x));
+  const double e = exp(x);
+  return e / (1.0 + e);
+}
+__device__ __forceinline__ double logistic_loss(double x, double y) {
+  return ((x > 0.0 ? x : 0.0) + log1p(exp(-fabs(x)))) - y * x;
+}
+
 // Residual of the solves in `phase` at their proposal (kCheck), or at beta = 0 for every solve with
 // finite inputs: r = mask (y - A_{S+ u C} beta+) and the residual centred over the subject set for
 // the gradient pass, rc = r - m on T, 0 elsewhere (up to n_pad). The centring constant m is the
@@ -357,6 +368,10 @@ __device__ double sum_partials(const double* P0, int32_t nb, int32_t pst, int f,
 // proposal is bcp = bc + mu gc and, when the support moved, omega = (1-c)||Delta||^2 / ||A Delta||^2
 // over S u S+ u C, with Delta = beta+ - beta on S+, -beta on S \ S+, bcp - bc on C. r and rc are
 // formed before the decision: until a proposal is taken nothing reads them.
+//
+// Logistic family: r = mask (y - sigma(eta)) with eta the fit above, rc = r (no centring constant is
+// known in advance; any constant is exact), and the first partial is the loss sum_T [log(1 + e^eta)
+// - y eta] instead of ||r||^2; the proposal is judged by that loss, so the omega sums are skipped.
 template <bool kCheck>
 __global__ __launch_bounds__(kMbThreads) void k_residual(SolveSet Q, int32_t phase) {
   const int t = blockIdx.y, b = blockIdx.x;
@@ -396,19 +411,21 @@ __global__ __launch_bounds__(kMbThreads) void k_residual(SolveSet Q, int32_t pha
     a = acc_unpen(Q.U, Q.n, s.ucoef, nc, ii, a);
     fit = combine_waves(a, s);
   }
+  const bool logistic = Q.family == IHT_LOGISTIC;
   double msum = ys[0];
   if (kCheck)
     for (int q = 0; q < nc; ++q) msum -= s.ucoef[q] * ys[1 + q];
-  const double m = msum / (double)Q.sv[t].nT;
-  const double ri = ok ? V.y[ii] - fit : 0.0;
+  const double m = logistic ? 0.0 : msum / (double)Q.sv[t].nT;
+  const double ri = ok ? V.y[ii] - (logistic ? sigmoid(fit) : fit) : 0.0;
   const double rci = ok ? ri - m : 0.0;
+  const double li = logistic ? (ok ? logistic_loss(fit, V.y[ii]) : 0.0) : ri * ri;
   if (w == 0 && i < Q.n_pad) {
     V.r[i] = ri;
     V.rc[i] = rci;
   }
 
   double ad2 = 0.0, dd = 0.0;
-  if (kCheck && !same) {
+  if (kCheck && !same && !logistic) {
     double dd_t = 0.0, a = 0.0;
     for (int e0 = 0; e0 < 2 * k; e0 += kMbChunk) {
       const int ne = min(kMbChunk, 2 * k - e0);
@@ -447,7 +464,7 @@ __global__ __launch_bounds__(kMbThreads) void k_residual(SolveSet Q, int32_t pha
 
   if (w == 0) {
     double* P = Q.part + ((int64_t)t * Q.nb + b) * Q.pst;
-    const double rr = wsum(ri * ri), R = wsum(rci), sa = wsum(ad2);
+    const double rr = wsum(li), R = wsum(rci), sa = wsum(ad2);
     if (lane == 0) {
       P[0] = rr;
       P[1] = R;
@@ -476,12 +493,15 @@ __global__ __launch_bounds__(kMbThreads) void k_decide(SolveSet Q, int32_t phase
   FitState* fs = V.fs;
   const double* P0 = Q.part + (int64_t)t * Q.nb * Q.pst;
   const int nc = V.nc;
+  const bool logistic = Q.family == IHT_LOGISTIC;
   if (kCheck) {
     const double mu = fs->mu;
     const int same = P0[4] != 0.0 ? 1 : 0;
     double omega = 0.0;
     int accept = 1;
-    if (!same) {
+    if (logistic) {  // taken when the loss does not increase beyond the rounding of its sums
+      accept = sum_partials(P0, Q.nb, Q.pst, 0, s) <= fs->loss + 1e-12 * fabs(fs->loss) ? 1 : 0;
+    } else if (!same) {
       const double sa = sum_partials(P0, Q.nb, Q.pst, 2, s);
       omega = (1.0 - c) * P0[3] / sa;
       accept = mu < omega ? 1 : 0;
@@ -502,7 +522,8 @@ __global__ __launch_bounds__(kMbThreads) void k_decide(SolveSet Q, int32_t phase
     }
     if (!accept) return;
   }
-  const double loss = 0.5 * sum_partials(P0, Q.nb, Q.pst, 0, s);
+  const double lsum = sum_partials(P0, Q.nb, Q.pst, 0, s);
+  const double loss = logistic ? lsum : 0.5 * lsum;
   const double R = sum_partials(P0, Q.nb, Q.pst, 1, s);
   for (int q = 0; q < nc; ++q) {
     const double gq = sum_partials(P0, Q.nb, Q.pst, 5 + q, s);
@@ -551,7 +572,13 @@ __global__ __launch_bounds__(kMbThreads) void k_commit_den(SolveSet Q, int32_t m
   a = acc_unpen(Q.U, Q.n, s.ucoef, nc, ii, a);
   const double x = combine_waves(a, s);
   if (w == 0) {
-    const double dd = wsum(ok ? x * x : 0.0);
+    // logistic: curvature weight sigma (1 - sigma) at the current beta, sigma = y - r
+    double wt = 1.0;
+    if (Q.family == IHT_LOGISTIC && ok) {
+      const double sg = V.y[ii] - V.r[ii];
+      wt = sg * (1.0 - sg);
+    }
+    const double dd = wsum(ok ? wt * (x * x) : 0.0);
     if (lane == 0) Q.pmu[(int64_t)t * Q.nb + b] = dd;
   }
   if (mode == 0 || b != 0) return;

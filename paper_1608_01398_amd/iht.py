@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libiht.so")
 OK, NOT_CONVERGED, STALLED = 0, 1, 2
 EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = -1, -2, -3, -4, -5
 FP64, FP32, MIXED_I8 = 0, 1, 2
+GAUSSIAN, LOGISTIC = 0, 1
 HOST_PTR, DEVICE_PTR = 0, 1
 MAX_K = 4096
 
@@ -36,7 +37,7 @@ class IHTError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32)]
+                ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32), ("family", ctypes.c_int32)]
 
 
 class ServerInfo(ctypes.Structure):

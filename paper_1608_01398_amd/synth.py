@@ -139,6 +139,18 @@ def make_trait(bed: np.ndarray, n: int, q: np.ndarray, k_true: int, eff, seed: i
     return y, causal, beta, gamma
 
 
+def make_binary_trait(bed: np.ndarray, n: int, q: np.ndarray, k_true: int, eff, seed: int, intercept: float = -0.5):
+    """Case/control trait: y_i ~ Bernoulli(1 / (1 + exp(-(sum_l beta_l z_l + intercept)))) with the
+    causal columns and effects drawn as in make_trait. Returns (y float64 0/1 [n], causal, beta)."""
+    p = bed.shape[0]
+    rng = np.random.Generator(np.random.PCG64([seed, 5]))
+    causal = np.sort(rng.choice(p, size=k_true, replace=False))
+    beta = rng.uniform(eff[0], eff[1], size=k_true) * rng.choice([-1.0, 1.0], size=k_true)
+    eta = _population_standardized(bed, n, q, causal) @ beta + intercept
+    y = (rng.random(n) < 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    return y, causal, beta
+
+
 def make_subset(n: int, size: int, seed: int) -> np.ndarray:
     """A random subject subset of the given size as a 0/1 uint8 mask of length n."""
     rng = np.random.Generator(np.random.PCG64([seed, 4]))
