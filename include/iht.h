@@ -6,7 +6,15 @@
  * f(beta) = 1/2 ||y - A beta||^2 (Methods, eq. leastsquaresloss) subject to at most k nonzero SNP
  * effects, with A = [X_st | Z | 1]: X_st the standardised genotype matrix (Methods, "Bandwidth
  * optimization of IHT"), Z dense non-genetic covariates and an intercept, both unpenalised
- * (Results: SexOCPG and principal components enter as covariates).
+ * (Results: SexOCPG and principal components enter as covariates). Option IHT_LOGISTIC replaces
+ * f by the logistic negative log-likelihood (the extension the Discussion names).
+ *
+ * Entry points: the resident matrix (iht_geno_*) and its per-subject-set standardisation
+ * (iht_stats_*); the gradient pass for one residual (iht_gradient) and for many on the matrix cores
+ * (iht_gradient_batch); the projection (iht_project, iht_project_hint); whole fits, one or many in
+ * lock-step (iht_fit, iht_fit_batch); model selection by cross-validation (iht_cv) and prediction
+ * (iht_predict); a continuous-batching solve server (iht_server_*); introspection
+ * (iht_batch_tuning, iht_status_str, iht_last_error).
  *
  * Conventions shared by every entry point:
  *  - Return value: IHT_OK (0) on success; > 0 means a valid result with a warning; < 0 is an error,
