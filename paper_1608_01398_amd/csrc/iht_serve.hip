@@ -126,6 +126,7 @@ int admit_queued(iht_server* S) {
     }
     HIPCHK(launch_subject_mask(L, have, B.bits, B.mask, S->st));
     HIPCHK(launch_stats(S->g->tiled.as<uint8_t>(), L, B.bits, R.nT, B.u, B.v, S->st));
+    std::vector<uint32_t>().swap(R.bits);  // copied to the pinned row: a finished request keeps no bits
     // its traits into free slots
     int32_t j = 0;
     for (int32_t t = 0; t < S->slots && j < R.T; ++t) {
@@ -180,6 +181,7 @@ int retire_finished(iht_server* S, int32_t* completed) {
     --S->busy;
     if (--R.left == 0) {
       R.done = true;
+      std::vector<int32_t>().swap(R.ks);
       S->blocks[(size_t)R.block].busy = false;
       R.block = -1;
       --S->running;
