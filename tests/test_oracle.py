@@ -395,6 +395,103 @@ def test_backtracking_budget_exhaustion_reports_stalled():
     assert found
 
 
+def _iterates(bed, n, y, k, **kw):
+    """The oracle's iterates beta^0 .. beta^m (dense over SNPs then the intercept), by replaying the fit
+    with max_iter = 0 .. m; with the full run's loss and step-size traces."""
+    full = oracle.fit(bed, n, y, k, intercept=True, **kw)
+    kw = {a: b for a, b in kw.items() if a != "max_iter"}
+    p = synth.unpack_codes(bed, n).shape[0]
+    betas, supports = [np.zeros(p + 1)], []
+    for m in range(1, full["n_iter"] + 1):
+        r = oracle.fit(bed, n, y, k, intercept=True, max_iter=m, **kw)
+        b = np.zeros(p + 1)
+        b[r["support"]] = r["beta_S"]
+        b[p] = r["beta_cov"][0]
+        betas.append(b)
+        supports.append(r["support"])
+    return full, betas, supports
+
+
+@pytest.mark.parametrize("c", [0.01, 0.3, 0.6])
+def test_backtracking_rule_of_the_step_size_section(c):
+    """Pins the omega rule of Methods, "IHT step sizes" (App. A3 of the design notes) on LD instances
+    where halvings happen, with c up to 0.6 so that a rule with a different constant or a different
+    Delta takes different decisions:
+      - every accepted support change decreases the loss by at least c ||Delta||^2 / (2 mu), with
+        Delta = beta+ - beta over S u S+ u C (the decrease the (1-c) factor guarantees);
+      - with the support unchanged the step runs along g_{S u C}, so the loss falls by
+        mu ||g_{S u C}||^2 - mu^2 ||A g_{S u C}||^2 / 2 (the line-search optimum at the normalised mu);
+      - every accepted mu is the normalised step times shrink^j, and each of the j halvings was
+        necessary: at mu / shrink the proposal changed the support and failed mu < omega;
+      - at least one halving happens over the instances."""
+    n, k, shrink = 300, 8, 0.5
+    halvings = 0
+    for seed in range(3):
+        bed, y = ld_problem(seed, n=n)
+        p = synth.unpack_codes(bed, n).shape[0]
+        A = design_matrix(bed, n)
+        full, betas, supports = _iterates(bed, n, y, k, c=c, shrink=shrink, max_iter=60)
+        tr, mus = full["loss_trace"], full["mu_trace"]
+        f = lambda b: 0.5 * np.sum((y - A @ b) ** 2)
+        S_prev = None
+        for m in range(full["n_iter"]):
+            b0, b1, mu = betas[m], betas[m + 1], mus[m]
+            g = A.T @ (y - A @ b0)
+            S0 = (np.sort(np.lexsort((np.arange(p), -np.abs(g[:p])))[:k]) if m == 0 else supports[m - 1])
+            on = np.zeros(p + 1, bool)
+            on[S0] = True
+            on[p] = True
+            d = np.where(on, g, 0.0)
+            mu_hat = d @ d / np.sum((A @ d) ** 2)
+            j = np.log(mu / mu_hat) / np.log(shrink)
+            assert abs(j - round(j)) < 1e-6 and round(j) >= 0, (m, mu, mu_hat)
+            j = int(round(j))
+            halvings += j
+            # the loss at the accepted iterate is the trace entry
+            assert abs(f(b1) - tr[m + 1]) <= 1e-10 * tr[0]
+            delta = b1 - b0
+            if set(supports[m]) != set(S0):
+                omega = (1 - c) * (delta @ delta) / np.sum((A @ delta) ** 2)
+                assert mu < omega * (1 + 1e-10), (m, mu, omega)
+                assert tr[m + 1] <= tr[m] - c * (delta @ delta) / (2 * mu) + 1e-9 * tr[0], (m, c)
+            else:
+                # the step along d = g_{S u C}: f falls by mu ||d||^2 - mu^2 ||A d||^2 / 2, which at the
+                # normalised step (j = 0) is the line-search optimum 1/2 ||d||^4 / ||A d||^2
+                drop = mu * (d @ d) - 0.5 * mu * mu * np.sum((A @ d) ** 2)
+                if j == 0:
+                    assert abs(drop - 0.5 * (d @ d) ** 2 / np.sum((A @ d) ** 2)) <= 1e-10 * drop
+                assert abs((tr[m] - tr[m + 1]) - drop) <= 1e-8 * drop + 1e-12 * tr[0], (m, drop)
+            # every halving was needed: one step longer, the proposal moved the support and failed
+            for h in range(j):
+                big = mu / shrink ** (h + 1)
+                w = b0 + big * g
+                Sb = np.sort(np.lexsort((np.arange(p), -np.abs(w[:p])))[:k])
+                bp = np.zeros(p + 1)
+                bp[Sb] = w[Sb]
+                bp[p] = w[p]
+                db = bp - b0
+                assert set(Sb) != set(S0), (m, h)
+                assert big >= (1 - c) * (db @ db) / np.sum((A @ db) ** 2) * (1 - 1e-10), (m, h)
+    assert halvings >= 1
+
+
+def test_logistic_acceptance_tolerates_only_rounding_increases():
+    """The logistic proposal is taken when f+ <= f + 1e-12 |f|. With tol = 0 the iteration keeps going
+    once f stops decreasing in floating point: the trace then shows accepted steps where f rose,
+    each by at most 1e-12 |f| (rounding of the loss sum over the subjects), which a strict test would
+    have rejected and halved until the budget ran out; no fit stalls."""
+    rises = 0
+    for seed in (50, 52, 55):
+        n, p, k = 500, 80, 4
+        bed, y, _ = _logistic_problem(n, p, k, seed)
+        res = oracle.fit(bed, n, y, k, family=1, tol=0.0, max_iter=400)
+        assert res["status"] in (oracle.OK, oracle.NOT_CONVERGED)
+        d = np.diff(res["loss_trace"])
+        assert np.all(d <= 1e-12 * np.abs(res["loss_trace"][:-1]))
+        rises += int((d > 0).sum())
+    assert rises > 0
+
+
 # ------------------------------------------------------------------ prediction X_st beta (+ covariates)
 
 def test_predict_from_first_principles():
