@@ -59,7 +59,8 @@ extern "C" {
 #define IHT_FP64 0     /* table entries and accumulation in FP64 (default)                          */
 #define IHT_FP32 1     /* table entries in FP32, per-tile FP32 sums accumulated in FP64              */
 #define IHT_MIXED_I8 2 /* fits only: one matrix-core pass per iteration for all solves (int8 genotype */
-                       /* and residual-digit operands, exact int32 sums, FP64 combination)           */
+                       /* and residual-digit operands, exact int32 sums, FP64 combination), with the */
+                       /* FP64 iteration's decisions (see iht_opts)                                  */
 
 /* model family of a fit (iht_opts.family) */
 #define IHT_GAUSSIAN 0 /* least squares, f = 1/2 ||y - A beta||^2 (Methods, eq. leastsquaresloss)    */
@@ -78,10 +79,16 @@ typedef struct iht_stats iht_stats; /* u, v [p] FP64 and the subject set T they 
 
 /*
  * Options of iht_fit and iht_fit_batch. The paper fixes none of them (Methods, "IHT step sizes"
- * only asks 0 < c << 1). With a reduced-precision gradient (IHT_FP32, IHT_MIXED_I8) the iteration
- * stops at max(tol, mixed_tol); each converged solve is then refined in FP64 on its final support
- * to the least-squares fit on S and the unpenalised columns (the fixed point of the IHT map on a
- * fixed support), with at most polish_iter conjugate-gradient steps and the stopping rule at tol.
+ * only asks 0 < c << 1). IHT_MIXED_I8 takes the decisions of the FP64 iteration (Results, "Analysis
+ * of compressed data with IHT", weighs single against double precision): the matrix-core gradient
+ * is within a bound of the exact one that the pass itself reports (the residual's quantisation
+ * error), the gradient on the support is recomputed in FP64 from the decoded support columns, and
+ * every projection is certified: the entries whose value lies within that bound of the k-th largest
+ * are recomputed in FP64 before the selection. Supports, step sizes, backtracking and the stopping
+ * rule (at tol) are then those of IHT_FP64; k <= 512 (else IHT_EUNSUPPORTED). With IHT_FP32 the
+ * iteration stops at max(tol, mixed_tol); each converged solve is then refined in FP64 on its final
+ * support to the least-squares fit on S and the unpenalised columns (the fixed point of the IHT map
+ * on a fixed support), with at most polish_iter conjugate-gradient steps and the stopping rule at tol.
  * IHT_LOGISTIC: the residual is y - sigma(eta), so the same gradient pass gives A^T r = -grad f; the
  * step is mu = ||g_{S u C}||^2 / sum_T w_i (A_{S u C} g_{S u C})_i^2 with w = sigma(eta)(1 - sigma(eta))
  * at the current beta, and a proposal is taken when f does not increase by more than 1e-12 |f| (the
@@ -96,8 +103,8 @@ typedef struct iht_opts {
     double c;              /* omega = (1-c)||d||^2/||A d||^2, 0 < c < 1; default 0.01        */
     double shrink;         /* mu <- shrink*mu on each backtrack, 0 < shrink < 1; default 0.5 */
     int32_t precision;     /* IHT_FP64, IHT_FP32 or IHT_MIXED_I8; default IHT_FP64          */
-    double mixed_tol;      /* iteration tolerance of the reduced precisions; default 1e-6   */
-    int32_t polish_iter;   /* FP64 refinement steps after a reduced-precision solve; default 200 */
+    double mixed_tol;      /* iteration tolerance of IHT_FP32; default 1e-6                 */
+    int32_t polish_iter;   /* FP64 refinement steps after an IHT_FP32 solve; default 200    */
     int32_t family;        /* IHT_GAUSSIAN (default) or IHT_LOGISTIC                        */
 } iht_opts;
 
@@ -214,8 +221,8 @@ int iht_fit(const iht_geno *g, const iht_stats *s, const double *y, const float 
  *   support    device int64 [T][kmax]: row t ascending, entries past ks[t] set to -1.
  *   beta_S     device FP64 [T][kmax]: effects on the support, entries past ks[t] set to 0.
  *   beta_cov   device FP64 [T][cz + intercept], or NULL if cz + intercept = 0.
- *   loss_trace device FP64 [T][max_iter + 1]: f at beta^0 .. beta^{n_iter[t]} of each solve (with a
- *              reduced precision the last entry is the loss after the FP64 refinement).
+ *   loss_trace device FP64 [T][max_iter + 1]: f at beta^0 .. beta^{n_iter[t]} of each solve (with
+ *              IHT_FP32 the last entry is the loss after the FP64 refinement).
  *   n_iter     host int32 [T]: iterations performed by each solve.
  *   status     host int32 [T]: IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED or IHT_ENONFINITE per solve.
  *   precision  IHT_FP64 / IHT_FP32 run one gradient pass per solve and iteration; IHT_MIXED_I8 runs

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -78,8 +79,34 @@ int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes,
     }
     e = launch_retile(src, row_bytes, G->L, G->tiled.as<uint8_t>(), st);
     if (e != hipSuccess) { rc = hip_fail(e, "retile launch"); break; }
+    // the missing-genotype lists: counts and their prefix, then the entries
+    DevBuf scan;
+    if ((e = G->miss_off.ensure((size_t)(G->L.p_pad + 1) * 8)) != hipSuccess ||
+        (e = scan.ensure(std::max<size_t>(miss_scan_work_bytes(G->L), 8))) != hipSuccess) {
+      rc = hip_fail(e, "hipMalloc(missing lists)");
+      break;
+    }
+    e = launch_miss_count(G->tiled.as<uint8_t>(), G->L, G->miss_off.as<int64_t>(), scan.as<int64_t>(), st);
+    if (e != hipSuccess) { rc = hip_fail(e, "missing-list launch"); break; }
+    int64_t total = 0;
+    if ((e = hipMemcpyAsync(&total, G->miss_off.as<int64_t>() + G->L.p_pad, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      rc = hip_fail(e, "retile / missing-list count");
+      break;
+    }
+    if (total >= (int64_t(1) << 32)) {  // list positions are 32-bit in the passes
+      rc = fail(IHT_EUNSUPPORTED, "iht_geno_create: more than 2^32 - 1 missing genotypes");
+      break;
+    }
+    G->miss_wide = n > 65536 ? 1 : 0;
+    if ((e = G->miss_idx.ensure((size_t)std::max<int64_t>(total, 1) * (G->miss_wide ? 4 : 2))) != hipSuccess) {
+      rc = hip_fail(e, "hipMalloc(missing lists)");
+      break;
+    }
+    e = launch_miss_fill(G->tiled.as<uint8_t>(), G->L, G->miss_off.as<int64_t>(), G->miss_idx.p, G->miss_wide, st);
+    if (e != hipSuccess) { rc = hip_fail(e, "missing-list launch"); break; }
     e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { rc = hip_fail(e, "retile"); break; }
+    if (e != hipSuccess) { rc = hip_fail(e, "missing lists"); break; }
   } while (0);
   if (rc != IHT_OK) {
     delete G;
@@ -188,7 +215,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
   HIPCHK(G->state.ensure(sizeof(FitState)));
   HIPCHK(G->partial.ensure(gradient_work_bytes(L)));
   FitState* fs = G->state.as<FitState>();
-  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask, s->nT, s->u, s->v, fs,
+  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), g->miss(), L, r, s->mask, s->nT, s->u, s->v, fs,
                          precision, grad, G->partial.as<double>(), nullptr, st));
   return IHT_OK;
 }

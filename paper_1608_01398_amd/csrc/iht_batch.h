@@ -4,14 +4,6 @@
 
 namespace iht {
 
-// Per-solve view of its subject set: u, v [p] and mask [n_pad] of the stats handle, and |T|.
-struct BatchSolve {
-  const double* u;
-  const double* v;
-  const double* mask;
-  int64_t nT;
-};
-
 int32_t batch_t_pad(int32_t T);
 size_t batch_r8_bytes(const Layout& L, int32_t T);
 // SNPs per block of the matrix-core pass the autotuner chose for this matrix and T (0: not tuned yet).
@@ -21,9 +13,13 @@ int32_t batch_tuned_snps(const Layout& L, int32_t T);
 // ignored). Slot s < *count computes solve t = slots[s]; with slots == NULL and count == NULL the
 // slots are the solves 0..T-1. Work areas: R8 (batch_r8_bytes), scale and rsum (T_pad doubles
 // each); sv is a device array of T BatchSolve entries. A solve's result does not depend on which
-// slot it occupies or on the other solves of the launch.
+// slot it occupies or on the other solves of the launch. With fs (device [T]), fs[t].gerr receives
+// a bound on |G_tj - (X_st^T R_t)_j| valid for every SNP j (the quantisation error of the residual,
+// summed against a standardised column: |T_t| s_t / 254^2, twice the rounding bound); with rq
+// (device, row t at rq + t * ldr, n_pad entries), the centred residual the digits were taken from.
 hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
                                  const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
-                                 double* rsum, double* G, int64_t ldg, hipStream_t st);
+                                 double* rsum, double* G, int64_t ldg, hipStream_t st, FitState* fs = nullptr,
+                                 double* rq = nullptr);
 
 }  // namespace iht

@@ -72,7 +72,8 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
                                                 int32_t T_pad, const BatchSolve* __restrict__ sv,
                                                 const int32_t* __restrict__ slots, const int32_t* __restrict__ count,
                                                 int8_t* __restrict__ R8, double* __restrict__ scale,
-                                                double* __restrict__ rsum) {
+                                                double* __restrict__ rsum, FitState* __restrict__ fs,
+                                                double* __restrict__ rq) {
   __shared__ double sh[40];
   const int slot = blockIdx.x;
   const int live = count ? *count : T;
@@ -98,7 +99,9 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
   double sq[kDigits] = {0.0, 0.0, 0.0};
   for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x) {
     int q[kDigits] = {0, 0, 0};
-    if (i < n && mask[i] != 0.0 && mx > 0.0) {
+    const bool in = i < n && mask[i] != 0.0;
+    if (rq) rq[(int64_t)t * ldr + i] = in ? r[i] - mean : 0.0;
+    if (in && mx > 0.0) {
       double x = (r[i] - mean) / s;  // |x| <= 127, exact division by a power of two
       const double q0 = rint(x);
       const double e0 = (x - q0) * kBase;  // |e0| <= 127
@@ -121,6 +124,10 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
   if (threadIdx.x == 0) {
     scale[slot] = s;
     rsum[slot] = s * ((tot[0] + tot[1] * (1.0 / kBase)) + tot[2] * (1.0 / (kBase * kBase)));
+    // |r_i - mean - R~_i| <= s / (2 254^2) (plus far smaller rounding); a standardised column has
+    // sum_T x^2 = |T|, so sum_T |x| <= |T| (Cauchy-Schwarz) and every G_j is within |T| s / (2 254^2)
+    // of the exact X_st^T r, before the FP64 combination's own rounding: twice that bounds both.
+    if (fs) fs[t].gerr = (double)sv[t].nT * s * (1.0 / (kBase * kBase));
   }
 }
 
@@ -333,10 +340,10 @@ int32_t batch_tuned_snps(const Layout& L, int32_t T) {
 
 hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
                                  const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
-                                 double* rsum, double* G, int64_t ldg, hipStream_t st) {
+                                 double* rsum, double* G, int64_t ldg, hipStream_t st, FitState* fs, double* rq) {
   const int32_t T_pad = batch_t_pad(T);
   hipLaunchKernelGGL(k_quant, dim3((unsigned)T_pad), dim3(1024), 0, st, R, ldr, L.n, L.n_pad, T, T_pad, sv, slots, count, R8,
-                     scale, rsum);
+                     scale, rsum, fs, rq);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int si = tuned_shape(tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st);

@@ -129,6 +129,111 @@ __global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, 
 }
 
 // ------------------------------------------------------------------------------------------------
+// Missing-genotype lists (code 01 in the PLINK encoding), built once per matrix.
+
+// Missing entries of SNP j (one thread per SNP, pad SNPs count 0).
+__global__ __launch_bounds__(256) void k_miss_count(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
+                                                    int64_t* __restrict__ off) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p_pad) return;
+  int64_t c = 0;
+  if (j < p)
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const uint2 d = tiled[t * p_pad + j];
+      c += __popc(d.x & ~(d.x >> 1) & 0x55555555u) + __popc(d.y & ~(d.y >> 1) & 0x55555555u);
+    }
+  off[j] = c;
+}
+
+constexpr int kScanItems = 8;                     // per thread
+constexpr int64_t kScanBlock = 1024 * kScanItems;  // entries per block (p_pad is a multiple)
+
+// Exclusive prefix of 1024 per-thread totals held by the block (sh: 1024 words).
+__device__ int64_t block_exclusive(int64_t v, int64_t* sh) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t x = tid >= d ? sh[tid - d] : 0;
+    __syncthreads();
+    sh[tid] += x;
+    __syncthreads();
+  }
+  const int64_t incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+// In-place exclusive prefix of each 8192-entry block; the block totals go to sums[b].
+__global__ __launch_bounds__(1024) void k_scan_local(int64_t* __restrict__ x, int64_t* __restrict__ sums) {
+  __shared__ int64_t sh[1024];
+  int64_t* b = x + (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+  int64_t v[kScanItems], t = 0;
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    v[e] = b[e];
+    t += v[e];
+  }
+  int64_t run = block_exclusive(t, sh);
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    b[e] = run;
+    run += v[e];
+  }
+  if (threadIdx.x == 1023) sums[blockIdx.x] = run;
+}
+
+// Exclusive prefix of the nb block totals (one block, chunks of 1024 with a carry); the grand total
+// goes to x[p_pad].
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ sums, int64_t nb, int64_t* __restrict__ x,
+                                                   int64_t p_pad) {
+  __shared__ int64_t sh[1024];
+  __shared__ int64_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < nb ? sums[i] : 0;
+    const int64_t ex = block_exclusive(v, sh);
+    const int64_t base = carry;
+    if (i < nb) sums[i] = base + ex;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = base + ex + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) x[p_pad] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ x, const int64_t* __restrict__ sums, int64_t p_pad) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < p_pad) x[j] += sums[j / kScanBlock];
+}
+
+// Subject indices of SNP j's missing entries, ascending, at idx[off[j] ..). Byte b of a segment holds
+// 4-subject group (b + j) mod 8, so the groups are visited in subject order through that rotation.
+template <class IdxT>
+__global__ __launch_bounds__(256) void k_miss_fill(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
+                                                   const int64_t* __restrict__ off, IdxT* __restrict__ idx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  int64_t pos = off[j];
+  const int rot = (int)(j & (kSegBytes - 1));
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const uint2 d = tiled[t * p_pad + j];
+    const uint64_t seg = (uint64_t)d.x | ((uint64_t)d.y << 32);
+    const uint64_t mm = seg & ~(seg >> 1) & 0x5555555555555555ull;
+    if (!mm) continue;
+    for (int gq = 0; gq < 8; ++gq) {
+      const int b = (gq - rot) & (kSegBytes - 1);
+      const uint32_t byte = (uint32_t)(mm >> (8 * b)) & 0xFFu;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((byte >> (2 * q)) & 1u) idx[pos++] = (IdxT)(t * kTileSubjects + 4 * gq + q);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
 // Top-k of |w| with ties to the lower index (the projection of eq. ihta).
 // Level 0: 8192-bin histogram of key bits 62..50 (key = IEEE bits of |w|) -> threshold bucket.
 // Collect: keys above the bucket are selected; keys in it are candidates. The last block finds the
@@ -167,6 +272,14 @@ __device__ __forceinline__ bool topk_row(const TopkJob& J, int t, TopkRow& R) {
 }
 
 __device__ __forceinline__ uint64_t abs_key(double w) { return (uint64_t)__double_as_longlong(fabs(w)); }
+__device__ __forceinline__ double key_value(uint64_t key) { return __longlong_as_double((long long)key); }
+
+// Bound on |w~_j - w_j| for the entries of a certified row off its exact support: the gradient's
+// bound, times the step size when w = beta + mu g.
+__device__ __forceinline__ double row_err(const TopkJob& J, int t, const TopkRow& R) {
+  const double e = J.fs[t].gerr;
+  return R.beta ? R.mu * e : e;
+}
 
 // (bucket, count above, count in bucket) of the need-th largest over nb bins held in LDS h,
 // found by the first wave (per-lane bin sums, then a shuffle suffix scan); out[] is visible to the
@@ -694,6 +807,10 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
 #pragma unroll
     for (int i = 1; i < 4; ++i) tk = shk[i] < tk ? shk[i] : tk;
   }
+  if (J.certify) {  // values off the exact support may be off by err: keep 2 err below the bound
+    const double lo = __longlong_as_double((long long)tk) - 2.0 * row_err(J, blockIdx.y, src);
+    tk = lo > 0.0 ? abs_key(lo) : 0ull;
+  }
   // Appends this wave's `in` lanes to the row's candidate list: one atomic add per wave.
   auto append = [&](bool in, uint64_t key, int64_t j) {
     const uint64_t m = __ballot(in);
@@ -797,14 +914,17 @@ __device__ void select_global(const uint64_t* __restrict__ keys, const int32_t* 
 }
 
 // Pass 2, one block per row: the k first of the row's candidates (nb blocks x kmax slots, or the
-// filtered list), sorted by index.
-__global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32_t nb) {
+// filtered list), sorted by index. With save (a certified row's first selection), the list length
+// and the k-th largest key of the selection are left in counters[5], counters[6..7] for
+// k_topk_exact, and the list is kept.
+__global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32_t nb, int32_t save) {
   TopkRow src;
   if (!topk_row(J, blockIdx.x, src)) return;
   __shared__ uint32_t hist[kSelBins];
   __shared__ uint32_t sh[32];
   __shared__ int32_t sel[kLocalMaxK];
   __shared__ uint32_t nsel;
+  __shared__ unsigned long long kth;
   const int tid = threadIdx.x;
   const int k = src.k;
   int64_t total = (int64_t)nb * J.kmax;  // <= 1024 * kFinalEPT (checked at launch)
@@ -821,7 +941,10 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
     total = min((int64_t)nsel, J.cap);
     __syncthreads();  // every thread has read it before nsel is reused
   }
-  if (tid == 0) nsel = 0u;
+  if (tid == 0) {
+    nsel = 0u;
+    kth = ~0ull;
+  }
   for (int q = tid; q < kLocalMaxK; q += 1024) sel[q] = 0;
   __syncthreads();
   if (total <= 1024) {
@@ -895,10 +1018,87 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
     const bool ok = x >= 0 && x < p && rank < k;  // always true when the counts agree
     if (!ok) atomicOr(&src.tw.state[3], 2u);
     if (rank < k) {
+      const double w = ok ? src.at(x) : 0.0;
       src.out[rank] = ok ? x : 0;
-      if (src.vals) src.vals[rank] = ok ? src.at(x) : 0.0;
+      if (src.vals) src.vals[rank] = w;
+      if (save) atomicMin(&kth, (unsigned long long)abs_key(w));
     }
   }
+  if (save) {
+    __syncthreads();
+    if (tid == 0) {
+      (void)atomicExch(&src.tw.counters[5], (uint32_t)total);
+      (void)atomicExch(&src.tw.counters[6], (uint32_t)kth);
+      (void)atomicExch(&src.tw.counters[7], (uint32_t)(kth >> 32));
+    }
+  }
+}
+
+// Certified selection, between the two final selections of a certified row: every entry of the
+// row's filtered list whose value lies within 2 err below the approximate k-th largest (and, when the
+// values at prev are exact, is off prev) gets its exact gradient in FP64, g_j = sum_i x_st(i, j)
+// rc_i over the decoded standardised column (missing and outside the subject set: 0), written to g
+// and to the list's key. Every entry left approximate is then below the exact k-th largest, so the
+// second selection returns the projection of the exact w. One wave per entry to evaluate; the list
+// length is restored for the second selection.
+__global__ __launch_bounds__(256) void k_topk_exact(TopkJob J, int64_t p) {
+  TopkRow src;
+  const int t = blockIdx.y;
+  if (!topk_row(J, t, src)) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t cnt = atomic_load_u32(&src.tw.counters[5]);
+  const uint64_t kkey = (uint64_t)atomic_load_u32(&src.tw.counters[6]) | ((uint64_t)atomic_load_u32(&src.tw.counters[7]) << 32);
+  const double lo = key_value(kkey) - 2.0 * row_err(J, t, src);
+  const int64_t* prev = J.prev + (int64_t)t * J.ldprev;
+  const BatchSolve sv = J.sv[t];
+  const double* rc = J.rc + (int64_t)t * J.ldr;
+  double* g = const_cast<double*>(src.g);
+  const int64_t len = min((int64_t)cnt, J.cap);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64; c0 < len; c0 += waves * 64) {
+    const int64_t pos = c0 + lane;
+    int32_t j = -1;
+    bool need = false;
+    if (pos < len) {
+      j = src.tw.cand_idx[pos];
+      need = j >= 0 && j < p && key_value(src.tw.cand_key[pos]) >= lo;
+      if (need && J.prev_exact) {  // warm row: values on the support are exact already
+        int a = 0, b = src.k;
+        while (a < b) {
+          const int mid = (a + b) >> 1;
+          if (prev[mid] < j)
+            a = mid + 1;
+          else
+            b = mid;
+        }
+        need = !(a < src.k && prev[a] == j);
+      }
+    }
+    uint64_t m = __ballot(need);
+    while (m) {
+      const int bl = __ffsll((long long)m) - 1;
+      m &= m - 1;
+      const int32_t jj = __shfl(j, bl, 64);
+      const double uj = sv.u[jj], vj = sv.v[jj];
+      const int rot = jj & (kSegBytes - 1);
+      double a = 0.0;
+      for (int64_t i = lane; i < J.n; i += 64) {
+        const int64_t tile = i / kTileSubjects;
+        const int grp = (int)((i % kTileSubjects) >> 2);
+        const uint8_t byte = J.tiled[(tile * J.p_pad + jj) * kSegBytes + ((grp - rot) & (kSegBytes - 1))];
+        const int code = (byte >> (2 * (i & 3))) & 3;
+        const double x = code == 1 ? 0.0 : vj * ((code == 0 ? 0.0 : (double)(code - 1)) - uj);
+        a += x * rc[i];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+      if (lane == 0) {
+        g[jj] = a;
+        src.tw.cand_key[c0 + bl] = abs_key(src.at(jj));
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) (void)atomicExch(&src.tw.counters[4], cnt);
 }
 
 // Subject mask of a stats handle: mask[i] = bit i of the tile bits (given), or every subject i < n
@@ -969,40 +1169,90 @@ hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* m
   return hipGetLastError();
 }
 
+size_t miss_scan_work_bytes(const Layout& L) { return (size_t)(L.p_pad / kScanBlock) * sizeof(int64_t); }
+
+hipError_t launch_miss_count(const uint8_t* tiled, const Layout& L, int64_t* off, int64_t* work, hipStream_t st) {
+  const uint2* t2 = reinterpret_cast<const uint2*>(tiled);
+  hipLaunchKernelGGL(k_miss_count, dim3((unsigned)((L.p_pad + 255) / 256)), dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nb = L.p_pad / kScanBlock;
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(1024), 0, st, off, work);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, work, nb, off, L.p_pad);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((L.p_pad + 255) / 256)), dim3(256), 0, st, off, work, L.p_pad);
+  return hipGetLastError();
+}
+
+hipError_t launch_miss_fill(const uint8_t* tiled, const Layout& L, const int64_t* off, void* idx, int32_t wide,
+                            hipStream_t st) {
+  const uint2* t2 = reinterpret_cast<const uint2*>(tiled);
+  const dim3 grid((unsigned)((L.p + 255) / 256));
+  if (wide)
+    hipLaunchKernelGGL(k_miss_fill<uint32_t>, grid, dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off,
+                       static_cast<uint32_t*>(idx));
+  else
+    hipLaunchKernelGGL(k_miss_fill<uint16_t>, grid, dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off,
+                       static_cast<uint16_t*>(idx));
+  return hipGetLastError();
+}
+
 hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st) {
   // two-pass selection when every row's candidates fit pass 2: chunks of 2048 (256-thread blocks,
   // enough of them to fill the chip) when they do, else of 8192
   const int64_t cap2 = 1024 * (int64_t)kFinalEPT;
   const int64_t nb_s = (p + kSmallChunk - 1) / kSmallChunk;
   const int64_t nb_l = (p + kLargeChunk - 1) / kLargeChunk;
+  // A certified row's filtered list is selected from twice: first by the approximate values, then,
+  // after k_topk_exact has made the entries near the k-th largest exact, by those.
+  auto filter_final = [&](const TopkJob& Jf) -> hipError_t {
+    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, Jf, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p, 0, Jf.certify);
+    e = hipGetLastError();
+    if (e != hipSuccess || !Jf.certify) return e;
+    hipLaunchKernelGGL(k_topk_exact, dim3(8u, (unsigned)rows), dim3(256), 0, st, Jf, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p, 0, 0);
+    return hipGetLastError();
+  };
+  if (J.certify && !(J.fs && J.kmax <= kLocalMaxK && J.cap >= p)) return hipErrorInvalidValue;
   if (J.prev && J.kmax <= kLocalMaxK && J.cap >= p) {
     TopkJob Jf = J;
     Jf.use_bound = J.beta != nullptr ? 1 : 0;  // solver rows: prev is beta's ascending support
+    Jf.prev_exact = Jf.use_bound;               // whose gradient entries a certified row keeps exact
     if (Jf.use_bound) {
       hipLaunchKernelGGL(k_topk_bound, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, Jf, p);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p, 0);
-    return hipGetLastError();
+    return filter_final(Jf);
   }
+  // a certified cold row: the approximate top-k below, then a filter with it as the hint
+  TopkJob Jc = J;
+  Jc.prev = J.out;
+  Jc.ldprev = J.ldo;
+  Jc.prev_exact = 0;  // approximate values (with beta, every beta entry is 0 on a cold row)
   if (J.kmax <= kLocalMaxK && nb_s * J.kmax <= cap2 && nb_s * J.kmax <= J.cap) {
     hipLaunchKernelGGL((k_topk_local<256, kLocalEPT>), dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, J, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_s);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_s, 0);
+    e = hipGetLastError();
+    return (e != hipSuccess || !J.certify) ? e : filter_final(Jc);
   }
   if (J.kmax <= kLocalMaxK && nb_l * J.kmax <= cap2 && nb_l * J.kmax <= J.cap) {
     hipLaunchKernelGGL((k_topk_local<1024, kLocalEPT>), dim3((unsigned)nb_l, (unsigned)rows), dim3(1024), 0, st, J, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_l);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, J, p, (int32_t)nb_l, 0);
+    e = hipGetLastError();
+    return (e != hipSuccess || !J.certify) ? e : filter_final(Jc);
   }
+  if (J.certify) return hipErrorInvalidValue;
   // histogram path (large k or very long rows): about 2048 blocks over all rows, 4096 to 65536
   // entries per block
   int64_t chunk = 4096;

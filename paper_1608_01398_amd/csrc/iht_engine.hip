@@ -25,6 +25,12 @@ int check_opts(const iht_opts& o, const char* who) {
   return IHT_OK;
 }
 
+int check_kmax(const iht_opts& o, int32_t kmax, const char* who) {
+  if (o.precision == IHT_MIXED_I8 && kmax > kCertifyMaxK)
+    return fail(IHT_EUNSUPPORTED, std::string(who) + ": IHT_MIXED_I8 takes k <= " + std::to_string(kCertifyMaxK));
+  return IHT_OK;
+}
+
 Engine::~Engine() {
   if (exec_) (void)hipGraphExecDestroy(exec_);
   if (cap_st_) (void)hipStreamDestroy(cap_st_);
@@ -43,9 +49,12 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
   kmax_ = kmax;
   nc_ = U.cz + U.icpt;
   mixed_ = o.precision == IHT_MIXED_I8;
+  if (int rc = check_kmax(o, kmax, "engine")) return rc;
   if (exec_) (void)hipGraphExecDestroy(exec_);
   exec_ = nullptr;
-  tol_main_ = o.precision == IHT_FP64 ? o.tol : std::max(o.tol, o.mixed_tol);
+  // the matrix-core path follows the FP64 iteration exactly (certified projection, FP64 gradient on
+  // the support), so it stops by the same rule; the FP32 pass stops at mixed_tol and is refined
+  tol_main_ = o.precision == IHT_FP32 ? std::max(o.tol, o.mixed_tol) : o.tol;
   const size_t Tz = (size_t)T, kz = (size_t)kmax;
 
   HIPCHK(W.beta.ensure(Tz * L.p * 8));
@@ -77,6 +86,7 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
     HIPCHK(W.rsum.ensure((size_t)batch_t_pad(T) * 8));
     HIPCHK(W.slots.ensure(Tz * 4));
     HIPCHK(W.count.ensure(4));
+    HIPCHK(W.rg.ensure(Tz * L.n_pad * 8));
   }
   // pinned areas: FitStates; ks, subject sets, flags, output rows, top-k error words
   HIPCHK(W.host.ensure(Tz * sizeof(FitState)));
@@ -140,6 +150,15 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
   J.cand_key = W.topk.cand_key();
   J.cand_idx = W.topk.cand_idx();
   J.cap = W.topk.cap;
+  if (mixed_) {  // the projection of the exact w from the matrix-core gradient
+    J.certify = 1;
+    J.tiled = g->tiled.as<uint8_t>();
+    J.sv = Q.sv;
+    J.rc = W.rg.as<double>();
+    J.ldr = L.n_pad;
+    J.n = L.n;
+    J.p_pad = L.p_pad;
+  }
   // every slot starts idle (not fresh, not active, not retiring)
   HIPCHK(launch_zero_u32(reinterpret_cast<uint32_t*>(Q.fs), (int64_t)(Tz * sizeof(FitState) / 4), st));
   return IHT_OK;
@@ -178,13 +197,16 @@ int Engine::gradient(int32_t phase) {
   if (mixed_) {
     HIPCHK(solve_slots(Q_.fs, T_, phase, W.slots.as<int32_t>(), W.count.as<int32_t>(), st_));
     HIPCHK(launch_gradient_batch(tiled, L_, Q_.r, L_.n_pad, T_, Q_.sv, W.slots.as<int32_t>(), W.count.as<int32_t>(),
-                                 W.r8.as<int8_t>(), W.scale.as<double>(), W.rsum.as<double>(), Q_.g, L_.p, st_));
+                                 W.r8.as<int8_t>(), W.scale.as<double>(), W.rsum.as<double>(), Q_.g, L_.p, st_, Q_.fs,
+                                 W.rg.as<double>()));
+    // the accepted proposals' own entries exactly (the initial support is certified by its projection)
+    if (phase == kPhaseGo) HIPCHK(solve_exact_support(Q_, W.rg.as<double>(), st_));
     return IHT_OK;
   }
   for (int32_t t = 0; t < T_; ++t) {
     if (!launch_[t]) continue;
     const BatchSolve& b = sv_h_[t];
-    HIPCHK(launch_gradient(tiled, L_, Q_.r + (size_t)t * L_.n_pad, b.mask, b.nT, b.u, b.v, Q_.fs + t, o_.precision,
+    HIPCHK(launch_gradient(tiled, g_->miss(), L_, Q_.r + (size_t)t * L_.n_pad, b.mask, b.nT, b.u, b.v, Q_.fs + t, o_.precision,
                            Q_.g + (size_t)t * L_.p, W.partial.as<double>(),
                            phase == kPhaseInit ? &Q_.fs[t].fresh : &Q_.fs[t].go, st_, Q_.rc + (size_t)t * L_.n_pad));
   }
@@ -302,7 +324,7 @@ int Engine::retire(const uint8_t* flags, const OutRow* rows) {
   std::memcpy(rows_h_, rows, Tz * sizeof(OutRow));
   HIPCHK(hipMemcpyAsync(W_->rows.p, rows_h_, Tz * sizeof(OutRow), hipMemcpyHostToDevice, st_));
   HIPCHK(solve_mark(Q_, fl, 1, 1, st_));
-  if (o_.precision != IHT_FP64 && o_.polish_iter > 0) HIPCHK(solve_polish(Q_, o_.tol, o_.polish_iter, st_));
+  if (o_.precision == IHT_FP32 && o_.polish_iter > 0) HIPCHK(solve_polish(Q_, o_.tol, o_.polish_iter, st_));
   HIPCHK(solve_output(Q_, W_->rows.as<OutRow>(), st_));
   HIPCHK(solve_mark(Q_, fl, 1, 0, st_));
   HIPCHK(hipMemcpy2DAsync(terr_, 4, J_.small + kTopkErrorWord, (size_t)kTopkRowWords * 4, 4, Tz, hipMemcpyDeviceToHost,

@@ -130,13 +130,15 @@ struct TopkArea {
 // through which the engine exchanges the slots' small inputs and flags.
 struct SolveWork {
   DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv, flags, rows;
-  DevBuf r8, scale, rsum, slots, count;
+  DevBuf r8, scale, rsum, slots, count, rg;  // matrix-core pass work; rg: centred residual of each slot's gradient
   TopkArea topk;
   PinnedBuf host;   // the slots' FitStates as last read
   PinnedBuf stage;  // ks, subject sets, flags, output rows and top-k error words
 };
 
 int check_opts(const iht_opts& o, const char* who);
+// IHT_EUNSUPPORTED (with the message) when the precision cannot take model sizes up to kmax.
+int check_kmax(const iht_opts& o, int32_t kmax, const char* who);
 
 // The solve loop of Methods, eq. (ihta) with the normalised step and the omega rule of "IHT step
 // sizes", over T slots sharing one genotype matrix. Every per-slot kernel is gated on the slot's
@@ -175,9 +177,9 @@ class Engine {
   int admit(const int32_t* ks, const BatchSolve* sv, const uint8_t* admit);
   // One turn of every slot still iterating; ends with the states read.
   int turn();
-  // Writes out the slots with flags[t] != 0 (every slot if NULL): the FP64 refinement after a
-  // reduced-precision solve, then the outputs into rows[t] (host [T]). Ends with the states and
-  // the top-k error words read.
+  // Writes out the slots with flags[t] != 0 (every slot if NULL): the FP64 refinement after an
+  // FP32 solve, then the outputs into rows[t] (host [T]). Ends with the states and the top-k error
+  // words read.
   int retire(const uint8_t* flags, const OutRow* rows);
 
   const FitState& state(int32_t t) const { return h_[t]; }
@@ -223,6 +225,10 @@ struct iht_geno {
   int device = 0;
   iht::Layout L{};
   iht::DevBuf tiled;
+  // missing-genotype lists (built with the layout): offsets [p_pad + 1], subject indices
+  iht::DevBuf miss_off, miss_idx;
+  int32_t miss_wide = 0;
+  iht::MissList miss() const { return iht::MissList{miss_off.as<int64_t>(), miss_idx.p, miss_wide}; }
   // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
   iht::DevBuf partial, state;
   iht::SolveWork fit;

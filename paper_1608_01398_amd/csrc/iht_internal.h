@@ -21,7 +21,7 @@ constexpr int64_t kSnpAlign = 8192;  // p is padded to this (covers 1024 lanes x
 #define IHT_PASS_SNP_BARRIER 0
 #endif
 #ifndef IHT_PASS_MAX_NS
-#define IHT_PASS_MAX_NS 4
+#define IHT_PASS_MAX_NS 2
 #endif
 constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (128 KB of table in LDS)
 constexpr int kPassMaxNS = IHT_PASS_MAX_NS;     // SNPs per lane, at most
@@ -36,6 +36,7 @@ constexpr int kSmallThreads = 1024;
 constexpr int kMaxUnpenalized = 64;  // dense covariates + intercept
 constexpr int kTopkBins0 = 8192;     // first-level histogram: key bits 62..50
 constexpr int kTopkMaxK = 4096;
+constexpr int kCertifyMaxK = 512;    // largest k of a certified (matrix-core) projection
 
 struct Layout {
   int64_t n, p;
@@ -50,6 +51,7 @@ struct FitState {
   double mu, omega, num, den;
   double loss, mean, Rsum;
   double dmax, bmax;
+  double gerr;  // bound on |g~_j - g_j| of the last matrix-core gradient (0: exact gradient)
   int32_t same, accept, den_zero, conv;
   int32_t nonfinite, topk_error;
   int32_t go;       // proposal accepted (or support unchanged): residual, gradient and commit run
@@ -88,11 +90,20 @@ __device__ __forceinline__ bool fs_selected(const FitState* fs, int32_t phase) {
   return fs->active != 0 && fs->go != 0;
 }
 
+// Per-solve view of its subject set: u, v [p] and mask [n_pad] of the stats handle, and |T|.
+struct BatchSolve {
+  const double* u;
+  const double* v;
+  const double* mask;
+  int64_t nT;
+};
+
 // Top-k work area of one row (counters are self-resetting: the last block of each kernel clears
 // them). Rows are laid out kTopkRowWords apart in one small buffer; candidates `cap` apart.
 struct TopkWork {
   uint32_t* hist;      // [kTopkBins0]
-  uint32_t* counters;  // [8]: 0 hist ticket, 1 collect ticket, 2 n_sel, 3 n_cand, 4 filtered candidates
+  uint32_t* counters;  // [8]: 0 hist ticket, 1 collect ticket, 2 n_sel, 3 n_cand, 4 filtered candidates,
+                       // 5 saved list length, 6-7 approximate k-th key (certified selection)
   uint32_t* state;     // [8]: bucket, n_above, n_eq, error (bit 0 non-finite, bit 1 count mismatch)
   int32_t* sel;        // [kTopkMaxK]
   uint64_t* cand_key;  // [cap]
@@ -128,6 +139,19 @@ struct TopkJob {
   const int64_t* prev;  // may be NULL
   int64_t ldprev;
   int32_t use_bound;  // set by launch_topk: the filter reads the bound k_topk_bound left in the row
+  // Certified rows (certify != 0; needs fs, prev or a cold row, kmax <= 512): every g_j off the
+  // exact support may be off by up to err = fs[t].gerr (times mu_t with beta), as after the
+  // matrix-core pass. The filter keeps a margin of 2 err below its bound, and the entries of its list
+  // within 2 err of the approximate k-th largest value get their exact FP64 gradient (the decoded
+  // standardised column against rc) before the final selection, which is then the projection of
+  // the exact w. Entries of g replaced that way hold the exact value afterwards.
+  int32_t certify;
+  int32_t prev_exact;    // set by launch_topk: the values at prev are exact (a warm row's support)
+  const uint8_t* tiled;  // genotype layout [tile][p_pad][8 B]
+  const BatchSolve* sv;  // [rows] subject set and standardisation of each row
+  const double* rc;      // row t at rc + t * ldr: the centred residual the gradient was taken at
+  int64_t ldr;
+  int64_t n, p_pad;
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
@@ -136,6 +160,23 @@ hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L,
 
 hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
                         hipStream_t st);
+
+// Missing genotypes of each SNP as a sorted list of subject indices, built once per matrix from the
+// re-tiled codes: SNP j's entries are idx[off[j] .. off[j+1]) (off: int64 [p_pad + 1]; idx: uint16 when
+// n <= 65536, else uint32). The gradient passes sum the residual over these lists for the missing
+// term instead of carrying it through the tables.
+struct MissList {
+  const int64_t* off;
+  const void* idx;
+  int32_t wide;  // 1: uint32 entries
+};
+// Pass 1: off[j] = number of missing entries of SNP j (j < p_pad), then the exclusive prefix over
+// p_pad + 1 entries (off[p_pad] = total); `work` holds miss_scan_work_bytes(L). Pass 2 (after the
+// caller has sized idx from off[p_pad]): the entries.
+size_t miss_scan_work_bytes(const Layout& L);
+hipError_t launch_miss_count(const uint8_t* tiled, const Layout& L, int64_t* off, int64_t* work, hipStream_t st);
+hipError_t launch_miss_fill(const uint8_t* tiled, const Layout& L, const int64_t* off, void* idx, int32_t wide,
+                            hipStream_t st);
 // The subject set's FP64 mask [n_pad] from its bits [ntiles] (have_bits), or both for every subject.
 hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, double* mask, hipStream_t st);
 
@@ -143,9 +184,9 @@ hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, 
 // residual into fs, centred residual into `work`), the pass kernel, and a finalize kernel when the
 // subjects are split over workgroups. `work` holds gradient_work_bytes(L). With rc_ready the
 // centred residual (and fs->Rsum) come from the caller and the centring kernel is skipped.
-hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask, int64_t nT,
-                           const double* u, const double* v, FitState* fs, int precision, double* g, double* work,
-                           const int32_t* gate, hipStream_t st, const double* rc_ready = nullptr);
+hipError_t launch_gradient(const uint8_t* tiled, const MissList& ML, const Layout& L, const double* r, const double* mask,
+                           int64_t nT, const double* u, const double* v, FitState* fs, int precision, double* g,
+                           double* work, const int32_t* gate, hipStream_t st, const double* rc_ready = nullptr);
 size_t gradient_work_bytes(const Layout& L);
 
 // Top-k of |w| (rows of TopkJob) over p entries for `rows` problems.

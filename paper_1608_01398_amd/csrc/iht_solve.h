@@ -70,6 +70,9 @@ hipError_t solve_check_residual(const SolveSet& Q, int32_t phase, double c, int3
 // mode 0: first step size of the newly admitted solves
 hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t max_iter, hipStream_t st);
 hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st);
+// g on the accepted proposals' supports (phase go), exactly: each column of S+ (the proposal's cache)
+// against the centred residual rq [T][n_pad] the gradient was taken at.
+hipError_t solve_exact_support(const SolveSet& Q, const double* rq, hipStream_t st);
 // FP64 refinement of the solves marked retire that converged
 hipError_t solve_polish(const SolveSet& Q, double tol, int32_t max_steps, hipStream_t st);
 // outputs of the solves marked retire into rows[t] (device [T])

@@ -669,6 +669,30 @@ __global__ __launch_bounds__(kMbThreads) void k_mu(SolveSet Q, int32_t mode, int
   }
 }
 
+// Exact gradient on the support of an accepted proposal (matrix-core fits): g_j = sum_i x_st(i, j) rq_i
+// for the columns of S+, held decoded in the proposal's cache, one wave per column in a fixed order.
+// The matrix-core pass leaves every g_j within fs.gerr of this; the step size, the support's values
+// in the next proposal and the convergence test then see the FP64 values, as after a FP64 pass.
+__global__ __launch_bounds__(256) void k_exact_support(SolveSet Q, const double* __restrict__ rq) {
+  const int t = blockIdx.y;
+  if (!fs_selected(Q.fs + t, kPhaseGo)) return;
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= Q.ks[t]) return;
+  const int cp = 1 - Q.fs[t].xcur;
+  const double* col = Q.X + (((int64_t)t * 2 + cp) * Q.kmax + q) * Q.n_pad;
+  const double* r = rq + (int64_t)t * Q.n_pad;
+  double a0 = 0.0, a1 = 0.0;
+  int64_t i = lane;
+  for (; i + 64 < Q.n; i += 128) {
+    a0 += col[i] * r[i];
+    a1 += col[i + 64] * r[i + 64];
+  }
+  if (i < Q.n) a0 += col[i] * r[i];
+  const double a = wsum(a0 + a1);
+  if (lane == 0) Q.g[(int64_t)t * Q.p + Q.Sp[(int64_t)t * Q.kmax + q]] = a;
+}
+
 __global__ void k_shrink(SolveSet Q, double shrink) {
   FitState* fs = Q.fs + blockIdx.x;
   if (threadIdx.x == 0 && fs_selected(fs, kPhaseBacktrack)) {
@@ -883,6 +907,11 @@ hipError_t solve_commit_mu(const SolveSet& Q, int32_t mode, double tol, int32_t 
 
 hipError_t solve_shrink(const SolveSet& Q, double shrink, hipStream_t st) {
   hipLaunchKernelGGL(k_shrink, dim3((unsigned)Q.T), dim3(64), 0, st, Q, shrink);
+  return hipGetLastError();
+}
+
+hipError_t solve_exact_support(const SolveSet& Q, const double* rq, hipStream_t st) {
+  hipLaunchKernelGGL(k_exact_support, dim3((unsigned)((Q.kmax + 3) / 4), (unsigned)Q.T), dim3(256), 0, st, Q, rq);
   return hipGetLastError();
 }
 

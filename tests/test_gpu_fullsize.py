@@ -3,10 +3,11 @@
 The oracle checks outputs it can compute one by one: gradient entries of sampled SNPs (every SNP's
 statistics and gradient entry depend on its own row only, so the oracle runs on the sampled rows),
 and whole fits where an oracle fit finishes in seconds (n = 5000, p = 500,000). At n = 20,000,
-p = 2,000,000 (10 GB packed) an oracle fit would take many minutes, so the fits are checked by
-properties that hold at any size: a converged fit is the least-squares fit of y on its support and
-the unpenalised columns (the fixed point of the IHT map on a fixed support), and the int8
-matrix-core solves select the same supports as the FP64 solves up to the number of effects.
+p = 2,000,000 (10 GB packed) an oracle fit takes many minutes, so two oracle solves are stored as
+goldens (tests/golden/make_c5_goldens.py) and the other fits are checked by properties that hold
+at any size: a converged fit is the least-squares fit of y on its support and the unpenalised
+columns (the fixed point of the IHT map on a fixed support), and the int8 matrix-core solves take
+the FP64 solves' decisions (same statuses, supports and iteration counts).
 """
 import numpy as np
 import pytest
@@ -103,19 +104,31 @@ def test_c3_batched_pass_sampled(c2):
 
 
 def test_c3_batched_fit_sample_matches_oracle(c2):
+    """The 108-solve layout in one int8 matrix-core batch (5 training folds x k = 1..20 on the trait,
+    plus 8 further traits at k = 20 on all subjects); 5 sampled solves against the oracle, including
+    k = 1 and two of the further traits, at the FP64 bars (same status, support and iteration count,
+    beta within 1e-6, loss trace within 1e-9)."""
     n = c2["n"]
     fold = synth.make_folds(n, 5, 1)
     masks = [(fold != f).astype(np.uint8) for f in range(5)]
-    stats = [iht.Stats(c2["geno"], m) for m in masks]
-    ks = [k for _ in range(5) for k in range(1, 21)]
-    Y = np.stack([c2["y"]] * 100)
-    res = iht.fit_batch(c2["geno"], [stats[t // 20] for t in range(100)], dev(Y), ks, precision=iht.MIXED_I8)
+    stats = [iht.Stats(c2["geno"], m) for m in masks] + [iht.Stats(c2["geno"])]
+    ks = [k for _ in range(5) for k in range(1, 21)] + [20] * 8
+    traits = [synth.make_trait(c2["bed"], n, c2["q"], 20, (0.1, 0.4), seed=100 + e)[0] for e in range(8)]
+    Y = np.stack([c2["y"]] * 100 + traits)
+    which = [t // 20 for t in range(100)] + [5] * 8
+    res = iht.fit_batch(c2["geno"], [stats[w] for w in which], dev(Y), ks, precision=iht.MIXED_I8)
     say("c3 batched fit: statuses", np.bincount(np.asarray(res["statuses"]) + 4, minlength=7)[4:].tolist())
-    t = 19  # fold 0, k = 20
-    ref = oracle.fit(c2["bed"], n, c2["y"], 20, intercept=True, subset=masks[0])
-    assert int(res["statuses"][t]) == ref["status"]
-    assert np.array_equal(res["support"][t, :20].cpu().numpy(), ref["support"])
-    assert np.abs(res["beta_S"][t, :20].cpu().numpy() - ref["beta_S"]).max() <= 1e-6 * np.abs(ref["beta_S"]).max()
+    for t in (0, 19, 57, 100, 107):
+        k = ks[t]
+        sub = masks[which[t]] if which[t] < 5 else None
+        say(f"  oracle solve {t}: k={k} subset {'fold ' + str(which[t]) if sub is not None else 'all'}")
+        ref = oracle.fit(c2["bed"], n, Y[t], k, intercept=True, subset=sub)
+        it = int(res["n_iter"][t])
+        assert int(res["statuses"][t]) == ref["status"], t
+        assert it == ref["n_iter"], (t, it, ref["n_iter"])
+        assert np.array_equal(res["support"][t, :k].cpu().numpy(), ref["support"]), t
+        assert np.abs(res["beta_S"][t, :k].cpu().numpy() - ref["beta_S"]).max() <= 1e-6 * np.abs(ref["beta_S"]).max()
+        np.testing.assert_allclose(res["loss_trace"][t, :it + 1].cpu().numpy(), ref["loss_trace"], rtol=1e-9)
 
 
 # ------------------------------------------------------------------ n = 20,000, p = 2,000,000
@@ -160,13 +173,10 @@ def test_c5_fit_is_least_squares_on_its_support(c5):
 
 def test_c5_batched_mixed_against_fp64(c5):
     """32 traits x k in {50, 100, 150} in one int8 matrix-core batch against the FP64 solves of the
-    same traits and sizes. Up to the number of effects (100) every converged solve has the FP64
-    support. Past it the extra SNPs are noise at near-ties, where the quantised gradient (relative
-    error ~1e-7) can lead to another fixed point: there each int8 solve must still be the least-squares
-    fit on its own support, share all but a few SNPs with the FP64 support, and reach the same loss
-    within 0.5 % (a swapped noise SNP moves the loss by about one residual variance); the count of
-    identical supports and the loss differences are printed."""
-    n = c5["n"]
+    same traits and sizes. The matrix-core path takes the FP64 iteration's decisions (its projection
+    is certified against the quantisation bound, the support's gradient is FP64), so every solve has
+    the FP64 status, support and iteration count, above the number of effects (100) too, with beta
+    within 1e-6 and the loss trace within 1e-9 relative."""
     Z = dev(c5["Z"], torch.float32)
     s = iht.Stats(c5["geno"])
     ks = [k for k in (50, 100, 150) for _ in range(32)]
@@ -177,27 +187,44 @@ def test_c5_batched_mixed_against_fp64(c5):
         int(np.min(res["n_iter"])), "..", int(np.max(res["n_iter"])))
     ref = iht.fit_batch(c5["geno"], [s] * 96, dev(Y), ks, Z=Z, precision=iht.FP64)
     st64 = np.asarray(ref["statuses"])
-    both = (st == iht.OK) & (st64 == iht.OK)
-    say("converged in both precisions:", int(both.sum()), "of 96")
-    assert both.sum() >= 90
-    same = {50: 0, 100: 0, 150: 0}
-    for t in np.flatnonzero(both):
-        k = ks[t]
-        a = res["support"][t, :k].cpu().numpy()
-        b = ref["support"][t, :k].cpu().numpy()
-        if np.array_equal(a, b):
-            same[k] += 1
-            continue
-        assert k > 100, (t, k)  # within the number of effects the supports must agree
-        assert len(np.intersect1d(a, b)) >= k - 5, t
-        la = float(res["loss_trace"][t, int(res["n_iter"][t])])
-        lb = float(ref["loss_trace"][t, int(ref["n_iter"][t])])
-        say(f"  solve {t} (k={k}): {k - len(np.intersect1d(a, b))} SNPs differ, loss int8 {la:.3f} vs FP64 {lb:.3f}")
-        assert abs(la - lb) <= 5e-3 * lb, (t, la, lb)
-        bS, _ = ls_fit(c5["bed"], n, Y[t], a, Z=c5["Z"])
-        assert np.abs(res["beta_S"][t, :k].cpu().numpy() - bS).max() <= 1e-6 * np.abs(bS).max(), t
-    say("identical supports (converged in both), by k:", same)
-    for t in [t for t in (0, 45) if both[t]]:
-        k = ks[t]
-        b, _ = ls_fit(c5["bed"], n, Y[t], res["support"][t, :k].cpu().numpy(), Z=c5["Z"])
-        assert np.abs(res["beta_S"][t, :k].cpu().numpy() - b).max() <= 1e-6 * np.abs(b).max(), t
+    assert np.array_equal(st, st64)
+    assert np.array_equal(np.asarray(res["n_iter"]), np.asarray(ref["n_iter"]))
+    sup, sup64 = res["support"].cpu().numpy(), ref["support"].cpu().numpy()
+    b, b64 = res["beta_S"].cpu().numpy(), ref["beta_S"].cpu().numpy()
+    tr, tr64 = res["loss_trace"].cpu().numpy(), ref["loss_trace"].cpu().numpy()
+    same = 0
+    for t in range(96):
+        k, it = ks[t], int(res["n_iter"][t])
+        assert np.array_equal(sup[t, :k], sup64[t, :k]), t
+        assert np.abs(b[t, :k] - b64[t, :k]).max() <= 1e-6 * np.abs(b64[t, :k]).max(), t
+        np.testing.assert_allclose(tr[t, :it + 1], tr64[t, :it + 1], rtol=1e-9)
+        same += 1
+    say(f"identical supports and iteration counts: {same} of 96")
+
+
+def test_c5_solves_match_oracle_goldens(c5):
+    """Two FP64 oracle solves of this workload (k = 100 on its trait, k = 150 on a further trait of the
+    same generator; 5 covariates + intercept), stored by tests/golden/make_c5_goldens.py, against the
+    FP64 fit and the int8 matrix-core fit of the same problem."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c5_oracle_solves.json")
+    doc = json.load(open(path))
+    assert doc["generator"] == {"cfg": "c5", "seed": 2}
+    Z = dev(c5["Z"], torch.float32)
+    s = iht.Stats(c5["geno"])
+    for row in doc["solves"]:
+        ts, k = row["trait_seed"], row["k"]
+        y = c5["traits"][0 if ts is None else 1 + (ts - 700)]
+        for prec in (iht.FP64, iht.MIXED_I8):
+            say(f"c5 golden: trait seed {ts} k={k} precision {prec}")
+            res = iht.fit_batch(c5["geno"], [s], dev(y[None, :]), [k], Z=Z, precision=prec)
+            it = int(res["n_iter"][0])
+            assert int(res["statuses"][0]) == row["status"]
+            assert it == row["n_iter"], (it, row["n_iter"])
+            assert np.array_equal(res["support"][0, :k].cpu().numpy(), np.asarray(row["support"]))
+            ref_b = np.asarray(row["beta_S"])
+            assert np.abs(res["beta_S"][0, :k].cpu().numpy() - ref_b).max() <= 1e-6 * np.abs(ref_b).max()
+            np.testing.assert_allclose(res["beta_cov"][0].cpu().numpy(), row["beta_cov"], rtol=1e-6,
+                                       atol=1e-6 * np.abs(ref_b).max())
+            np.testing.assert_allclose(res["loss_trace"][0, :it + 1].cpu().numpy(), row["loss_trace"], rtol=1e-9)

@@ -70,8 +70,8 @@ def test_stats_degenerate_columns():
 GRAD_CASES = [(1, 3), (5, 17), (32, 8192), (33, 8193), (100, 1), (1001, 1234), (1000, 10_000), (2500, 40_000)]
 
 
-# p chosen so the pass runs each of its geometries at n = 1000 (32 tiles): 8, 4, 2 SNPs per lane,
-# the larger ones with the subject range split over workgroups (partial sums + finalize)
+# p chosen so the pass runs each of its geometries at n = 1000 (32 tiles): 1 and 2 SNPs per lane with
+# the subject range split over 3 workgroups (partial sums + finalize), and 2 SNPs per lane unsplit
 @pytest.mark.parametrize("p", [70_000, 140_000, 270_000])
 @pytest.mark.parametrize("precision", [iht.FP64, iht.FP32])
 def test_gradient_parity_pass_geometries(p, precision):
@@ -111,6 +111,43 @@ def test_gradient_parity(n, p, precision):
             assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
         else:
             assert rel(got, ref) <= 2e-6, rel(got, ref)
+
+
+@pytest.mark.parametrize("miss", [0.3, 0.97])
+@pytest.mark.parametrize("p", [3000, 140_000])
+def test_gradient_heavy_missingness(miss, p):
+    """The missing term comes from per-SNP lists of missing subjects; with 30 % and 97 % missing
+    the lists are longer than the pass's table steps (the part of a list past them is summed after
+    the steps), on an unsplit and a split subject range; plus columns that are entirely missing."""
+    n = 1000
+    say(f"gradient missingness {miss} n={n} p={p}")
+    bed, _ = synth.make_genotypes(n, p, seed=int(miss * 100) + p, miss=miss)
+    codes = synth.unpack_codes(bed, n)
+    codes[:3] = synth.CODE_MISSING
+    bed = synth.pack_codes(codes)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    r = np.random.default_rng(p).standard_normal(n) + 1.0
+    got = iht.gradient(g, s, dev(r)).cpu().numpy()
+    u, v = oracle.stats(bed, n)
+    ref = oracle.gradient(bed, n, u, v, r)
+    assert np.all(got[:3] == 0.0)
+    assert rel(got, ref) <= 1e-12, rel(got, ref)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_gradient_more_than_65536_subjects():
+    """n = 70,000: the missing lists hold 32-bit subject indices."""
+    n, p = 70_000, 2000
+    bed, _ = synth.make_genotypes(n, p, seed=23)
+    g = iht.Geno(bed, n)
+    s = iht.Stats(g)
+    r = np.random.default_rng(4).standard_normal(n)
+    got = iht.gradient(g, s, dev(r)).cpu().numpy()
+    u, v = oracle.stats(bed, n)
+    ref = oracle.gradient(bed, n, u, v, r)
+    assert rel(got, ref) <= 1e-12, rel(got, ref)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_gradient_subset_ignores_rows_outside():

@@ -119,6 +119,39 @@ def test_served_fp64_matches_oracle(prob):
     srv.close()
 
 
+def test_served_mixed_matches_fp64_and_oracle_above_effects(prob):
+    """The serving workload's regime on a small matrix: int8 matrix-core served solves with k above
+    the traits' 10 effects (k up to 40, near-ties among noise SNPs), two requests on different subject
+    sets sharing the slots. Each equals the FP64 fit of the same solve (status, support, iteration
+    count; beta within 1e-6, loss trace within 1e-9 relative), and two of them equal the oracle."""
+    srv = iht.Server(prob["geno"], slots=16, kmax=40, hbm_budget=8 << 30, precision=iht.MIXED_I8)
+    reqs = [(synth.make_subset(prob["n"], 1000, 9), np.array([0, 3, 5, 8, 11, 14]), np.array([12, 20, 25, 30, 35, 40])),
+            (None, np.array([1, 2, 6, 7]), np.array([40, 33, 18, 27]))]
+    ids = [srv.submit(dev(prob["traits"][rows]), ks, subset) for subset, rows, ks in reqs]
+    srv.run_until_idle()
+    checked = 0
+    for rid, (subset, rows, ks) in zip(ids, reqs):
+        res = srv.result(rid)
+        for j, (row, k) in enumerate(zip(rows, ks)):
+            k = int(k)
+            ref = alone(prob, subset, row, k, iht.FP64)
+            it = int(ref["n_iter"])
+            assert int(res["statuses"][j]) == ref["status"], (rid, j)
+            assert int(res["n_iter"][j]) == it, (rid, j)
+            assert torch.equal(res["support"][j, :k], ref["support"]), (rid, j)
+            b64 = ref["beta_S"].cpu().numpy()
+            assert np.abs(res["beta_S"][j, :k].cpu().numpy() - b64).max() <= 1e-6 * np.abs(b64).max()
+            np.testing.assert_allclose(res["loss_trace"][j, :it + 1].cpu().numpy(),
+                                       ref["loss_trace"].cpu().numpy(), rtol=1e-9)
+            if j == 0:
+                o = oracle.fit(prob["bed"], prob["n"], prob["traits"][row], k, intercept=True, subset=subset)
+                assert int(res["n_iter"][j]) == o["n_iter"]
+                assert np.array_equal(res["support"][j, :k].cpu().numpy(), o["support"])
+                checked += 1
+    assert checked == 2
+    srv.close()
+
+
 def test_budget_limits_admission_to_one_subject_set(prob):
     """A budget with room for one statistics block admits one request at a time."""
     g = prob["geno"]
