@@ -1252,9 +1252,8 @@ hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st
     e = hipGetLastError();
     return (e != hipSuccess || !J.certify) ? e : filter_final(Jc);
   }
-  if (J.certify) return hipErrorInvalidValue;
   // histogram path (large k or very long rows): about 2048 blocks over all rows, 4096 to 65536
-  // entries per block
+  // entries per block; a certified row then filters with its result as the hint, as above
   int64_t chunk = 4096;
   while (chunk < 65536 && (p + chunk - 1) / chunk * rows > 2048) chunk <<= 1;
   const dim3 grid((unsigned)((p + chunk - 1) / chunk), (unsigned)rows);
@@ -1262,7 +1261,8 @@ hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_topk_collect, grid, dim3(1024), 0, st, J, p, chunk);
-  return hipGetLastError();
+  e = hipGetLastError();
+  return (e != hipSuccess || !J.certify) ? e : filter_final(Jc);
 }
 
 hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, double* mask, hipStream_t st) {

@@ -165,6 +165,28 @@ def test_fit_batch_mixed_equals_fp64_above_effects():
         assert np.array_equal(a["support"][t, :ks[t]].cpu().numpy(), ref["support"])
 
 
+def test_fit_batch_mixed_long_rows_equals_fp64():
+    """p = 700,000 with k = 100 and 130: the first (cold) projection of a row has more candidates than
+    one block's registers hold (p k > 8192 * 8192), so it takes the histogram top-k before the
+    certified filter. The int8 batch takes the FP64 batch's decisions there too."""
+    prob = synth.make_problem("c1", seed=12, n=640, p=700_000)
+    n = prob["n"]
+    traits = [synth.make_trait(prob["bed"], n, prob["q"], 10, (0.2, 0.5), seed=500 + e)[0] for e in range(3)]
+    g = iht.Geno(prob["bed"], n)
+    s = iht.Stats(g)
+    ks = [100, 100, 130, 130]
+    Y = dev(np.stack([traits[0], traits[1], traits[0], traits[2]]))
+    out = {p_: iht.fit_batch(g, [s] * 4, Y, ks, precision=p_, max_iter=60) for p_ in (iht.MIXED_I8, iht.FP64)}
+    a, b = out[iht.MIXED_I8], out[iht.FP64]
+    assert list(a["statuses"]) == list(b["statuses"])
+    assert list(a["n_iter"]) == list(b["n_iter"])
+    for t, k in enumerate(ks):
+        assert torch.equal(a["support"][t, :k], b["support"][t, :k]), t
+        bb = b["beta_S"][t, :k].cpu().numpy()
+        assert np.abs(a["beta_S"][t, :k].cpu().numpy() - bb).max() <= 1e-6 * np.abs(bb).max(), t
+    say(f"  iterations {list(a['n_iter'])}, statuses {list(a['statuses'])}")
+
+
 def test_fit_fp32_single_converges_with_polish():
     prob = synth.make_problem("c1", seed=2)
     g = iht.Geno(prob["bed"], prob["n"])
