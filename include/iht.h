@@ -26,7 +26,9 @@
  *    stream themselves.
  *  - Ownership: the caller owns every input and output buffer and keeps it alive for the call;
  *    handles own their device memory and free it in the matching *_destroy.
- *  - Threading: a handle must not be used by two threads at once; distinct handles are independent.
+ *  - Threading: a handle must not be used by two threads at once, and the calls on one genotype handle
+ *    must go to one stream (iht_gradient, iht_gradient_batch and fits without a workspace share the
+ *    handle's device scratch); distinct handles are independent.
  *  - Genotypes: PLINK 1 SNP-major .bed rows. SNP j occupies `row_bytes` bytes; subject i is in byte
  *    i/4 at bits 2(i%4) (low) and 2(i%4)+1 (high); two-bit value 0 = homozygous first allele
  *    (dosage 0), 1 = missing, 2 = heterozygous (dosage 1), 3 = homozygous second allele (dosage 2).
@@ -106,10 +108,29 @@ typedef struct iht_opts {
     double mixed_tol;      /* iteration tolerance of IHT_FP32; default 1e-6                 */
     int32_t polish_iter;   /* FP64 refinement steps after an IHT_FP32 solve; default 200    */
     int32_t family;        /* IHT_GAUSSIAN (default) or IHT_LOGISTIC                        */
+    void *workspace;       /* NULL (default): the solve state lives in the genotype handle (device */
+                           /* memory allocated on first use, grown and reused); else device memory */
+                           /* of at least iht_workspace_bytes[_batch] bytes, 256-byte aligned     */
+    uint64_t workspace_bytes; /* size of workspace                                           */
 } iht_opts;
 
 /* Fill *o with the defaults above. */
 void iht_opts_default(iht_opts *o);
+
+/*
+ * Device memory of one solve's state (Methods, "Penalized regression": the problem is fixed by n,
+ * p, the model size k and the unpenalised columns): the size of the workspace that iht_fit takes
+ * through iht_opts.workspace for n subjects, p SNPs, k and c unpenalised columns (covariates plus
+ * the intercept column), at `precision`. With a workspace, iht_fit and iht_fit_batch allocate no
+ * device memory (they keep a small pinned host staging area per genotype handle, allocated on its
+ * first use); the caller owns the workspace, keeps it alive until the call returns, and must not
+ * use it from two calls at once; its contents on entry do not matter and on return are undefined.
+ * iht_cv and the server ignore iht_opts.workspace. Returns 0 for arguments out of range
+ * (n, p, k < 1, c < 0 or c > 64).
+ */
+size_t iht_workspace_bytes(int64_t n, int64_t p, int32_t k, int32_t c, int32_t precision);
+/* The same for iht_fit_batch with T solves of model sizes up to kmax. */
+size_t iht_workspace_bytes_batch(int64_t n, int64_t p, int32_t T, int32_t kmax, int32_t c, int32_t precision);
 
 /*
  * Upload (if IHT_HOST_PTR) and re-tile a PLINK SNP-major matrix once onto the current device
@@ -202,7 +223,8 @@ int iht_project_hint(const double *w, int64_t p, int32_t k, const int64_t *hint,
  *   loss_trace device [max_iter + 1] FP64 output: f at beta^0 .. beta^{n_iter}.
  *   n_iter     host int32 output: iterations performed.
  * Returns IHT_OK, IHT_NOT_CONVERGED, IHT_STALLED, or an error (IHT_EINVAL, IHT_ENONFINITE,
- * IHT_ENOMEM, IHT_EDEVICE). Synchronises the stream. Same as iht_fit_batch with T = 1.
+ * IHT_ENOMEM, IHT_EDEVICE; IHT_EINVAL also for a workspace smaller than iht_workspace_bytes or not
+ * 256-byte aligned). Synchronises the stream. Same as iht_fit_batch with T = 1.
  */
 int iht_fit(const iht_geno *g, const iht_stats *s, const double *y, const float *Z, int32_t cz, int32_t intercept, int32_t k,
             const iht_opts *opts, int64_t *support, double *beta_S, double *beta_cov, double *loss_trace, int32_t *n_iter,

@@ -31,6 +31,17 @@ void iht_opts_default(iht_opts* o) {
   o->mixed_tol = 1e-6;
   o->polish_iter = 200;
   o->family = IHT_GAUSSIAN;
+  o->workspace = nullptr;
+  o->workspace_bytes = 0;
+}
+
+size_t iht_workspace_bytes_batch(int64_t n, int64_t p, int32_t T, int32_t kmax, int32_t c, int32_t precision) {
+  if (n < 1 || p < 1 || T < 1 || kmax < 1 || c < 0 || c > kMaxUnpenalized) return 0;
+  return SolveWork::workspace_bytes(make_layout(n, p), T, kmax, c, precision == IHT_MIXED_I8);
+}
+
+size_t iht_workspace_bytes(int64_t n, int64_t p, int32_t k, int32_t c, int32_t precision) {
+  return iht_workspace_bytes_batch(n, p, 1, k, c, precision);
 }
 
 const char* iht_last_error(void) { return last_error_text().c_str(); }
@@ -351,7 +362,13 @@ int run_fit(const FitArgs& A) {
                      A.beta_cov ? A.beta_cov + (size_t)t * nc : nullptr, nullptr, kmax};
   }
   Engine E;
-  if (int rc = E.setup(g, &const_cast<iht_geno*>(g)->fit, T, kmax, A.U, A.Y, A.ldy, A.trace, A.o, A.st)) return rc;
+  // device state: the handle's own (allocated on first use, grown and reused), or the caller's workspace
+  iht_geno* G = const_cast<iht_geno*>(g);
+  SolveWork borrowed;
+  SolveWork* W = A.o.workspace ? &borrowed : &G->fit;
+  if (int rc = E.setup(g, W, &G->fit_stage, T, kmax, A.U, A.Y, A.ldy, A.trace, A.o, A.st, A.o.workspace,
+                       (size_t)A.o.workspace_bytes))
+    return rc;
   if (int rc = E.admit(A.ks, sv.data(), nullptr)) return rc;
   for (int32_t turn = 0; turn <= A.o.max_iter && E.count_active() > 0; ++turn)
     if (int rc = E.turn()) return rc;
@@ -437,6 +454,8 @@ int iht_cv(const iht_geno* g, const double* y, const float* Z, int32_t cz, int32
   iht_opts o;
   iht_opts_default(&o);
   if (opts) o = *opts;
+  o.workspace = nullptr;  // the training batch and the refit use the handle's own memory
+  o.workspace_bytes = 0;
   if (!g || !y || !folds || !ks || !mse || !k_best || !support || !beta_S || !loss_trace || !n_iter)
     return fail(IHT_EINVAL, "iht_cv: NULL argument");
   const Layout& L = g->L;

@@ -31,16 +31,100 @@ int check_kmax(const iht_opts& o, int32_t kmax, const char* who) {
   return IHT_OK;
 }
 
+std::vector<std::pair<DevBuf*, size_t>> SolveWork::plan(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed) {
+  const size_t Tz = (size_t)T, kz = (size_t)kmax;
+  const size_t nb = (size_t)solve_subject_blocks(L.n), pst = (size_t)solve_partial_stride(nc);
+  std::vector<std::pair<DevBuf*, size_t>> P = {
+      {&beta, Tz * L.p * 8},
+      {&g, Tz * L.p * 8},
+      {&partial, gradient_work_bytes(L)},
+      {&r, Tz * L.n_pad * 8},
+      {&rc, Tz * L.n_pad * 8},
+      {&S, Tz * kz * 8},
+      {&Sp, Tz * kz * 8},
+      {&betap, Tz * kz * 8},
+      {&X, Tz * 2 * kz * L.n_pad * 8},
+      {&bc, Tz * kMaxUnpenalized * 8},
+      {&bcp, Tz * kMaxUnpenalized * 8},
+      {&gc, Tz * kMaxUnpenalized * 8},
+      {&fs, Tz * sizeof(FitState)},
+      {&part, Tz * nb * pst * 8},
+      {&pmu, Tz * nb * 8},
+      {&ysum, Tz * kYsumStride * 8},
+      {&pw, Tz * 3 * (kz + kMaxUnpenalized) * 8},
+      {&ks, Tz * 4},
+      {&sv, Tz * sizeof(BatchSolve)},
+      {&flags, Tz * 4},
+      {&rows, Tz * sizeof(OutRow)},
+  };
+  if (mixed) {
+    P.push_back({&r8, batch_r8_bytes(L, T)});
+    P.push_back({&scale, (size_t)batch_t_pad(T) * 8});
+    P.push_back({&rsum, (size_t)batch_t_pad(T) * 8});
+    P.push_back({&slots, Tz * 4});
+    P.push_back({&count, 4});
+    P.push_back({&rg, Tz * L.n_pad * 8});
+  }
+  P.push_back({&topk.small, TopkArea::small_bytes(T)});
+  P.push_back({&topk.cand, TopkArea::cand_bytes(L.p, T)});
+  return P;
+}
+
+namespace {
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+size_t SolveWork::workspace_bytes(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed) {
+  SolveWork W;
+  size_t s = 0;
+  for (const auto& e : W.plan(L, T, kmax, nc, mixed)) s += align256(e.second);
+  return s;
+}
+
+int SolveWork::provide(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed, void* ws, size_t ws_bytes,
+                       hipStream_t st) {
+  const auto P = plan(L, T, kmax, nc, mixed);
+  if (!ws) {
+    for (size_t i = 0; i + 2 < P.size(); ++i) HIPCHK(P[i].first->ensure(P[i].second));
+    return topk.ensure(L.p, T, st);
+  }
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(IHT_EINVAL, "workspace not 256-byte aligned");
+  size_t need = 0;
+  for (const auto& e : P) need += align256(e.second);
+  if (ws_bytes < need)
+    return fail(IHT_EINVAL, "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(need) + " bytes");
+  char* at = static_cast<char*>(ws);
+  for (size_t i = 0; i + 2 < P.size(); ++i) {
+    P[i].first->borrow(at, P[i].second);
+    at += align256(P[i].second);
+  }
+  char* small_p = at;
+  char* cand_p = at + align256(P[P.size() - 2].second);
+  return topk.borrow(small_p, cand_p, L.p, T, st);
+}
+
+int64_t SolveWork::device_bytes() const {
+  const DevBuf* b[] = {&beta, &g,    &partial, &r,     &rc,   &S,     &Sp,    &betap, &X,     &bc,
+                       &bcp,  &gc,   &fs,      &part,  &pmu,  &ysum,  &pw,    &ks,    &sv,    &flags,
+                       &rows, &r8,   &scale,   &rsum,  &slots, &count, &rg,   &topk.small, &topk.cand};
+  int64_t s = 0;
+  for (const DevBuf* d : b) s += (int64_t)d->bytes;
+  return s;
+}
+
 Engine::~Engine() {
   if (exec_) (void)hipGraphExecDestroy(exec_);
   if (cap_st_) (void)hipStreamDestroy(cap_st_);
 }
 
-int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, const Unpen& U, const double* Y,
-                  int64_t ldy, double* trace, const iht_opts& o, hipStream_t st) {
+int Engine::setup(const iht_geno* g, SolveWork* Wp, SolveStage* Pp, int32_t T, int32_t kmax, const Unpen& U,
+                  const double* Y, int64_t ldy, double* trace, const iht_opts& o, hipStream_t st, void* ws,
+                  size_t ws_bytes) {
   g_ = g;
   W_ = Wp;
+  P_ = Pp;
   SolveWork& W = *Wp;
+  SolveStage& PS = *Pp;
   L_ = g->L;
   const Layout& L = L_;
   o_ = o;
@@ -55,51 +139,21 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, int32_t T, int32_t kmax, con
   // the matrix-core path follows the FP64 iteration exactly (certified projection, FP64 gradient on
   // the support), so it stops by the same rule; the FP32 pass stops at mixed_tol and is refined
   tol_main_ = o.precision == IHT_FP32 ? std::max(o.tol, o.mixed_tol) : o.tol;
-  const size_t Tz = (size_t)T, kz = (size_t)kmax;
-
-  HIPCHK(W.beta.ensure(Tz * L.p * 8));
-  HIPCHK(W.g.ensure(Tz * L.p * 8));
-  HIPCHK(W.partial.ensure(gradient_work_bytes(L)));
-  HIPCHK(W.r.ensure(Tz * L.n_pad * 8));
-  HIPCHK(W.rc.ensure(Tz * L.n_pad * 8));
-  HIPCHK(W.S.ensure(Tz * kz * 8));
-  HIPCHK(W.Sp.ensure(Tz * kz * 8));
-  HIPCHK(W.betap.ensure(Tz * kz * 8));
-  HIPCHK(W.X.ensure(Tz * 2 * kz * L.n_pad * 8));
-  HIPCHK(W.bc.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.bcp.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.gc.ensure(Tz * kMaxUnpenalized * 8));
-  HIPCHK(W.fs.ensure(Tz * sizeof(FitState)));
+  const size_t Tz = (size_t)T;
+  if (int rc = W.provide(L, T, kmax, nc_, mixed_, ws, ws_bytes, st)) return rc;
   const int32_t nb = solve_subject_blocks(L.n), pst = solve_partial_stride(nc_);
-  HIPCHK(W.part.ensure(Tz * (size_t)nb * (size_t)pst * 8));
-  HIPCHK(W.pmu.ensure(Tz * (size_t)nb * 8));
-  HIPCHK(W.ysum.ensure(Tz * kYsumStride * 8));
-  HIPCHK(W.pw.ensure(Tz * 3 * (kz + kMaxUnpenalized) * 8));
-  HIPCHK(W.ks.ensure(Tz * 4));
-  HIPCHK(W.sv.ensure(Tz * sizeof(BatchSolve)));
-  HIPCHK(W.flags.ensure(Tz * 4));
-  HIPCHK(W.rows.ensure(Tz * sizeof(OutRow)));
-  if (int rc = W.topk.ensure(L.p, T, st)) return rc;
-  if (mixed_) {
-    HIPCHK(W.r8.ensure(batch_r8_bytes(L, T)));
-    HIPCHK(W.scale.ensure((size_t)batch_t_pad(T) * 8));
-    HIPCHK(W.rsum.ensure((size_t)batch_t_pad(T) * 8));
-    HIPCHK(W.slots.ensure(Tz * 4));
-    HIPCHK(W.count.ensure(4));
-    HIPCHK(W.rg.ensure(Tz * L.n_pad * 8));
-  }
   // pinned areas: FitStates; ks, subject sets, flags, output rows, top-k error words
-  HIPCHK(W.host.ensure(Tz * sizeof(FitState)));
+  HIPCHK(PS.host.ensure(Tz * sizeof(FitState)));
   const size_t o_sv = align16(Tz * 4), o_fl = o_sv + align16(Tz * sizeof(BatchSolve));
   const size_t o_rows = o_fl + align16(Tz * 4), o_err = o_rows + align16(Tz * sizeof(OutRow));
-  HIPCHK(W.stage.ensure(o_err + Tz * 4));
-  h_ = reinterpret_cast<FitState*>(W.host.p);
+  HIPCHK(PS.stage.ensure(o_err + Tz * 4));
+  h_ = reinterpret_cast<FitState*>(PS.host.p);
   std::memset(h_, 0, Tz * sizeof(FitState));
-  ks_h_ = reinterpret_cast<int32_t*>(W.stage.p);
-  sv_h_ = reinterpret_cast<BatchSolve*>(W.stage.p + o_sv);
-  flags_h_ = reinterpret_cast<int32_t*>(W.stage.p + o_fl);
-  rows_h_ = reinterpret_cast<OutRow*>(W.stage.p + o_rows);
-  terr_ = reinterpret_cast<uint32_t*>(W.stage.p + o_err);
+  ks_h_ = reinterpret_cast<int32_t*>(PS.stage.p);
+  sv_h_ = reinterpret_cast<BatchSolve*>(PS.stage.p + o_sv);
+  flags_h_ = reinterpret_cast<int32_t*>(PS.stage.p + o_fl);
+  rows_h_ = reinterpret_cast<OutRow*>(PS.stage.p + o_rows);
+  terr_ = reinterpret_cast<uint32_t*>(PS.stage.p + o_err);
   launch_.assign(Tz, 0);
 
   SolveSet& Q = Q_;

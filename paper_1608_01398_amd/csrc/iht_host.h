@@ -40,14 +40,23 @@ inline int hip_fail(hipError_t e, const char* what) {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool owned = true;  // false: a view into memory the caller owns (a workspace); never freed here
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
+  }
+  // views b bytes at q (owned memory is released first)
+  void borrow(void* q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    owned = false;
   }
   // grows to at least b bytes (contents are lost when it grows); *fresh tells whether it did
   hipError_t ensure(size_t b, bool* fresh = nullptr) {
@@ -105,19 +114,32 @@ struct TopkArea {
   DevBuf cand;   // rows x cap x (8 + 4) bytes
   int64_t cap = 0;
   int32_t rows = 0;
+  static int64_t cap_for(int64_t p) { return std::max<int64_t>(p, 16384); }  // also holds the two-pass candidates
+  static size_t small_bytes(int32_t nrows) { return (size_t)nrows * kTopkRowWords * 4; }
+  static size_t cand_bytes(int64_t p, int32_t nrows) {
+    return (size_t)nrows * (size_t)cap_for(p) * (sizeof(uint64_t) + sizeof(int32_t));
+  }
   int ensure(int64_t p, int32_t nrows, hipStream_t st) {
     if (nrows > rows || !small.p) {
       bool fresh = false;
-      const size_t words = (size_t)nrows * kTopkRowWords;
-      HIPCHK(small.ensure(words * 4, &fresh));
-      if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)words, st));
+      HIPCHK(small.ensure(small_bytes(nrows), &fresh));
+      if (fresh) HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)nrows * kTopkRowWords, st));
       rows = nrows;
     }
-    const int64_t want = std::max<int64_t>(p, 16384);  // also holds the two-pass candidates
+    const int64_t want = cap_for(p);
     if (want > cap || (size_t)rows * (size_t)cap * 12 > cand.bytes) {
       cap = std::max(cap, want);
       HIPCHK(cand.ensure((size_t)rows * (size_t)cap * (sizeof(uint64_t) + sizeof(int32_t))));
     }
+    return IHT_OK;
+  }
+  // views caller memory laid out by the plan below; the counters are cleared on the stream
+  int borrow(void* small_p, void* cand_p, int64_t p, int32_t nrows, hipStream_t st) {
+    small.borrow(small_p, small_bytes(nrows));
+    cand.borrow(cand_p, cand_bytes(p, nrows));
+    rows = nrows;
+    cap = cap_for(p);
+    HIPCHK(launch_zero_u32(small.as<uint32_t>(), (int64_t)nrows * kTopkRowWords, st));
     return IHT_OK;
   }
   uint64_t* cand_key() const { return cand.as<uint64_t>(); }
@@ -126,12 +148,28 @@ struct TopkArea {
   }
 };
 
-// Device state of a set of solve slots (grown on demand and reused), plus the pinned host areas
-// through which the engine exchanges the slots' small inputs and flags.
+// Device state of a set of solve slots: allocated by the library (grown on demand and reused) or
+// carved out of a caller's workspace.
 struct SolveWork {
   DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv, flags, rows;
   DevBuf r8, scale, rsum, slots, count, rg;  // matrix-core pass work; rg: centred residual of each slot's gradient
   TopkArea topk;
+
+  // Every device buffer of T slots with model sizes up to kmax and nc unpenalised columns, with its
+  // size (the top-k area's two buffers last). One list serves allocation, carving a workspace and
+  // sizing one, so the three cannot disagree.
+  std::vector<std::pair<DevBuf*, size_t>> plan(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed);
+  // Bytes of a workspace that holds plan(...) (each buffer 256-byte aligned).
+  static size_t workspace_bytes(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed);
+  // Allocates (ws == NULL) or carves ws (ws_bytes >= workspace_bytes) into the plan's buffers.
+  int provide(const Layout& L, int32_t T, int32_t kmax, int32_t nc, bool mixed, void* ws, size_t ws_bytes,
+              hipStream_t st);
+  int64_t device_bytes() const;
+};
+
+// Pinned host memory through which an engine exchanges the slots' small inputs and flags with the
+// device (kept by the handle that owns the engine's memory).
+struct SolveStage {
   PinnedBuf host;   // the slots' FitStates as last read
   PinnedBuf stage;  // ks, subject sets, flags, output rows and top-k error words
 };
@@ -168,8 +206,10 @@ class Engine {
 
   // Device state of T slots with model sizes up to kmax (allocated in W). Slot t reads its trait
   // at Y + t * ldy and keeps its loss trace at trace + t * (max_iter + 1).
-  int setup(const iht_geno* g, SolveWork* W, int32_t T, int32_t kmax, const Unpen& U, const double* Y, int64_t ldy,
-            double* trace, const iht_opts& o, hipStream_t st);
+  // The device state comes from W (allocated there, or carved from the workspace ws of ws_bytes
+  // bytes when ws is not NULL), the pinned staging from P.
+  int setup(const iht_geno* g, SolveWork* W, SolveStage* P, int32_t T, int32_t kmax, const Unpen& U, const double* Y,
+            int64_t ldy, double* trace, const iht_opts& o, hipStream_t st, void* ws = nullptr, size_t ws_bytes = 0);
   // Admits the slots with admit[t] != 0 (every slot if admit is NULL): ks and sv (host [T]) give
   // every slot's model size and subject set; the admitted ones get beta = 0, the initial residual,
   // gradient, support and step size, and their first proposal. The other slots are untouched.
@@ -198,6 +238,7 @@ class Engine {
 
   const iht_geno* g_ = nullptr;
   SolveWork* W_ = nullptr;
+  SolveStage* P_ = nullptr;
   Layout L_{};
   iht_opts o_{};
   hipStream_t st_ = nullptr;
@@ -232,6 +273,7 @@ struct iht_geno {
   // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
   iht::DevBuf partial, state;
   iht::SolveWork fit;
+  iht::SolveStage fit_stage;
   iht::DevBuf batch_r8, batch_scale, batch_rsum, batch_sv;  // iht_gradient_batch work areas
   iht::DevBuf pred_err;                                      // iht_predict's error word
 };

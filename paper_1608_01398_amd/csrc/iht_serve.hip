@@ -70,6 +70,7 @@ struct iht_server {
   int32_t slots = 0, kmax = 0;
   int64_t budget = 0;
   SolveWork W;
+  SolveStage P;
   Engine E;
   DevBuf Y;          // [slots][n] traits of the admitted solves
   DevBuf trace;      // [slots][max_iter + 1] loss traces until written out
@@ -87,16 +88,6 @@ struct iht_server {
 };
 
 namespace {
-
-int64_t work_bytes(const SolveWork& W) {
-  const DevBuf* b[] = {&W.beta, &W.g,   &W.partial, &W.r,     &W.rc,     &W.S,     &W.Sp,    &W.betap,
-                       &W.X,    &W.bc,  &W.bcp,     &W.gc,    &W.fs,     &W.part,  &W.pmu,   &W.ysum,
-                       &W.pw,   &W.ks,  &W.sv,      &W.flags, &W.rows,   &W.r8,    &W.scale, &W.rsum,
-                       &W.slots, &W.count, &W.topk.small, &W.topk.cand};
-  int64_t s = 0;
-  for (const DevBuf* d : b) s += (int64_t)d->bytes;
-  return s;
-}
 
 // Admits queued requests in arrival order while the one at the head fits.
 int admit_queued(iht_server* S) {
@@ -204,6 +195,8 @@ int iht_server_create(const iht_geno* g, int32_t slots, int32_t kmax, int64_t hb
   iht_opts o;
   iht_opts_default(&o);
   if (opts) o = *opts;
+  o.workspace = nullptr;  // the server allocates its state at creation, inside its budget
+  o.workspace_bytes = 0;
   const Layout& L = g->L;
   if (slots < 1 || slots > 65535) return fail(IHT_EINVAL, "iht_server_create: slots out of range");
   if (kmax < 1 || kmax > L.p || kmax > IHT_MAX_K) return fail(IHT_EINVAL, "iht_server_create: kmax out of range");
@@ -229,10 +222,10 @@ int iht_server_create(const iht_geno* g, int32_t slots, int32_t kmax, int64_t hb
   if ((e = S->Y.ensure((size_t)slots * (size_t)L.n * 8)) != hipSuccess ||
       (e = S->trace.ensure((size_t)slots * (size_t)(o.max_iter + 1) * 8)) != hipSuccess)
     return bail(hip_fail(e, "hipMalloc(server slots)"));
-  if (int rc = S->E.setup(g, &S->W, slots, kmax, S->U, S->Y.as<double>(), L.n, S->trace.as<double>(), o, S->st))
+  if (int rc = S->E.setup(g, &S->W, &S->P, slots, kmax, S->U, S->Y.as<double>(), L.n, S->trace.as<double>(), o, S->st))
     return bail(rc);
   S->E.use_graphs(IHT_SERVER_GRAPHS != 0);
-  const int64_t slot_bytes = work_bytes(S->W) + (int64_t)S->Y.bytes + (int64_t)S->trace.bytes;
+  const int64_t slot_bytes = S->W.device_bytes() + (int64_t)S->Y.bytes + (int64_t)S->trace.bytes;
   const int64_t block_bytes = (int64_t)stats_block_bytes(L);
   if (hbm_budget < slot_bytes + block_bytes)
     return bail(fail(IHT_ENOMEM, "iht_server_create: the budget holds less than the slot state (" +

@@ -25,7 +25,7 @@ EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
            "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
            "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning", "iht_status_str",
-           "iht_last_error")
+           "iht_last_error", "iht_workspace_bytes", "iht_workspace_bytes_batch")
 
 
 class IHTError(RuntimeError):
@@ -37,7 +37,8 @@ class IHTError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("max_backtrack", ctypes.c_int32),
                 ("c", ctypes.c_double), ("shrink", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32), ("family", ctypes.c_int32)]
+                ("mixed_tol", ctypes.c_double), ("polish_iter", ctypes.c_int32), ("family", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
 
 
 class ServerInfo(ctypes.Structure):
@@ -89,6 +90,10 @@ def load():
               "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
               "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning"):
         getattr(L, f).restype = ctypes.c_int
+    L.iht_workspace_bytes.argtypes = [I64, I64, I32, I32, I32]
+    L.iht_workspace_bytes.restype = ctypes.c_size_t
+    L.iht_workspace_bytes_batch.argtypes = [I64, I64, I32, I32, I32, I32]
+    L.iht_workspace_bytes_batch.restype = ctypes.c_size_t
     L.iht_status_str.argtypes = [ctypes.c_int]
     L.iht_status_str.restype = ctypes.c_char_p
     L.iht_last_error.argtypes = []
@@ -131,13 +136,31 @@ def _dev(t, dtype, shape=None, name="tensor"):
 
 
 def default_opts(**kw):
+    """iht_opts with the library defaults and the given fields; `workspace` may be a CUDA tensor (its
+    bytes become the workspace; the caller keeps it alive for the call)."""
     o = Opts()
     load().iht_opts_default(ctypes.byref(o))
+    ws = kw.pop("workspace", None)
     for k, v in kw.items():
-        if not hasattr(o, k):
+        if not hasattr(o, k) or k == "workspace_bytes":
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
+    if ws is not None:
+        torch = _torch()
+        if not isinstance(ws, torch.Tensor) or not ws.is_cuda or not ws.is_contiguous():
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        o.workspace = ws.data_ptr()
+        o.workspace_bytes = ws.numel() * ws.element_size()
     return o
+
+
+def workspace_bytes(n: int, p: int, k: int, c: int, precision: int = 0, T: int | None = None) -> int:
+    """Device bytes of the workspace of one fit (iht_workspace_bytes) or of T solves with model sizes up
+    to k (iht_workspace_bytes_batch); c = unpenalised columns (covariates + intercept)."""
+    L = load()
+    if T is None:
+        return int(L.iht_workspace_bytes(n, p, k, c, precision))
+    return int(L.iht_workspace_bytes_batch(n, p, T, k, c, precision))
 
 
 class Geno:

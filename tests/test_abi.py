@@ -88,3 +88,24 @@ def test_oracle_builds_and_is_not_linked_by_the_library(lib_path):
     assert "oracle" not in out
     deps = subprocess.check_output(["nm", "-D", "--undefined-only", lib_path], text=True)
     assert "iht_ref" not in deps
+
+
+def test_workspace_bytes_host_only(lib_path):
+    """iht_workspace_bytes sizes the caller's workspace on the host (no device needed): it grows with
+    the number of solves, the model size and the matrix, the matrix-core path needs more (its residual
+    digits and scales), one fit equals a batch of one, and arguments out of range give 0."""
+    from paper_1608_01398_amd import iht
+
+    one = iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64)
+    assert one > 0 and one % 256 == 0
+    assert one == iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=1)
+    # beta and g (16 B per SNP), the top-k candidates (12 B per SNP) dominate at this shape
+    assert 28 * 500_000 <= one <= 28 * 500_000 + (64 << 20)
+    assert iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=8) > 7 * one
+    assert iht.workspace_bytes(5000, 500_000, 40, 1, iht.FP64) > one
+    assert iht.workspace_bytes(5000, 600_000, 20, 1, iht.FP64) > one
+    assert iht.workspace_bytes(5000, 500_000, 20, 1, iht.MIXED_I8) > one
+    L = iht.load()
+    for args in ((0, 10, 1, 1, 0), (10, 0, 1, 1, 0), (10, 10, 0, 1, 0), (10, 10, 1, -1, 0), (10, 10, 1, 65, 0)):
+        assert L.iht_workspace_bytes(*args) == 0, args
+    assert L.iht_workspace_bytes_batch(10, 10, 0, 1, 1, 0) == 0
