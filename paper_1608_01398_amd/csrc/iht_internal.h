@@ -21,7 +21,7 @@ constexpr int64_t kSnpAlign = 8192;  // p is padded to this (covers 1024 lanes x
 #define IHT_PASS_SNP_BARRIER 0
 #endif
 #ifndef IHT_PASS_MAX_NS
-#define IHT_PASS_MAX_NS 2
+#define IHT_PASS_MAX_NS 4
 #endif
 constexpr int kPassThreads = IHT_PASS_THREADS;  // one pass workgroup per CU (128 KB of table in LDS)
 constexpr int kPassMaxNS = IHT_PASS_MAX_NS;     // SNPs per lane, at most

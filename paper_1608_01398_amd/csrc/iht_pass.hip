@@ -7,12 +7,9 @@
 // mean-imputed missing entries (x~ = u_j, so they contribute 0). Centring is exact in real
 // arithmetic because every standardised column sums to zero over the subject set.
 //
-// D_j comes from a table in LDS built per pair of subject tiles from the residual: for each group of
-// 4 subjects and each of the 256 possible packed bytes, T = sum dose * r over the group. One 8-byte
-// LDS lookup then replaces the decode and 4 multiply-adds of 4 genotypes. M_j, which involves only
-// the ~1 % of missing genotypes, comes from the SNP's list of missing subjects (built once with the
-// matrix): one gather of r per listed subject, interleaved with the table steps so that its latency
-// is hidden behind them.
+// D_j and M_j come from a table in LDS built per subject tile from the residual: for each group of
+// 4 subjects and each of the 256 possible packed bytes, (sum of dose*r, sum of missing*r). One
+// 16-byte LDS lookup then replaces the decode and 4 multiply-adds of 4 genotypes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,67 +43,102 @@ __device__ double block_sum(double x, double* sh) {
 // The gradient pass.
 //
 // The block walks its subject range two tiles (64 subjects) at a time. For each pair it builds in
-// LDS, for every 4-subject group g (8 per tile) and every packed byte value v, T = sum dose * r over
-// the group's subjects (the "Four Russians" table); each packed byte then costs one table read
-// instead of 4 decodes and multiply-adds. Table of one pair: 256 rows of 256 B; row v = two copies
-// of [tile A: 8 groups][tile B: 8 groups] x 8 B (FP64 T; FP32 T in the low half of the slot). Two
-// buffers: pair q builds into buffer q % 2; buffer 0 is LDS [0, 64 KB), buffer 1 is [64 KB, 128 KB).
-// The lookup address is one v_perm of a per-lane offset register and the packed data: byte 0 = slot
-// offset, byte 1 = packed byte value, byte 2 = buffer (buffer 1's offset registers carry a 0x01 byte
-// for it), byte 3 = 0.
+// LDS, for every 4-subject group g (8 per tile) and every packed byte value v, the sums
+// T = sum dose * r and M = sum [missing] * r over the group's subjects (the "Four Russians" table);
+// each packed byte then costs one table read instead of 4 decodes and multiply-adds. Table of one
+// pair: 256 rows of 256 B, row v = [tile A: 8 groups][tile B: 8 groups] x 16 B (FP64 (T, M)); FP32
+// rows hold two copies of [A: 8 x 8 B][B: 8 x 8 B]. Two buffers: pair q builds into buffer q % 2;
+// buffer 0 is LDS [0, 64 KB), buffer 1 is [64 KB, 128 KB). The lookup address is one v_perm of a
+// per-lane offset register and the packed data: byte 0 = slot offset, byte 1 = packed byte value,
+// byte 2 = buffer (buffer 1's offset registers carry a 0x01 byte for it), byte 3 = 0.
 //
-// Conflict-free reads: the LDS serves 32 lanes per cycle for 8-byte reads, and a 256-byte row spans
-// all 64 banks, so the bank of an entry is fixed by its slot within the row. Lane L reads, at step b
-// of a pair, copy (L / 16) % 2 of the byte at position b % 8 of its SNP's segment of tile
+// Conflict-free reads: the LDS serves 16 lanes per cycle for 16-byte reads (32 for 8-byte reads).
+// Lane L reads, at step b of a pair, the byte at position b % 8 of its SNP's segment of tile
 // (b / 8) ^ ((L / 8) % 2); by the per-SNP rotation of the layout that byte is group (b + L) % 8 of
-// that tile. So the 32 lanes served together read 32 distinct slots (copy x tile x group) for any
-// data.
-constexpr uint32_t kPassBuf1 = 65536;     // LDS offset of table buffer 1
-constexpr uint32_t kPassMissAcc = 131072;  // LDS offset of the missing-term sums [NS][1024] FP64
-constexpr size_t kPassLdsBytes = 2 * 65536 + 4 * kPassThreads * 8;
+// that tile. So among 16 lanes served together, lanes 0-7 and 8-15 read different tiles (different
+// halves of the row) and different groups within them: 16 distinct bank quads for any data.
+constexpr uint32_t kPassBuf1 = 65536;  // LDS offset of table buffer 1
+constexpr size_t kPassLdsBytes = 2 * 65536;
 
-typedef __attribute__((address_space(3))) double lds_double;
-typedef __attribute__((address_space(3))) float lds_float;
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) v2d_t lds_double2;
+typedef __attribute__((address_space(3))) v2f_t lds_float2;
 
-// slot offset inside a row: copy * 128 + tile half * 64 + group * 8
-__device__ __forceinline__ uint32_t pass_slot(int lane, int tile, int grp) {
-  return (uint32_t)(((lane >> 4) & 1) * 128 + tile * 64 + grp * 8);
-}
+template <bool F32>
+struct PassTab;
+template <>
+struct PassTab<false> {
+  // slot offset inside a row: tile half * 128 + group * 16
+  __device__ static uint32_t slot(int lane, int tile, int grp) { return (uint32_t)(tile * 128 + grp * 16); }
+};
+template <>
+struct PassTab<true> {
+  // copy (lanes 16-31 of every 32) * 128 + tile half * 64 + group * 8
+  __device__ static uint32_t slot(int lane, int tile, int grp) {
+    return (uint32_t)(((lane >> 4) & 1) * 128 + tile * 64 + grp * 8);
+  }
+};
 
 __device__ __forceinline__ double dose_of(int c) { return c == 3 ? 2.0 : (c == 2 ? 1.0 : 0.0); }
+__device__ __forceinline__ double miss_of(int c) { return c == 1 ? 1.0 : 0.0; }
 
-// Builder thread: group G = tid % 16 of the pair (tile G / 8, group G % 8) and byte values
-// v = tid / 16 + 64 m, m < 4. Codes c0, c1, c2 come from tid / 16, c3 = m. Entries sum the group's 4
-// subjects in order, T = ((d0 r0 + d1 r1) + d2 r2) + d3 r3; the part fixed by the thread is formed
-// once, so each entry costs one add, stored into both copies of its row.
-template <bool F32>
+// Builder thread (1024 or 512 per block): group G = tid % 16 of the pair (tile G / 8, group G % 8)
+// and byte values v = tid / 16 + STEP m, STEP = threads / 16 (m < 4096 / threads). Codes c0, c1 and
+// the low bit of c2 come from tid / 16, the rest from m. Entries sum the group's 4 subjects in order:
+// T = ((d0 r0 + d1 r1) + d2 r2) + d3 r3; the part fixed by the thread and the two values of the
+// c2 term are formed once, so each entry costs one add for T and one for M, stored immediately.
+template <bool F32, int THREADS>
 __device__ __forceinline__ void build_pair(uint32_t buf, int G, int vb, const double (&r)[4]) {
-  const int c0 = vb & 3, c1 = (vb >> 2) & 3, c2 = (vb >> 4) & 3;
-  const double T3 = (dose_of(c0) * r[0] + dose_of(c1) * r[1]) + dose_of(c2) * r[2];
+  static_assert(THREADS == 512 || THREADS == 1024, "builder mapping");
+  constexpr int EPT = 4096 / THREADS;
+  constexpr int STEP = THREADS / 16;
+  const int c0 = vb & 3, c1 = (vb >> 2) & 3;
+  const double T2 = dose_of(c0) * r[0] + dose_of(c1) * r[1];
+  const double M2 = miss_of(c0) * r[0] + miss_of(c1) * r[1];
+  // the two c2 values reachable from this thread (bit 4 of v is vb bit 4; bit 5 varies with m when
+  // STEP = 32, and comes from vb when STEP = 64)
+  double T3[2], M3[2];
+#pragma unroll
+  for (int hb = 0; hb < 2; ++hb) {
+    const int c2 = ((vb >> 4) & (STEP == 64 ? 3 : 1)) | (STEP == 64 ? 0 : hb << 1);
+    T3[hb] = T2 + dose_of(c2) * r[2];
+    M3[hb] = M2 + miss_of(c2) * r[2];
+  }
   const uint32_t tile = (uint32_t)(G >> 3), grp = (uint32_t)(G & 7);
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const double T = m >= 2 ? T3 + dose_of(m) * r[3] : T3;
-    const uint32_t off = buf + ((uint32_t)(vb + 64 * m) << 8) + tile * 64 + grp * 8;
+  for (int m = 0; m < EPT; ++m) {
+    const int v = vb + STEP * m;
+    const int hb = STEP == 64 ? 0 : (m & 1);
+    const int c3 = v >> 6;  // fixed per m: v = vb + STEP m with vb < STEP
+    const double T = c3 >= 2 ? T3[hb] + dose_of(c3) * r[3] : T3[hb];
+    const double M = c3 == 1 ? M3[hb] + r[3] : M3[hb];
+    const uint32_t row = buf + ((uint32_t)v << 8);
     if constexpr (F32) {
-      *reinterpret_cast<lds_float*>((size_t)off) = (float)T;
-      *reinterpret_cast<lds_float*>((size_t)(off + 128)) = (float)T;
+      const v2f_t e = {(float)T, (float)M};
+      const uint32_t off = row + tile * 64 + grp * 8;
+      *reinterpret_cast<lds_float2*>((size_t)off) = e;
+      *reinterpret_cast<lds_float2*>((size_t)(off + 128)) = e;
     } else {
-      *reinterpret_cast<lds_double*>((size_t)off) = T;
-      *reinterpret_cast<lds_double*>((size_t)(off + 128)) = T;
+      const v2d_t e = {T, M};
+      *reinterpret_cast<lds_double2*>((size_t)(row + tile * 128 + grp * 16)) = e;
     }
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
   }
 }
 
-// A lookup unit: the byte positions {c, c+4} for two consecutive c of one tile of one SNP, so a tile
-// takes two units.
-constexpr int kUnitLookups = 4;
+// A lookup unit: kUnitLookups lookups of one tile of one SNP. With 8, a unit is the whole tile
+// (steps 8 half .. 8 half + 7 of the pair); with 4 it is the byte positions {c, c+4} for two
+// consecutive c, so a tile takes two units.
+constexpr int kUnitLookups = IHT_PASS_UNIT;
 constexpr int kUnitsPerTile = 8 / kUnitLookups;
 
 template <bool F32>
 struct Unit {
   using acc_t = typename std::conditional<F32, float, double>::type;
-  acc_t t[kUnitLookups];
+  acc_t t[kUnitLookups], m[kUnitLookups];
 };
 
 // Unit `part` of tile `half`: byte positions c + 4h for c in [part * C, part * C + C), h in {0, 1},
@@ -132,10 +164,15 @@ __device__ __forceinline__ void unit_lookup(const uint32_t (&offs0)[4], const ui
         const uint32_t sel = (uint32_t)(4 + (b % 3)) | ((uint32_t)c << 8) | (7u << 16) | (0x0Cu << 24);
         addr = __builtin_amdgcn_perm(offs1[b / 3], dw, sel);
       }
-      if constexpr (F32)
-        U.t[cc + C * h] = *reinterpret_cast<const lds_float*>((size_t)addr);
-      else
-        U.t[cc + C * h] = *reinterpret_cast<const lds_double*>((size_t)addr);
+      if constexpr (F32) {
+        const v2f_t e = *reinterpret_cast<const lds_float2*>((size_t)addr);
+        U.t[cc + C * h] = e.x;
+        U.m[cc + C * h] = e.y;
+      } else {
+        const v2d_t e = *reinterpret_cast<const lds_double2*>((size_t)addr);
+        U.t[cc + C * h] = e.x;
+        U.m[cc + C * h] = e.y;
+      }
     }
   }
 }
@@ -144,43 +181,58 @@ __device__ __forceinline__ void unit_lookup(const uint32_t (&offs0)[4], const ui
 // The same pairings of byte positions are the same pairings of groups for every rotation, so the
 // tile sum depends only on the column's bytes. q[] collects the QT of a tile across its units.
 template <bool F32>
-__device__ __forceinline__ void unit_pairs(const Unit<F32>& U, int part, typename Unit<F32>::acc_t (&qt)[4]) {
+__device__ __forceinline__ void unit_pairs(const Unit<F32>& U, int part, typename Unit<F32>::acc_t (&qt)[4],
+                                           typename Unit<F32>::acc_t (&qm)[4]) {
   constexpr int C = kUnitLookups / 2;
 #pragma unroll
-  for (int cc = 0; cc < C; ++cc) qt[part * C + cc] = U.t[cc] + U.t[cc + C];
+  for (int cc = 0; cc < C; ++cc) {
+    qt[part * C + cc] = U.t[cc] + U.t[cc + C];
+    qm[part * C + cc] = U.m[cc] + U.m[cc + C];
+  }
 }
 
-// All lookups of one pair for the lane's NS SNPs, software-pipelined one unit ahead. The two tile
-// sums of a SNP are combined as acc += (A + B), which is commutative: identical columns give
-// bitwise identical gradients whichever tile a lane reads first.
+// All lookups of one pair for the lane's NS SNPs, software-pipelined over the units (kPassPipeDepth
+// units of lookups in flight ahead of the one being summed). The two tile sums of a SNP are
+// combined as acc += (A + B), which is commutative: identical columns give bitwise identical
+// gradients whichever tile a lane reads first.
 template <bool F32, int BUF, int NS>
-__device__ __forceinline__ void pair_step(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], const uint2 (&dA)[NS],
-                                          const uint2 (&dB)[NS], int hh, double (&accT)[NS]) {
+__device__ __forceinline__ void pair_step(const uint32_t (&offs0)[4], const uint32_t (&offs1)[6], const uint2 (&first)[NS],
+                                          const uint2 (&second)[NS], double (&accT)[NS], double (&accM)[NS]) {
   using acc_t = typename Unit<F32>::acc_t;
   constexpr int UPS = 2 * kUnitsPerTile;  // units per SNP
   constexpr int NU = NS * UPS;
-  Unit<F32> U[2];
-  acc_t qt[4];    // pair sums of the tile in progress
-  acc_t PT0 = 0;  // first tile's sum of the current SNP
+  constexpr int D = kPassPipeDepth;
+  Unit<F32> U[D + 1];
+  acc_t qt[4], qm[4];      // pair sums of the tile in progress
+  acc_t PT0 = 0, PM0 = 0;  // first tile's sums of the current SNP
   auto issue = [&](int u, Unit<F32>& dst) {
     const int snp = u / UPS, half = (u % UPS) / kUnitsPerTile, part = u % kUnitsPerTile;
-    // the lane reads tile B first when hh is set (half 0 = its first tile)
-    const uint2 d = (half != 0) == (hh != 0) ? dA[snp] : dB[snp];
-    unit_lookup<F32, BUF>(offs0, offs1, d, half, part, dst);
+    unit_lookup<F32, BUF>(offs0, offs1, half ? second[snp] : first[snp], half, part, dst);
   };
-  issue(0, U[0]);
+#pragma unroll
+  for (int u = 0; u < D && u < NU; ++u) issue(u, U[u]);
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
-    if (u + 1 < NU) issue(u + 1, U[(u + 1) & 1]);
+    if (u + D < NU) issue(u + D, U[(u + D) % (D + 1)]);
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
     const int snp = u / UPS, half = (u % UPS) / kUnitsPerTile, part = u % kUnitsPerTile;
-    unit_pairs<F32>(U[u & 1], part, qt);
+    unit_pairs<F32>(U[u % (D + 1)], part, qt, qm);
     if (part == kUnitsPerTile - 1) {
       const acc_t PT = (qt[0] + qt[2]) + (qt[1] + qt[3]);
-      if (half)
+      const acc_t PM = (qm[0] + qm[2]) + (qm[1] + qm[3]);
+      if (half) {
         accT[snp] += (double)PT0 + (double)PT;
-      else
+        accM[snp] += (double)PM0 + (double)PM;
+      } else {
         PT0 = PT;
+        PM0 = PM;
+      }
     }
+#if IHT_PASS_SNP_BARRIER
+    __builtin_amdgcn_sched_barrier(0);
+#endif
   }
 }
 
@@ -226,65 +278,12 @@ __global__ __launch_bounds__(1024) void k_center(const double* __restrict__ r, c
   }
 }
 
-// Missing term of the lane's SNPs: this block takes share y of `split` of each SNP's list (by
-// position; M is a plain sum). Entry e of the share has its subject index loaded at step e, its
-// residual gathered at step e + 1 and added at step e + 2 (steps: the pair iterations, then as many
-// more as the longest share needs), so no load is waited for within a step. Values past the share
-// are 0 and add nothing. The running sums live in LDS beside the tables (registers are the pass's
-// limit), at [s][thread].
-template <class IdxT, int NS>
-struct MissState {
-  uint32_t pos[NS], len[NS], idx[NS];
-  double val[NS];
-
-  __device__ __forceinline__ static lds_double* acc(int s) {
-    return reinterpret_cast<lds_double*>((size_t)(kPassMissAcc + (uint32_t)(s * kPassThreads + threadIdx.x) * 8u));
-  }
-  __device__ __forceinline__ void start(const int64_t* __restrict__ off, int64_t jb, int64_t p, int y, int split) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const int64_t j = jb + (int64_t)s * kPassThreads;
-      uint32_t a = 0, b = 0;
-      if (j < p) {
-        a = (uint32_t)off[j];
-        b = (uint32_t)off[j + 1];
-      }
-      const uint32_t n = b - a;
-      pos[s] = a + (uint32_t)(((uint64_t)n * (uint32_t)y) / (uint32_t)split);
-      len[s] = a + (uint32_t)(((uint64_t)n * (uint32_t)(y + 1)) / (uint32_t)split) - pos[s];
-      idx[s] = 0;
-      val[s] = 0.0;
-      *acc(s) = 0.0;
-    }
-  }
-  __device__ __forceinline__ double sum(int s) const { return *acc(s); }
-  __device__ __forceinline__ void step(uint32_t q, const IdxT* __restrict__ midx, const double* __restrict__ rc) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      *acc(s) += val[s];
-      const double x = rc[idx[s]];  // idx = 0 outside the share: a valid address
-      val[s] = (q >= 1 && q - 1 < len[s]) ? x : 0.0;
-      const uint32_t e = q < len[s] ? pos[s] + q : 0u;  // entry 0 exists whenever any list is loaded
-      const uint32_t ix = (uint32_t)midx[e];
-      idx[s] = q < len[s] ? ix : 0u;
-    }
-  }
-  __device__ __forceinline__ uint32_t steps_needed() const {
-    uint32_t m = 0;
-#pragma unroll
-    for (int s = 0; s < NS; ++s) m = len[s] > m ? len[s] : m;
-    return m + 2;
-  }
-};
-
-template <int NS, bool F32, class IdxT>
+template <int NS, bool F32>
 __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
                                                   int32_t tps, const double* __restrict__ rc,
                                                   const double* __restrict__ u, const double* __restrict__ v,
-                                                  const FitState* __restrict__ fs, const int64_t* __restrict__ moff,
-                                                  const IdxT* __restrict__ midx, double* __restrict__ g,
+                                                  const FitState* __restrict__ fs, double* __restrict__ g,
                                                   double2* __restrict__ partial, int64_t pst, const int32_t* __restrict__ gate) {
-  static_assert(kPassThreads == 1024, "builder mapping: 16 groups x 64 byte values per pass");
   if (gate && *gate == 0) return;
   // The kernel has no static LDS, so the dynamic allocation starts at LDS address 0: the table
   // buffers are addressed by absolute LDS offsets.
@@ -300,8 +299,6 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
   uint2 dA[2][NS], dB[2][NS];
   load_tile<NS>(dA[0], tiled, p_pad, voff, t0, t1);
   load_tile<NS>(dB[0], tiled, p_pad, voff, t0 + 1, t1);
-  MissState<IdxT, NS> ms;
-  ms.start(moff, jb, p, (int)blockIdx.y, (int)gridDim.y);
 
   // lane constants: the rotation of its SNPs (j % 8 == tid % 8) and which tile it reads first
   const int rot = tid & 7;
@@ -315,7 +312,7 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
   for (int k = 0; k < 6; ++k) offs1[k] = 0x01000000u;
 #pragma unroll
   for (int b = 0; b < 16; ++b) {
-    const uint32_t o = pass_slot(lane, (b >> 3) ^ hh, ((b & 7) + rot) & 7);
+    const uint32_t o = PassTab<F32>::slot(lane, (b >> 3) ^ hh, ((b & 7) + rot) & 7);
     offs0[b >> 2] |= o << (8 * (b & 3));
     offs1[b / 3] |= o << (8 * (b % 3));
   }
@@ -332,52 +329,55 @@ __global__ __launch_bounds__(kPassThreads, 1) void k_pass(const uint2* __restric
     rr[3] = live ? x.w : 0.0;
   };
 
-  double accT[NS];
+  double accT[NS], accM[NS];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) accT[s] = 0.0;
+  for (int s = 0; s < NS; ++s) {
+    accT[s] = 0.0;
+    accM[s] = 0.0;
+  }
   double rr[4];
   group_r(0, rr);
-  build_pair<F32>(0u, G, vb, rr);
+  build_pair<F32, kPassThreads>(0u, G, vb, rr);
   group_r(1, rr);
   __syncthreads();
 
   // Pair q uses register slot q % 2 and table buffer q % 2, both compile-time in the unrolled body.
-  // Each step loads pair q+1, builds the table of pair q+1, prefetches the residuals of pair q+2,
-  // advances the missing lists and consumes pair q. Pairs past the range (at most 1) have all-zero
-  // tables and add exact zeros.
+  // Each step loads pair q+1, builds the table of pair q+1, prefetches the residuals of pair q+2 and
+  // consumes pair q. Pairs past the range (at most 1) have all-zero tables and add exact zeros.
   const int npairs = (t1 - t0 + 1) / 2;
   const int trips = (npairs + 1) / 2;
-  uint32_t q = 0;
-  // one pair step; UU (the pair's register slot and table buffer) is a compile-time constant
-  auto pair_iter = [&](int trip, auto UU) {
-    constexpr int uu = decltype(UU)::value;
-    const int qq = trip * 2 + uu;
-    const int tn = t0 + 2 * (qq + 1);
-    load_tile<NS>(dA[uu ^ 1], tiled, p_pad, voff, tn, t1);
-    load_tile<NS>(dB[uu ^ 1], tiled, p_pad, voff, tn + 1, t1);
-    build_pair<F32>(uu ? 0u : kPassBuf1, G, vb, rr);
-    group_r(qq + 2, rr);
-    pair_step<F32, uu, NS>(offs0, offs1, dA[uu], dB[uu], hh, accT);
-    // after the lookups: its loads were issued a whole step ago
-    ms.step(q++, midx, rc);
-    __syncthreads();
-    __builtin_amdgcn_sched_barrier(0);
-  };
   for (int trip = 0; trip < trips; ++trip) {
-    pair_iter(trip, std::integral_constant<int, 0>{});
-    pair_iter(trip, std::integral_constant<int, 1>{});
+#pragma unroll
+    for (int uu = 0; uu < 2; ++uu) {
+      const int q = trip * 2 + uu;
+      const int tn = t0 + 2 * (q + 1);
+      load_tile<NS>(dA[uu ^ 1], tiled, p_pad, voff, tn, t1);
+      load_tile<NS>(dB[uu ^ 1], tiled, p_pad, voff, tn + 1, t1);
+      build_pair<F32, kPassThreads>(uu ? 0u : kPassBuf1, G, vb, rr);
+      group_r(q + 2, rr);
+      uint2 first[NS], second[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        first[s] = hh ? dB[uu][s] : dA[uu][s];
+        second[s] = hh ? dA[uu][s] : dB[uu][s];
+      }
+      if (uu == 0)
+        pair_step<F32, 0, NS>(offs0, offs1, first, second, accT, accM);
+      else
+        pair_step<F32, 1, NS>(offs0, offs1, first, second, accT, accM);
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  // the lists longer than the pair steps (rare: more than one missing entry per 64 subjects)
-  for (const uint32_t need = ms.steps_needed(); q < need; ++q) ms.step(q, midx, rc);
 
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     const int64_t j = jb + s * kPassThreads;
     if (j < p) {
       if (partial) {
-        partial[(int64_t)blockIdx.y * pst + j] = make_double2(accT[s], ms.sum(s));
+        partial[(int64_t)blockIdx.y * pst + j] = make_double2(accT[s], accM[s]);
       } else {
-        g[j] = v[j] * (accT[s] - u[j] * (fs->Rsum - ms.sum(s)));
+        g[j] = v[j] * (accT[s] - u[j] * (fs->Rsum - accM[s]));
       }
     }
   }
@@ -412,11 +412,11 @@ struct PassGeom {
 
 PassGeom pass_geometry(const Layout& L, int precision) {
   (void)precision;
-  // 4 SNPs per lane would halve the table builds per SNP but needs more registers than the 128 a
-  // 1024-thread workgroup leaves each lane once the missing lists are in flight
-  const int cand[2] = {2, 1};
+  const int cand[4] = {8, 4, 2, 1};
+  const int ncand = 4;
   PassGeom G{1, 1, (int)((L.ntiles + 1) / 2 * 2), 0};
-  for (int ci = 0; ci < 2; ++ci) {
+  G.groups = (L.p + kPassThreads - 1) / kPassThreads;
+  for (int ci = 0; ci < ncand; ++ci) {
     const int ns = cand[ci];
     if (ns > kPassMaxNS) continue;
     const int64_t groups = (L.p + (int64_t)kPassThreads * ns - 1) / ((int64_t)kPassThreads * ns);
@@ -448,6 +448,25 @@ hipError_t allow_pass_lds(const void* fn) {
   return e;
 }
 
+template <int NS, bool F32>
+hipError_t launch_pass_one(dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* rc,
+                           const double* u, const double* v, const FitState* fs, double* g, double2* partial, int64_t pst,
+                           const int32_t* gate) {
+  hipError_t e = allow_pass_lds(reinterpret_cast<const void*>(&k_pass<NS, F32>));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pass<NS, F32>), grid, dim3(kPassThreads), kPassLdsBytes, st, tiled, L.p, L.p_pad, (int32_t)L.ntiles,
+                     tps, rc, u, v, fs, g, partial, pst, gate);
+  return hipGetLastError();
+}
+
+template <int NS>
+hipError_t launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* rc,
+                          const double* u, const double* v, const FitState* fs, double* g, double2* partial, int64_t pst,
+                          const int32_t* gate) {
+  return f32 ? launch_pass_one<NS, true>(grid, st, tiled, L, tps, rc, u, v, fs, g, partial, pst, gate)
+             : launch_pass_one<NS, false>(grid, st, tiled, L, tps, rc, u, v, fs, g, partial, pst, gate);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
@@ -462,32 +481,10 @@ size_t gradient_work_bytes(const Layout& L) {
   return (size_t)L.n_pad * sizeof(double) + b;
 }
 
-template <int NS, bool F32, class IdxT>
-static hipError_t launch_pass_one(dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps, const double* rc,
-                                  const double* u, const double* v, const FitState* fs, const MissList& ML, double* g,
-                                  double2* partial, int64_t pst, const int32_t* gate) {
-  const void* fn = reinterpret_cast<const void*>(&k_pass<NS, F32, IdxT>);
-  hipError_t e = allow_pass_lds(fn);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_pass<NS, F32, IdxT>), grid, dim3(kPassThreads), kPassLdsBytes, st, tiled, L.p, L.p_pad,
-                     (int32_t)L.ntiles, tps, rc, u, v, fs, ML.off, static_cast<const IdxT*>(ML.idx), g, partial, pst, gate);
-  return hipGetLastError();
-}
-
-template <int NS>
-static hipError_t launch_pass_ns(bool f32, dim3 grid, hipStream_t st, const uint2* tiled, const Layout& L, int tps,
-                                 const double* rc, const double* u, const double* v, const FitState* fs, const MissList& ML,
-                                 double* g, double2* partial, int64_t pst, const int32_t* gate) {
-  if (ML.wide)
-    return f32 ? launch_pass_one<NS, true, uint32_t>(grid, st, tiled, L, tps, rc, u, v, fs, ML, g, partial, pst, gate)
-               : launch_pass_one<NS, false, uint32_t>(grid, st, tiled, L, tps, rc, u, v, fs, ML, g, partial, pst, gate);
-  return f32 ? launch_pass_one<NS, true, uint16_t>(grid, st, tiled, L, tps, rc, u, v, fs, ML, g, partial, pst, gate)
-             : launch_pass_one<NS, false, uint16_t>(grid, st, tiled, L, tps, rc, u, v, fs, ML, g, partial, pst, gate);
-}
-
 hipError_t launch_gradient(const uint8_t* tiled, const MissList& ML, const Layout& L, const double* r, const double* mask,
                            int64_t nT, const double* u, const double* v, FitState* fs, int precision, double* g,
                            double* work, const int32_t* gate, hipStream_t st, const double* rc_ready) {
+  (void)ML;
   const PassGeom G = pass_geometry(L, precision);
   const double* rc = rc_ready ? rc_ready : work;
   double2* part = (G.split > 1) ? reinterpret_cast<double2*>(work + L.n_pad) : nullptr;
@@ -501,10 +498,14 @@ hipError_t launch_gradient(const uint8_t* tiled, const MissList& ML, const Layou
   const bool f32 = precision == 1;
   const uint2* t4 = reinterpret_cast<const uint2*>(tiled);
   const int64_t pst = G.stride();
-  if (G.ns == 2)
-    e = launch_pass_ns<2>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, ML, g, part, pst, gate);
+  if (G.ns == 8)
+    e = launch_pass_ns<8>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, pst, gate);
+  else if (G.ns == 4)
+    e = launch_pass_ns<4>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, pst, gate);
+  else if (G.ns == 2)
+    e = launch_pass_ns<2>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, pst, gate);
   else
-    e = launch_pass_ns<1>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, ML, g, part, pst, gate);
+    e = launch_pass_ns<1>(f32, grid, st, t4, L, G.tps, rc, u, v, fs, g, part, pst, gate);
   if (e != hipSuccess) return e;
   if (part) {
     hipLaunchKernelGGL(k_pass_finalize, dim3((unsigned)((L.p + 255) / 256)), dim3(256), 0, st, part, G.split, L.p, pst, u,
