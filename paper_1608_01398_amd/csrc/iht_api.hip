@@ -90,34 +90,8 @@ int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes,
     }
     e = launch_retile(src, row_bytes, G->L, G->tiled.as<uint8_t>(), st);
     if (e != hipSuccess) { rc = hip_fail(e, "retile launch"); break; }
-    // the missing-genotype lists: counts and their prefix, then the entries
-    DevBuf scan;
-    if ((e = G->miss_off.ensure((size_t)(G->L.p_pad + 1) * 8)) != hipSuccess ||
-        (e = scan.ensure(std::max<size_t>(miss_scan_work_bytes(G->L), 8))) != hipSuccess) {
-      rc = hip_fail(e, "hipMalloc(missing lists)");
-      break;
-    }
-    e = launch_miss_count(G->tiled.as<uint8_t>(), G->L, G->miss_off.as<int64_t>(), scan.as<int64_t>(), st);
-    if (e != hipSuccess) { rc = hip_fail(e, "missing-list launch"); break; }
-    int64_t total = 0;
-    if ((e = hipMemcpyAsync(&total, G->miss_off.as<int64_t>() + G->L.p_pad, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-      rc = hip_fail(e, "retile / missing-list count");
-      break;
-    }
-    if (total >= (int64_t(1) << 32)) {  // list positions are 32-bit in the passes
-      rc = fail(IHT_EUNSUPPORTED, "iht_geno_create: more than 2^32 - 1 missing genotypes");
-      break;
-    }
-    G->miss_wide = n > 65536 ? 1 : 0;
-    if ((e = G->miss_idx.ensure((size_t)std::max<int64_t>(total, 1) * (G->miss_wide ? 4 : 2))) != hipSuccess) {
-      rc = hip_fail(e, "hipMalloc(missing lists)");
-      break;
-    }
-    e = launch_miss_fill(G->tiled.as<uint8_t>(), G->L, G->miss_off.as<int64_t>(), G->miss_idx.p, G->miss_wide, st);
-    if (e != hipSuccess) { rc = hip_fail(e, "missing-list launch"); break; }
     e = hipStreamSynchronize(st);
-    if (e != hipSuccess) { rc = hip_fail(e, "missing lists"); break; }
+    if (e != hipSuccess) { rc = hip_fail(e, "retile"); break; }
   } while (0);
   if (rc != IHT_OK) {
     delete G;
@@ -226,7 +200,7 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
   HIPCHK(G->state.ensure(sizeof(FitState)));
   HIPCHK(G->partial.ensure(gradient_work_bytes(L)));
   FitState* fs = G->state.as<FitState>();
-  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), g->miss(), L, r, s->mask, s->nT, s->u, s->v, fs,
+  HIPCHK(launch_gradient(g->tiled.as<uint8_t>(), L, r, s->mask, s->nT, s->u, s->v, fs,
                          precision, grad, G->partial.as<double>(), nullptr, st));
   return IHT_OK;
 }
@@ -535,13 +509,14 @@ int iht_cv(const iht_geno* g, const double* y, const float* Z, int32_t cz, int32
               nc ? d_bc.as<double>() : nullptr, d_trace.as<double>(), it_t.data(), st_t.data(), st};
     rc = run_fit(A);
     if (rc < 0) break;
-    // held-out errors, the MSE table and the chosen size (pageable sources: synchronous copies)
-    if ((e = hipMemcpy(d_folds.p, folds, L.n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_count.p, count.data(), (size_t)q * 8, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_ks_solve.p, kss.data(), Tz * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_ks_path.p, ks, (size_t)r * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(d_sv.p, sv.data(), Tz * sizeof(BatchSolve), hipMemcpyHostToDevice)) != hipSuccess) {
-      rc = hip_fail(e, "hipMemcpy(cv)");
+    // held-out errors, the MSE table and the chosen size; the copies go to the caller's stream and
+    // their host arrays stay alive until the stream is synchronised below
+    if ((e = hipMemcpyAsync(d_folds.p, folds, L.n, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_count.p, count.data(), (size_t)q * 8, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_ks_solve.p, kss.data(), Tz * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_ks_path.p, ks, (size_t)r * 4, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_sv.p, sv.data(), Tz * sizeof(BatchSolve), hipMemcpyHostToDevice, st)) != hipSuccess) {
+      rc = hip_fail(e, "hipMemcpyAsync(cv)");
       break;
     }
     if ((e = cv_heldout_mse(g->tiled.as<uint8_t>(), L, d_folds.as<uint8_t>(), q, r, d_sv.as<BatchSolve>(),

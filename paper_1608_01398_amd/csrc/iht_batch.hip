@@ -281,9 +281,9 @@ hipError_t launch_shape(int si, const uint8_t* tiled, const Layout& L, const int
 }
 
 // Autotuner: the first launch for a (device, tiles, padded p, padded T) shape times every block
-// shape once on the call's own inputs (HIP events on the call's stream; each run writes the same
-// G) and keeps the fastest for the rest of the process. Not while the stream is being captured
-// into a graph: the first shape is used then, untimed.
+// shape three times on the call's own inputs (HIP events on the call's stream; each run writes the
+// same G) and keeps the one of least median time for the rest of the process. Not while the
+// stream is being captured into a graph: the first shape is used then, untimed.
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int64_t, int32_t>, int> g_tuned;
 
@@ -305,20 +305,32 @@ int tuned_shape(const uint8_t* tiled, const Layout& L, const int8_t* R8, int32_t
     if (e0) (void)hipEventDestroy(e0);
     return 0;
   }
+  // one untimed run of each shape (code load, caches), then kTuneReps timed runs of each, the shapes
+  // interleaved so that clock drift falls on all of them alike; the median decides
+  constexpr int kTuneReps = 3;
+  float ms[kNumShapes][kTuneReps];
+  bool ok[kNumShapes];
+  for (int si = 0; si < kNumShapes; ++si)
+    ok[si] = launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) == hipSuccess;
+  for (int rep = 0; rep < kTuneReps; ++rep)
+    for (int si = 0; si < kNumShapes; ++si) {
+      if (!ok[si]) continue;
+      ok[si] = hipEventRecord(e0, st) == hipSuccess &&
+               launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) == hipSuccess &&
+               hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+               hipEventElapsedTime(&ms[si][rep], e0, e1) == hipSuccess;
+    }
   int best = 0;
   float best_ms = 0.0f;
+  bool have = false;
   for (int si = 0; si < kNumShapes; ++si) {
-    // one untimed run (code load, caches), then one timed run
-    if (launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) != hipSuccess) continue;
-    float ms = 0.0f;
-    if (hipEventRecord(e0, st) != hipSuccess ||
-        launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st) != hipSuccess ||
-        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-      continue;
-    if (si == 0 || ms < best_ms) {
+    if (!ok[si]) continue;
+    std::sort(ms[si], ms[si] + kTuneReps);
+    const float med = ms[si][kTuneReps / 2];
+    if (!have || med < best_ms) {
       best = si;
-      best_ms = ms;
+      best_ms = med;
+      have = true;
     }
   }
   (void)hipEventDestroy(e0);

@@ -129,111 +129,6 @@ __global__ __launch_bounds__(256) void k_stats(const uint2* __restrict__ tiled, 
 }
 
 // ------------------------------------------------------------------------------------------------
-// Missing-genotype lists (code 01 in the PLINK encoding), built once per matrix.
-
-// Missing entries of SNP j (one thread per SNP, pad SNPs count 0).
-__global__ __launch_bounds__(256) void k_miss_count(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
-                                                    int64_t* __restrict__ off) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p_pad) return;
-  int64_t c = 0;
-  if (j < p)
-    for (int64_t t = 0; t < ntiles; ++t) {
-      const uint2 d = tiled[t * p_pad + j];
-      c += __popc(d.x & ~(d.x >> 1) & 0x55555555u) + __popc(d.y & ~(d.y >> 1) & 0x55555555u);
-    }
-  off[j] = c;
-}
-
-constexpr int kScanItems = 8;                     // per thread
-constexpr int64_t kScanBlock = 1024 * kScanItems;  // entries per block (p_pad is a multiple)
-
-// Exclusive prefix of 1024 per-thread totals held by the block (sh: 1024 words).
-__device__ int64_t block_exclusive(int64_t v, int64_t* sh) {
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t x = tid >= d ? sh[tid - d] : 0;
-    __syncthreads();
-    sh[tid] += x;
-    __syncthreads();
-  }
-  const int64_t incl = sh[tid];
-  __syncthreads();
-  return incl - v;
-}
-
-// In-place exclusive prefix of each 8192-entry block; the block totals go to sums[b].
-__global__ __launch_bounds__(1024) void k_scan_local(int64_t* __restrict__ x, int64_t* __restrict__ sums) {
-  __shared__ int64_t sh[1024];
-  int64_t* b = x + (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
-  int64_t v[kScanItems], t = 0;
-#pragma unroll
-  for (int e = 0; e < kScanItems; ++e) {
-    v[e] = b[e];
-    t += v[e];
-  }
-  int64_t run = block_exclusive(t, sh);
-#pragma unroll
-  for (int e = 0; e < kScanItems; ++e) {
-    b[e] = run;
-    run += v[e];
-  }
-  if (threadIdx.x == 1023) sums[blockIdx.x] = run;
-}
-
-// Exclusive prefix of the nb block totals (one block, chunks of 1024 with a carry); the grand total
-// goes to x[p_pad].
-__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ sums, int64_t nb, int64_t* __restrict__ x,
-                                                   int64_t p_pad) {
-  __shared__ int64_t sh[1024];
-  __shared__ int64_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
-    const int64_t i = c0 + threadIdx.x;
-    const int64_t v = i < nb ? sums[i] : 0;
-    const int64_t ex = block_exclusive(v, sh);
-    const int64_t base = carry;
-    if (i < nb) sums[i] = base + ex;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry = base + ex + v;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) x[p_pad] = carry;
-}
-
-__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ x, const int64_t* __restrict__ sums, int64_t p_pad) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < p_pad) x[j] += sums[j / kScanBlock];
-}
-
-// Subject indices of SNP j's missing entries, ascending, at idx[off[j] ..). Byte b of a segment holds
-// 4-subject group (b + j) mod 8, so the groups are visited in subject order through that rotation.
-template <class IdxT>
-__global__ __launch_bounds__(256) void k_miss_fill(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int64_t ntiles,
-                                                   const int64_t* __restrict__ off, IdxT* __restrict__ idx) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p) return;
-  int64_t pos = off[j];
-  const int rot = (int)(j & (kSegBytes - 1));
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const uint2 d = tiled[t * p_pad + j];
-    const uint64_t seg = (uint64_t)d.x | ((uint64_t)d.y << 32);
-    const uint64_t mm = seg & ~(seg >> 1) & 0x5555555555555555ull;
-    if (!mm) continue;
-    for (int gq = 0; gq < 8; ++gq) {
-      const int b = (gq - rot) & (kSegBytes - 1);
-      const uint32_t byte = (uint32_t)(mm >> (8 * b)) & 0xFFu;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if ((byte >> (2 * q)) & 1u) idx[pos++] = (IdxT)(t * kTileSubjects + 4 * gq + q);
-    }
-  }
-}
-
-// ------------------------------------------------------------------------------------------------
 // Top-k of |w| with ties to the lower index (the projection of eq. ihta).
 // Level 0: 8192-bin histogram of key bits 62..50 (key = IEEE bits of |w|) -> threshold bucket.
 // Collect: keys above the bucket are selected; keys in it are candidates. The last block finds the
@@ -1081,14 +976,24 @@ __global__ __launch_bounds__(256) void k_topk_exact(TopkJob J, int64_t p) {
       const int32_t jj = __shfl(j, bl, 64);
       const double uj = sv.u[jj], vj = sv.v[jj];
       const int rot = jj & (kSegBytes - 1);
+      // lane l takes tiles l, l + 64, ...: one 8-byte segment (32 subjects) per tile; byte b of the
+      // segment holds 4-subject group (b + rot) mod 8. Subjects past n have code 0 and rc 0.
+      const uint2* seg = reinterpret_cast<const uint2*>(J.tiled) + jj;
       double a = 0.0;
-      for (int64_t i = lane; i < J.n; i += 64) {
-        const int64_t tile = i / kTileSubjects;
-        const int grp = (int)((i % kTileSubjects) >> 2);
-        const uint8_t byte = J.tiled[(tile * J.p_pad + jj) * kSegBytes + ((grp - rot) & (kSegBytes - 1))];
-        const int code = (byte >> (2 * (i & 3))) & 3;
-        const double x = code == 1 ? 0.0 : vj * ((code == 0 ? 0.0 : (double)(code - 1)) - uj);
-        a += x * rc[i];
+      for (int64_t t = lane; t < J.ntiles; t += 64) {
+        const uint2 d = seg[t * J.p_pad];
+        const double* rt = rc + t * kTileSubjects;
+#pragma unroll
+        for (int b = 0; b < kSegBytes; ++b) {
+          const uint32_t byte = ((b < 4 ? d.x : d.y) >> (8 * (b & 3))) & 0xFFu;
+          const int grp = (b + rot) & (kSegBytes - 1);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int code = (int)((byte >> (2 * q)) & 3u);
+            const double x = code == 1 ? 0.0 : vj * ((code == 0 ? 0.0 : (double)(code - 1)) - uj);
+            a += x * rt[4 * grp + q];
+          }
+        }
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
@@ -1166,35 +1071,6 @@ hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* m
   else
     hipLaunchKernelGGL(k_stats<false>, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<const uint2*>(tiled), L.p,
                        L.p_pad, L.ntiles, mask_bits, nT, u, v);
-  return hipGetLastError();
-}
-
-size_t miss_scan_work_bytes(const Layout& L) { return (size_t)(L.p_pad / kScanBlock) * sizeof(int64_t); }
-
-hipError_t launch_miss_count(const uint8_t* tiled, const Layout& L, int64_t* off, int64_t* work, hipStream_t st) {
-  const uint2* t2 = reinterpret_cast<const uint2*>(tiled);
-  hipLaunchKernelGGL(k_miss_count, dim3((unsigned)((L.p_pad + 255) / 256)), dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t nb = L.p_pad / kScanBlock;
-  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(1024), 0, st, off, work);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, work, nb, off, L.p_pad);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((L.p_pad + 255) / 256)), dim3(256), 0, st, off, work, L.p_pad);
-  return hipGetLastError();
-}
-
-hipError_t launch_miss_fill(const uint8_t* tiled, const Layout& L, const int64_t* off, void* idx, int32_t wide,
-                            hipStream_t st) {
-  const uint2* t2 = reinterpret_cast<const uint2*>(tiled);
-  const dim3 grid((unsigned)((L.p + 255) / 256));
-  if (wide)
-    hipLaunchKernelGGL(k_miss_fill<uint32_t>, grid, dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off,
-                       static_cast<uint32_t*>(idx));
-  else
-    hipLaunchKernelGGL(k_miss_fill<uint16_t>, grid, dim3(256), 0, st, t2, L.p, L.p_pad, L.ntiles, off,
-                       static_cast<uint16_t*>(idx));
   return hipGetLastError();
 }
 

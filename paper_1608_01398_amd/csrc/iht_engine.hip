@@ -212,6 +212,7 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, SolveStage* Pp, int32_t T, i
     J.ldr = L.n_pad;
     J.n = L.n;
     J.p_pad = L.p_pad;
+    J.ntiles = L.ntiles;
   }
   // every slot starts idle (not fresh, not active, not retiring)
   HIPCHK(launch_zero_u32(reinterpret_cast<uint32_t*>(Q.fs), (int64_t)(Tz * sizeof(FitState) / 4), st));
@@ -260,7 +261,7 @@ int Engine::gradient(int32_t phase) {
   for (int32_t t = 0; t < T_; ++t) {
     if (!launch_[t]) continue;
     const BatchSolve& b = sv_h_[t];
-    HIPCHK(launch_gradient(tiled, g_->miss(), L_, Q_.r + (size_t)t * L_.n_pad, b.mask, b.nT, b.u, b.v, Q_.fs + t, o_.precision,
+    HIPCHK(launch_gradient(tiled, L_, Q_.r + (size_t)t * L_.n_pad, b.mask, b.nT, b.u, b.v, Q_.fs + t, o_.precision,
                            Q_.g + (size_t)t * L_.p, W.partial.as<double>(),
                            phase == kPhaseInit ? &Q_.fs[t].fresh : &Q_.fs[t].go, st_, Q_.rc + (size_t)t * L_.n_pad));
   }

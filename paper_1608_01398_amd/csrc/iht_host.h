@@ -266,10 +266,6 @@ struct iht_geno {
   int device = 0;
   iht::Layout L{};
   iht::DevBuf tiled;
-  // missing-genotype lists (built with the layout): offsets [p_pad + 1], subject indices
-  iht::DevBuf miss_off, miss_idx;
-  int32_t miss_wide = 0;
-  iht::MissList miss() const { return iht::MissList{miss_off.as<int64_t>(), miss_idx.p, miss_wide}; }
   // scratch for iht_gradient (centred residual, partial sums, scalars) and for iht_fit
   iht::DevBuf partial, state;
   iht::SolveWork fit;

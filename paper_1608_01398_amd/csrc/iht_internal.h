@@ -151,7 +151,7 @@ struct TopkJob {
   const BatchSolve* sv;  // [rows] subject set and standardisation of each row
   const double* rc;      // row t at rc + t * ldr: the centred residual the gradient was taken at
   int64_t ldr;
-  int64_t n, p_pad;
+  int64_t n, p_pad, ntiles;
 };
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
@@ -161,22 +161,6 @@ hipError_t launch_retile(const uint8_t* raw, int64_t row_bytes, const Layout& L,
 hipError_t launch_stats(const uint8_t* tiled, const Layout& L, const uint32_t* mask_bits, int64_t nT, double* u, double* v,
                         hipStream_t st);
 
-// Missing genotypes of each SNP as a sorted list of subject indices, built once per matrix from the
-// re-tiled codes: SNP j's entries are idx[off[j] .. off[j+1]) (off: int64 [p_pad + 1]; idx: uint16 when
-// n <= 65536, else uint32). The gradient passes sum the residual over these lists for the missing
-// term instead of carrying it through the tables.
-struct MissList {
-  const int64_t* off;
-  const void* idx;
-  int32_t wide;  // 1: uint32 entries
-};
-// Pass 1: off[j] = number of missing entries of SNP j (j < p_pad), then the exclusive prefix over
-// p_pad + 1 entries (off[p_pad] = total); `work` holds miss_scan_work_bytes(L). Pass 2 (after the
-// caller has sized idx from off[p_pad]): the entries.
-size_t miss_scan_work_bytes(const Layout& L);
-hipError_t launch_miss_count(const uint8_t* tiled, const Layout& L, int64_t* off, int64_t* work, hipStream_t st);
-hipError_t launch_miss_fill(const uint8_t* tiled, const Layout& L, const int64_t* off, void* idx, int32_t wide,
-                            hipStream_t st);
 // The subject set's FP64 mask [n_pad] from its bits [ntiles] (have_bits), or both for every subject.
 hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, double* mask, hipStream_t st);
 
@@ -184,7 +168,7 @@ hipError_t launch_subject_mask(const Layout& L, bool have_bits, uint32_t* bits, 
 // residual into fs, centred residual into `work`), the pass kernel, and a finalize kernel when the
 // subjects are split over workgroups. `work` holds gradient_work_bytes(L). With rc_ready the
 // centred residual (and fs->Rsum) come from the caller and the centring kernel is skipped.
-hipError_t launch_gradient(const uint8_t* tiled, const MissList& ML, const Layout& L, const double* r, const double* mask,
+hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask,
                            int64_t nT, const double* u, const double* v, FitState* fs, int precision, double* g,
                            double* work, const int32_t* gate, hipStream_t st, const double* rc_ready = nullptr);
 size_t gradient_work_bytes(const Layout& L);

@@ -481,10 +481,9 @@ size_t gradient_work_bytes(const Layout& L) {
   return (size_t)L.n_pad * sizeof(double) + b;
 }
 
-hipError_t launch_gradient(const uint8_t* tiled, const MissList& ML, const Layout& L, const double* r, const double* mask,
+hipError_t launch_gradient(const uint8_t* tiled, const Layout& L, const double* r, const double* mask,
                            int64_t nT, const double* u, const double* v, FitState* fs, int precision, double* g,
                            double* work, const int32_t* gate, hipStream_t st, const double* rc_ready) {
-  (void)ML;
   const PassGeom G = pass_geometry(L, precision);
   const double* rc = rc_ready ? rc_ready : work;
   double2* part = (G.split > 1) ? reinterpret_cast<double2*>(work + L.n_pad) : nullptr;

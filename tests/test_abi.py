@@ -91,19 +91,27 @@ def test_oracle_builds_and_is_not_linked_by_the_library(lib_path):
 
 
 def test_workspace_bytes_host_only(lib_path):
-    """iht_workspace_bytes sizes the caller's workspace on the host (no device needed): it grows with
-    the number of solves, the model size and the matrix, the matrix-core path needs more (its residual
-    digits and scales), one fit equals a batch of one, and arguments out of range give 0."""
+    """iht_workspace_bytes sizes the caller's workspace on the host (no device needed): it grows
+    linearly with the number of solves, with the model size and (per solve) with p; the matrix-core
+    path needs more (its residual digits and scales); one fit equals a batch of one; arguments out of
+    range give 0."""
     from paper_1608_01398_amd import iht
 
     one = iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64)
     assert one > 0 and one % 256 == 0
     assert one == iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=1)
-    # beta and g (16 B per SNP), the top-k candidates (12 B per SNP) dominate at this shape
-    assert 28 * 500_000 <= one <= 28 * 500_000 + (64 << 20)
-    assert iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=8) > 7 * one
+    # per solve: beta and g (16 B per SNP) and the top-k candidates (12 B per SNP) dominate at this
+    # shape; beside them one fixed area (the split pass's partial sums) serves every solve
+    per = iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=2) - one
+    assert 28 * 500_000 <= per <= 28 * 500_000 + (4 << 20)
+    assert one >= per
+    eight = iht.workspace_bytes(5000, 500_000, 20, 1, iht.FP64, T=8)
+    assert abs(eight - one - 7 * per) <= 7 * 40 * 256  # linear in T up to the 256-byte alignment of ~40 buffers
     assert iht.workspace_bytes(5000, 500_000, 40, 1, iht.FP64) > one
-    assert iht.workspace_bytes(5000, 600_000, 20, 1, iht.FP64) > one
+    # the per-solve part grows with p (the fixed part follows the pass geometry, which p also sets)
+    per_600k = (iht.workspace_bytes(5000, 600_000, 20, 1, iht.FP64, T=2)
+                - iht.workspace_bytes(5000, 600_000, 20, 1, iht.FP64))
+    assert per_600k > per
     assert iht.workspace_bytes(5000, 500_000, 20, 1, iht.MIXED_I8) > one
     L = iht.load()
     for args in ((0, 10, 1, 1, 0), (10, 0, 1, 1, 0), (10, 10, 0, 1, 0), (10, 10, 1, -1, 0), (10, 10, 1, 65, 0)):
