@@ -171,6 +171,25 @@ int iht_stats_read(const iht_stats *s, double *u, double *v, void *stream);
 int iht_gradient(const iht_geno *g, const iht_stats *s, const double *r, double *grad, int32_t precision, void *stream);
 
 /*
+ * iht_gradient for callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and bitwise the same result,
+ * with the pass's scratch (centring scalars, centred residual, split partial sums) in one fixed
+ * array of device memory per GPU (18 MB, held until the process ends) instead of memory the handle
+ * allocates on first use. Calls nothing that allocates. The array keeps the last call's contents;
+ * every call rewrites what it reads. Calls that overlap on one GPU (other streams, other threads,
+ * other handles) race on the array and must be serialised by the caller. The current device must
+ * be the handle's.
+ *   Arguments as iht_gradient. Limit: the matrix's scratch (8 bytes per padded subject plus the
+ *   partial sums of a split pass, at most 16 MB) must fit iht_gradient_noalloc_max_bytes(): every p
+ *   with n <= 262,144. Errors: IHT_EINVAL (also past that limit, before any device work),
+ *   IHT_EDEVICE. Asynchronous, as iht_gradient.
+ */
+int iht_gradient_noalloc(const iht_geno *g, const iht_stats *s, const double *r, double *grad, int32_t precision,
+                         void *stream);
+/* Bytes of the fixed scratch available to iht_gradient_noalloc's gradient work area. */
+size_t iht_gradient_noalloc_max_bytes(void);
+
+/*
  * Batched gradient pass G_t = X_st^T r_t for T solves sharing the genotype matrix (the many traits,
  * cross-validation folds and model sizes of Methods, "Model selection"), each over its own subject
  * set and standardisation. Runs on the matrix cores: dosages and missing flags as int8 against the

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("iht_pass.hip", "iht_device.hip", "iht_batch.hip", "iht_solve.hip", "iht_engine.hip", "iht_api.hip", "iht_serve.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("iht_pass.hip", "iht_device.hip", "iht_batch.hip", "iht_solve.hip", "iht_engine.hip", "iht_api.hip", "iht_serve.hip", "iht_noalloc.hip")]
 LIB = os.path.join(HERE, "libiht.so")
 ARCH = "gfx950"
 

@@ -25,7 +25,8 @@ EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_
            "iht_stats_destroy", "iht_stats_read", "iht_gradient", "iht_gradient_batch", "iht_project",
            "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
            "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning", "iht_status_str",
-           "iht_last_error", "iht_workspace_bytes", "iht_workspace_bytes_batch")
+           "iht_last_error", "iht_workspace_bytes", "iht_workspace_bytes_batch",
+           "iht_gradient_noalloc", "iht_gradient_noalloc_max_bytes")
 
 
 class IHTError(RuntimeError):
@@ -70,6 +71,10 @@ def load():
     L.iht_stats_read.argtypes = [P, P, P, P]
     L.iht_gradient.argtypes = [P, P, P, P, I32, P]
     L.iht_gradient_batch.argtypes = [P, ctypes.POINTER(ctypes.c_void_p), I32, P, P, P]
+    L.iht_gradient_noalloc.argtypes = [P, P, P, P, I32, P]
+    L.iht_gradient_noalloc.restype = ctypes.c_int
+    L.iht_gradient_noalloc_max_bytes.argtypes = []
+    L.iht_gradient_noalloc_max_bytes.restype = ctypes.c_size_t
     L.iht_project.argtypes = [P, I64, I32, P, P, P]
     L.iht_project_hint.argtypes = [P, I64, I32, P, P, P, P]
     L.iht_fit.argtypes = [P, P, P, P, I32, I32, I32, ctypes.POINTER(Opts), P, P, P, P, ctypes.POINTER(I32), P]
@@ -245,6 +250,15 @@ def gradient(geno: Geno, stats: Stats, r, precision: int = FP64, out=None):
         out = torch.empty(geno.p, dtype=torch.float64, device=r.device)
     gp = _dev(out, torch.float64, (geno.p,), "out")
     _check(load().iht_gradient(geno._h, stats._h, rp, gp, precision, _stream()))
+    return out
+
+
+def gradient_noalloc(geno: Geno, stats: Stats, r, out, precision: int = FP64):
+    """g = X_st^T r into the preallocated `out` (iht_gradient_noalloc: the library allocates nothing)."""
+    torch = _torch()
+    rp = _dev(r, torch.float64, (geno.n,), "r")
+    gp = _dev(out, torch.float64, (geno.p,), "out")
+    _check(load().iht_gradient_noalloc(geno._h, stats._h, rp, gp, precision, _stream()))
     return out
 
 
