@@ -5,8 +5,15 @@ the per-SNP mean/precision pass over the subject set plus the IHT fit to converg
 from the packed genotypes already resident (re-tiled once) in HBM. The reported value is the
 gradient passes' algorithmic bytes (ceil(n/4) * p per pass) divided by the whole-solve wall time.
 
+Further sections on the same JSON line: the 108-solve batched layout on the same matrix (int8
+matrix cores), cross-validation, logistic IHT, the continuous-batching server on n=10,000 x
+p=1,000,000 (saturated, then Poisson streams at 0.5 / 0.8 / 1.0 of capacity), the n=20,000 x
+p=2,000,000 workload (96 batched solves against the plain FP64 loop) and the oracle on the host.
+
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32] [--seed S]
                        [--no-cpu-baseline] [--pass-reps R] [--small] [--copy-calibration]
+                       [--no-batched] [--no-serving] [--no-c5] [--serve-requests R]
+                       [--passes-only single|batched]
 """
 from __future__ import annotations
 
@@ -62,11 +69,20 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-solves section")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section (n=10,000, p=1,000,000)")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--no-c5", action="store_true", help="skip the n=20,000 x p=2,000,000 section (10 GB packed)")
+    ap.add_argument("--oracle-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--passes-only", choices=["single", "batched"], default=None,
+                    help="launch only the gradient passes of the workload (3 FP64 + 3 FP32 single-trait calls, or 3 "
+                         "matrix-core calls for 108 random residual rows) and exit: for hardware-counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also launch one fill and one device-to-device copy of the packed matrix's size, "
                          "the known-size kernels that scale the HBM byte counters")
     args = ap.parse_args()
+
+    if args.oracle_child:
+        oracle_child(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on exactly one GPU; multi-GPU runs are not part of it "
@@ -103,6 +119,23 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: fill + copy of {pass_bytes} bytes")
         del src, dst
+
+    if args.passes_only:
+        stats = iht.Stats(geno)
+        if args.passes_only == "single":
+            g = torch.empty(p, dtype=torch.float64, device="cuda")
+            for precision in (iht.FP64, iht.FP32):
+                for _ in range(3):
+                    iht.gradient(geno, stats, y, precision, out=g)
+        else:
+            T = 108
+            R = torch.randn((T, n), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+            G = torch.empty((T, p), dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                iht.gradient_batch(geno, [stats] * T, R, out=G)
+        torch.cuda.synchronize()
+        log(f"passes only ({args.passes_only}): done")
+        return
 
     def solve():
         stats = iht.Stats(geno)
@@ -197,6 +230,8 @@ def main():
         out["logistic"] = bench_logistic(args, torch, iht, synth, prob, geno)
     if not args.no_serving and not args.small:
         out["serving"] = bench_serving(args, torch, iht, synth)
+    if not args.no_c5 and not args.small:
+        out["c5"] = bench_c5(args, torch, iht, synth)
 
     if not args.no_cpu_baseline:
         from oracle import oracle
@@ -213,6 +248,16 @@ def main():
             "sample": f"one complete oracle solve of the same workload (stats + {ref['n_iter']} iterations, "
                       f"{cpasses} gradient passes) in {ct:.1f}s",
         }
+        nproc = os.cpu_count()
+        t1 = oracle_timings(args, 1)
+        tn = oracle_timings(args, cores)
+        out["cpu_baseline"]["host_cpu"] = cpu_model()
+        out["cpu_baseline"]["host_logical_cpus"] = nproc
+        out["cpu_baseline"]["timings"] = {"threads_1": t1, f"threads_{cores}": tn}
+        if t1 and tn:
+            log(f"oracle timings ({cpu_model()}, {nproc} logical CPUs): n=1000 fit {t1['c1_fit_s_median_of_5']:.3f} s "
+                f"(1 thread) / {tn['c1_fit_s_median_of_5']:.3f} s ({cores}); n=5000 x p=500,000 pass "
+                f"{t1['c2_pass_gbs']:.3f} GB/s (1 thread) / {tn['c2_pass_gbs']:.3f} GB/s ({cores})")
         same = bool(np.array_equal(gpu_support, ref["support"]))
         brel = float(np.abs(gpu_beta - ref["beta_S"]).max() / np.abs(ref["beta_S"]).max()) if same else None
         lrel = float(abs(gpu_loss - ref["loss_trace"][-1]) / abs(ref["loss_trace"][-1]))
@@ -239,6 +284,66 @@ def main():
     if "batched" in out:
         out["batched"].pop("_sample", None)
     print(json.dumps(out), flush=True)
+
+
+def time_gradient(torch, iht, geno, stats, r, reps, precision=0):
+    """Mean and per-call times (us) of back-to-back iht_gradient calls, HIP events on the launch stream."""
+    g = torch.empty(geno.p, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        iht.gradient(geno, stats, r, precision, out=g)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(stream)
+    for i in range(reps):
+        iht.gradient(geno, stats, r, precision, out=g)
+        ev[i + 1].record(stream)
+    ev[-1].synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(reps)])
+    return ev[0].elapsed_time(ev[-1]) * 1e3 / reps, per
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_child(args):
+    """Oracle timings in a process of its own (its OpenMP thread count is fixed at start): one fit on the
+    n=1000 x p=10,000 workload (median of 5 after a warm-up) and one gradient pass on n=5000 x p=500,000."""
+    from oracle import oracle
+    from paper_1608_01398_amd import synth
+
+    c1 = synth.make_problem("c1", args.seed)
+    oracle.fit(c1["bed"], c1["n"], c1["y"], c1["k"], intercept=True)
+    ts = []
+    for _ in range(5):
+        t = time.perf_counter()
+        oracle.fit(c1["bed"], c1["n"], c1["y"], c1["k"], intercept=True)
+        ts.append(time.perf_counter() - t)
+    c2 = synth.make_problem("c2", args.seed)
+    u, v = oracle.stats(c2["bed"], c2["n"])
+    t = time.perf_counter()
+    oracle.gradient(c2["bed"], c2["n"], u, v, c2["y"])
+    tp = time.perf_counter() - t
+    print(json.dumps({"c1_fit_s_median_of_5": float(np.median(ts)), "c2_pass_s": tp,
+                      "c2_pass_gbs": (c2["n"] + 3) // 4 * c2["p"] / tp / 1e9}), flush=True)
+
+
+def oracle_timings(args, threads):
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", "--seed", str(args.seed)],
+                         env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        log(f"oracle child ({threads} threads) failed: {out.stderr[-500:]}")
+        return None
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def fold_masks(n, q, seed):
@@ -313,9 +418,12 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
     e1.record(stream)
     e1.synchronize()
     bpass_ms = e0.elapsed_time(e1) / reps
-    ops = 2.0 * n * p * T * 3 * 2  # int8 multiply-adds x2: 3 residual digits x (dosage, missing flag)
+    # algorithmic work: 2 n p T s int8 operations with s = 3 residual digits (the products with the
+    # missing-genotype flags, done on the matrix cores too, are not credited)
+    ops = 2.0 * n * p * T * 3
     tops = ops / (bpass_ms * 1e-3) / 1e12
-    log(f"batched pass (T={T}): {bpass_ms * 1e3:.1f} us, {tops:.0f} TOP/s int8 ({tops / INT8_PEAK_TOPS:.1%} of peak), "
+    log(f"batched pass (T={T}): {bpass_ms * 1e3:.1f} us, {tops:.0f} TOP/s int8 credited ({tops / INT8_PEAK_TOPS:.1%} of "
+        f"peak; {2 * tops:.0f} TOP/s with the missing-flag products), "
         f"{T * pass_bytes / (bpass_ms * 1e-3) / 1e9:.0f} GB/s-equivalent of single-trait passes")
     return {
         "workload": f"{T} solves on the resident n={n} x p={p} matrix: 5 training folds x k=1..20 on one trait "
@@ -323,9 +431,9 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
         "solves": T,
         "solves_per_s": round(T / bt, 2),
         "ms_per_batch": round(bt * 1e3, 2),
-        "latency_ms_p50": round(float(np.percentile(np.asarray(times) * 1e3, 50)), 2),
-        "latency_ms_p99": round(float(np.percentile(np.asarray(times) * 1e3, 99)), 2),
-        "latency_note": "every solve of a batch completes when the call returns: solve latency = batch time",
+        "ms_per_batch_runs": [round(x * 1e3, 2) for x in times],
+        "latency_note": "every solve of a batch completes when the call returns: solve latency = batch time "
+                        "(median of the timed batches above); request latency percentiles are in the serving section",
         "plain_fp64_loop_solves_per_s": round(T / plain, 2),
         "plain_fp64_solve_latency_ms_p50": round(float(np.percentile(np.asarray(lat) * 1e3, 50)), 2),
         "plain_fp64_solve_latency_ms_p99": round(float(np.percentile(np.asarray(lat) * 1e3, 99)), 2),
@@ -340,6 +448,7 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
             "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
             "frac": round(tops / INT8_PEAK_TOPS, 4), "traffic": None, "launch_us": round(bpass_ms * 1e3, 1),
             "algorithmic_ops_per_launch": ops,
+            "ops_note": "2 n p T x 3 residual digits; the missing-flag products (another 2 n p T x 3) not credited",
         },
         "_sample": dict(t=19, mask=masks[solves[19][0]], y=traits[solves[19][1]], k=solves[19][2],
                         support=res["support"][19, :solves[19][2]].cpu().numpy(),
@@ -451,8 +560,9 @@ def serve(iht, torch, srv, reqs, subsets, pool, arrivals=None):
 def bench_serving(args, torch, iht, synth):
     """Continuous-batching server on the n=10,000 x p=1,000,000 matrix (2.5 GB resident): requests
     with their own subject subsets, 1..64 traits and k ~ U{5..50}, int8 matrix-core gradient with the
-    FP64 refinement. Saturated (every request queued at once) for solves/s, then a Poisson stream at
-    70% of that rate for latency; against a plain loop of FP64 iht_fit calls on sampled solves."""
+    FP64 iteration's decisions. Saturated (every request queued at once) for solves/s, then Poisson
+    streams at 0.5, 0.8 and 1.0 of that rate for latency; against a plain loop of FP64 iht_fit calls
+    on the first solves of the stream. Also: the single-trait gradient pass at this size."""
     t = time.time()
     prob = synth.make_problem("c4", args.seed)
     n, p = prob["n"], prob["p"]
@@ -465,6 +575,9 @@ def bench_serving(args, torch, iht, synth):
     traits = int(sum(r["T"] for r in reqs))
     log(f"serving: c4 n={n} p={p} ({n * p / 4e9:.1f} GB packed) ready in {time.time() - t:.1f}s; "
         f"{len(reqs)} requests, {traits} solves")
+    pass_us, _ = time_gradient(torch, iht, geno, iht.Stats(geno), pool[0].contiguous(), 20)
+    pass_gbs = (n + 3) // 4 * p / (pass_us * 1e-6) / 1e9
+    log(f"gradient pass at n={n} x p={p}: {pass_us:.1f} us = {pass_gbs:.0f} GB/s ({pass_gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
     slots, kmax, budget = 256, 50, 24 << 30
     srv = iht.Server(geno, slots=slots, kmax=kmax, hbm_budget=budget, precision=iht.MIXED_I8)
     info0 = srv.info()
@@ -477,7 +590,7 @@ def bench_serving(args, torch, iht, synth):
         f"p50 {np.percentile(lat_sat, 50) * 1e3:.0f} ms p99 {np.percentile(lat_sat, 99) * 1e3:.0f} ms; "
         f"{srv.info()['turns'] - info0['turns']} turns")
     # the served results of a few solves against the same solves alone (bitwise)
-    same = True
+    same, fp64_same, fp64_beta_err = True, True, 0.0
     checked = 0
     for i in (0, len(reqs) // 2, len(reqs) - 1):
         res = srv.result(ids[i])
@@ -489,17 +602,30 @@ def bench_serving(args, torch, iht, synth):
         same &= bool(torch.equal(a["support"], res["support"][j, :k]) and torch.equal(a["beta_S"], res["beta_S"][j, :k])
                      and a["n_iter"] == int(res["n_iter"][j]))
         checked += 1
-    log(f"served = alone (bitwise) on {checked} sampled solves: {same}")
-    # Poisson arrivals at 70% of the saturated request rate
-    rate = 0.7 * len(reqs) / wall
-    arr = np.cumsum(np.random.default_rng([args.seed, 78]).exponential(1.0 / rate, len(reqs)))
-    wall_p, lat_p, _ = serve(iht, torch, srv, reqs, subsets, pool, arrivals=arr)
-    log(f"serving Poisson ({rate:.1f} requests/s): {traits / wall_p:.0f} solves/s; request latency p50 "
-        f"{np.percentile(lat_p, 50) * 1e3:.0f} ms p99 {np.percentile(lat_p, 99) * 1e3:.0f} ms")
+        # the same solve in plain FP64: the served int8 solve takes the FP64 iteration's decisions
+        b = iht.fit(geno, st, pool[r["row0"] + j].contiguous(), k)
+        fp64_same &= bool(torch.equal(b["support"], res["support"][j, :k]) and b["n_iter"] == int(res["n_iter"][j]))
+        bb = b["beta_S"].cpu().numpy()
+        fp64_beta_err = max(fp64_beta_err, float(np.abs(res["beta_S"][j, :k].cpu().numpy() - bb).max() / np.abs(bb).max()))
+    log(f"served = alone (bitwise) on {checked} sampled solves: {same}; same supports and iterations as FP64: "
+        f"{fp64_same}, beta max rel err {fp64_beta_err:.1e}")
+    # Poisson arrivals at 0.5, 0.8 and 1.0 of the saturated request rate
+    sweep = []
+    for frac in (0.5, 0.8, 1.0):
+        rate = frac * len(reqs) / wall
+        arr = np.cumsum(np.random.default_rng([args.seed, 78, int(frac * 10)]).exponential(1.0 / rate, len(reqs)))
+        wall_p, lat_p, _ = serve(iht, torch, srv, reqs, subsets, pool, arrivals=arr)
+        sweep.append({"load": frac, "requests_per_s": round(rate, 2), "solves_per_s": round(traits / wall_p, 1),
+                      "latency_ms_p50": round(float(np.percentile(lat_p, 50)) * 1e3, 1),
+                      "latency_ms_p99": round(float(np.percentile(lat_p, 99)) * 1e3, 1),
+                      "latency_ms_max": round(float(lat_p.max()) * 1e3, 1)})
+        log(f"serving Poisson at {frac:.1f} x capacity ({rate:.1f} requests/s): {traits / wall_p:.0f} solves/s; "
+            f"request latency p50 {np.percentile(lat_p, 50) * 1e3:.0f} ms p99 {np.percentile(lat_p, 99) * 1e3:.0f} ms "
+            f"max {lat_p.max() * 1e3:.0f} ms")
     info = srv.info()
     srv.close()
-    # plain loop: FP64 iht_fit per solve (stats per request), on the first solves of the stream
-    sample, t_plain, done = 32, 0.0, 0
+    # plain loop: FP64 iht_fit per solve (stats per request), on the first 96 solves of the stream
+    sample, t_plain, done = 96, 0.0, 0
     for i, r in enumerate(reqs):
         if done >= sample:
             break
@@ -517,21 +643,81 @@ def bench_serving(args, torch, iht, synth):
     return {
         "workload": f"continuous-batching server, n={n} x p={p} ({n * p / 4e9:.1f} GB packed) resident; "
                     f"{len(reqs)} requests: subsets U{{2000..{n}}} subjects, 1..64 traits, k~U{{5..50}}; "
-                    f"{slots} slots, kmax {kmax}, budget {budget >> 30} GiB; int8 matrix-core gradient + FP64 polish",
+                    f"{slots} slots, kmax {kmax}, budget {budget >> 30} GiB; int8 matrix-core gradient, FP64 decisions",
         "solves": traits,
         "saturated_solves_per_s": round(sat_rate, 1),
         "saturated_latency_ms_p50": round(float(np.percentile(lat_sat, 50)) * 1e3, 1),
         "saturated_latency_ms_p99": round(float(np.percentile(lat_sat, 99)) * 1e3, 1),
-        "poisson_requests_per_s": round(rate, 2),
-        "poisson_solves_per_s": round(traits / wall_p, 1),
-        "latency_ms_p50": round(float(np.percentile(lat_p, 50)) * 1e3, 1),
-        "latency_ms_p99": round(float(np.percentile(lat_p, 99)) * 1e3, 1),
+        "poisson": sweep,
+        "latency_ms_p50": sweep[1]["latency_ms_p50"],
+        "latency_ms_p99": sweep[1]["latency_ms_p99"],
+        "latency_note": "request latency (arrival to the end of the step that wrote it out) at 0.8 x capacity",
         "plain_fp64_loop_solves_per_s": round(plain_rate, 2),
         "speedup_vs_plain_fp64_loop": round(sat_rate / plain_rate, 1),
         "served_equals_alone_bitwise_sampled": same,
+        "served_vs_fp64_sampled": {"solves": checked, "same_supports_and_iterations": fp64_same,
+                                   "beta_max_rel_err": fp64_beta_err},
+        "gradient_pass_us": round(pass_us, 1), "gradient_pass_gbs": round(pass_gbs, 1),
+        "gradient_pass_hbm_frac": round(pass_gbs / HBM_PEAK_GBS, 4),
         "server_device_bytes": info["device_bytes"],
         "pass_block_snps_autotuned": iht.batch_tuning(geno, slots),
         "stats_blocks": info["stats_blocks"],
+    }
+
+
+def bench_c5(args, torch, iht, synth):
+    """The large workload: n=20,000 x p=2,000,000 (10 GB packed), 100 causal SNPs, 5 covariates +
+    intercept unpenalised; 32 traits x k in {50, 100, 150} = 96 solves in one int8 matrix-core batch
+    against the plain FP64 iht_fit loop over the same 96 solves; the single-trait pass at this size."""
+    t = time.time()
+    prob = synth.make_problem("c5", 2)
+    n, p = prob["n"], prob["p"]
+    geno = iht.Geno(prob["bed"], n)
+    traits = [prob["y"]] + [synth.make_trait(prob["bed"], n, prob["q"], 100, (0.05, 0.3), seed=700 + e, Z=prob["Z"],
+                                             intercept=1.0)[0] for e in range(31)]
+    del prob["bed"]
+    Z = torch.from_numpy(np.ascontiguousarray(prob["Z"])).to(device="cuda", dtype=torch.float32)
+    s = iht.Stats(geno)
+    ks = [k for k in (50, 100, 150) for _ in range(32)]
+    Y = torch.from_numpy(np.stack(traits * 3)).cuda()
+    torch.cuda.synchronize()
+    log(f"c5: n={n} p={p} ({n * p / 4e9:.0f} GB packed) ready in {time.time() - t:.0f}s")
+    pass_us, _ = time_gradient(torch, iht, geno, s, Y[0].contiguous(), 10)
+    pass_gbs = (n + 3) // 4 * p / (pass_us * 1e-6) / 1e9
+    log(f"gradient pass at n={n} x p={p}: {pass_us:.1f} us = {pass_gbs:.0f} GB/s ({pass_gbs / HBM_PEAK_GBS:.1%} of HBM peak)")
+    t0 = time.perf_counter()
+    res = iht.fit_batch(geno, [s] * 96, Y, ks, Z=Z, precision=iht.MIXED_I8)
+    torch.cuda.synchronize()
+    bt = time.perf_counter() - t0
+    log(f"c5 batched: 96 solves in {bt:.2f}s ({96 / bt:.1f} solves/s), statuses "
+        f"{np.bincount(np.asarray(res['statuses']) + 4, minlength=7)[4:].tolist()}")
+    t0 = time.perf_counter()
+    same, berr, lat = 0, 0.0, []
+    for tt in range(96):
+        a = time.perf_counter()
+        r64 = iht.fit(geno, s, Y[tt].contiguous(), ks[tt], Z=Z)
+        lat.append(time.perf_counter() - a)
+        k = ks[tt]
+        ok = bool(torch.equal(r64["support"], res["support"][tt, :k])) and r64["n_iter"] == int(res["n_iter"][tt])
+        same += int(ok)
+        bb = r64["beta_S"].cpu().numpy()
+        berr = max(berr, float(np.abs(res["beta_S"][tt, :k].cpu().numpy() - bb).max() / np.abs(bb).max()))
+    plain = time.perf_counter() - t0
+    log(f"c5 plain FP64 loop: 96 solves in {plain:.2f}s ({96 / plain:.1f} solves/s); batched speedup {plain / bt:.1f}x; "
+        f"identical supports and iterations {same}/96, beta max rel err {berr:.1e}")
+    return {
+        "workload": f"n={n} x p={p} ({n * p / 4e9:.0f} GB packed), 100 causal SNPs, 5 covariates + intercept "
+                    "unpenalised; 32 traits x k in {50, 100, 150} = 96 solves, int8 matrix-core batch (FP64 "
+                    "decisions) against the plain FP64 iht_fit loop",
+        "solves": 96, "batched_s": round(bt, 3), "batched_solves_per_s": round(96 / bt, 2),
+        "plain_fp64_loop_s": round(plain, 3), "plain_fp64_loop_solves_per_s": round(96 / plain, 2),
+        "plain_fp64_solve_latency_ms_p50": round(float(np.median(lat)) * 1e3, 1),
+        "speedup_vs_plain_fp64_loop": round(plain / bt, 2),
+        "same_supports_and_iterations_as_fp64": same, "beta_max_rel_err_vs_fp64": berr,
+        "iterations_mean": round(float(np.mean(res["n_iter"])), 2),
+        "gradient_pass_us": round(pass_us, 1), "gradient_pass_gbs": round(pass_gbs, 1),
+        "gradient_pass_hbm_frac": round(pass_gbs / HBM_PEAK_GBS, 4),
+        "pass_block_snps_autotuned": iht.batch_tuning(geno, 96),
     }
 
 
