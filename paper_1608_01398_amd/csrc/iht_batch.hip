@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "iht_batch.h"
 
@@ -67,7 +68,9 @@ __device__ __forceinline__ int kpos(int s) { return (s & 16) | ((s & 3) << 2) | 
 // One block per slot: centre the slot's residual over its subject set, choose the scale, write the
 // digits and the exact digit sums. Slots at or past the live count are skipped: a matrix-core
 // column only ever meets its own digits, so their contents never reach a live slot.
-// R8 layout: [tile][digit][T_pad][32 subjects] int8.
+// R8 layout: [tile][slot block of 32][digit][half of the tile][slot in the block][16 subjects] int8:
+// the 3 KB of one tile and slot block are contiguous (one direct-to-LDS copy per digit), and in LDS
+// lane (slot, half) reads its 16 bytes at consecutive 16-byte offsets (no bank conflicts).
 __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, int64_t ldr, int64_t n, int64_t n_pad, int32_t T,
                                                 int32_t T_pad, const BatchSolve* __restrict__ sv,
                                                 const int32_t* __restrict__ slots, const int32_t* __restrict__ count,
@@ -114,7 +117,9 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
     }
 #pragma unroll
     for (int d = 0; d < kDigits; ++d) {
-      R8[(((i >> 5) * kDigits + d) * T_pad + slot) * 32 + kpos((int)(i & 31))] = (int8_t)q[d];
+      const int kp = kpos((int)(i & 31));
+      R8[((((i >> 5) * (T_pad / 32) + slot / 32) * kDigits + d) * 2 + (kp >> 4)) * 512 + (slot % 32) * 16 + (kp & 15)] =
+          (int8_t)q[d];
       sq[d] += (double)q[d];  // integer-valued, exact
     }
   }
@@ -135,37 +140,61 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
 // 0-3 of the table): code 0 -> (0, 0), 1 (missing) -> (0, 1), 2 -> (1, 0), 3 -> (2, 0).
 constexpr uint32_t kDoseBytes = 0x02010000u;
 constexpr uint32_t kMissBytes = 0x00000100u;
-constexpr int kRbStride = 48;  // bytes per slot row of a staged digit plane (32 + 16: conflict-free)
+// s_waitcnt immediates of gfx9-family targets for "at most N vector-memory operations outstanding"
+// (vmcnt bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
+constexpr int kWaitVm1 = 0x0F71;
+constexpr int kWaitVm2 = 0x0F72;
 
-// One 32-SNP group per wave: 6 accumulator tiles (96 registers) leave 128 registers per wave, so
-// 16 waves share a CU; two groups per wave (192 accumulator registers, 8 waves per CU) measured
-// 16 % slower on the 108-slot pass.
-constexpr int kGroups = 1;  // 32-SNP groups per wave (accumulators: 6 per group)
+// One 32-SNP group per wave. With one slot block its 6 accumulator tiles (96 registers) leave 128
+// registers per wave, so 16 waves share a CU; with two slot blocks (192 accumulator registers, 8
+// waves per CU) each decoded genotype operand serves twice the matrix-core work and the matrix is
+// streamed half as often.
 constexpr int kBlockSolves = 32;
 
-// Block (bx, by): SNPs [256 bx, 256 bx + 256) x slots [32 by, 32 by + 32). Wave w: SNPs
-// [256 bx + 32 kGroups w, + 32 kGroups) as kGroups groups of 32 rows, each with a dosage and a
-// missing-flag operand, times the 3 digit column tiles: 6 kGroups accumulator tiles of 32x32 int32.
-// The block shape (SNPs per block, blocks per CU) is a template parameter; the launcher picks it
-// per problem shape by timing (every shape computes the same exact sums).
-template <int kBlockSnps, int kMinBlocks>
-__global__ __launch_bounds__(64 * (kBlockSnps / (32 * kGroups)), kMinBlocks) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad, int32_t ntiles,
-                                                  const int8_t* __restrict__ R8, int32_t T, int32_t T_pad,
-                                                  const BatchSolve* __restrict__ sv, const int32_t* __restrict__ slots,
-                                                  const int32_t* __restrict__ count, const double* __restrict__ scale,
-                                                  const double* __restrict__ rsum, double* __restrict__ G, int64_t ldg) {
-  constexpr int kBlockThreads = 64 * (kBlockSnps / (32 * kGroups));
+// Block (bx, by): kBlockSnps SNPs from kBlockSnps bx x the kSB blocks of 32 slots from kSB by. Wave
+// w owns SNPs [kBlockSnps bx + 32 w, + 32) as one 32-row dosage operand and one missing-flag
+// operand, times the 3 digit column tiles of each slot block: 6 kSB accumulator tiles of 32x32
+// int32. The block shape (SNPs per block, blocks per CU, slot blocks) is a template parameter; the
+// launcher picks it per problem shape by timing (every shape computes the same exact sums).
+template <int kBlockSnps, int kMinBlocks, int kSB>
+__global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint2* __restrict__ tiled, int64_t p, int64_t p_pad,
+                                                                     int32_t ntiles, const int8_t* __restrict__ R8, int32_t T,
+                                                                     int32_t T_pad, const BatchSolve* __restrict__ sv,
+                                                                     const int32_t* __restrict__ slots,
+                                                                     const int32_t* __restrict__ count,
+                                                                     const double* __restrict__ scale,
+                                                                     const double* __restrict__ rsum, double* __restrict__ G,
+                                                                     int64_t ldg) {
+  constexpr int kWaves = kBlockSnps / 32;
   const int live = count ? *count : T;
-  if ((int)blockIdx.y * kBlockSolves >= live) return;  // no live slot in this block (uniform)
-  __shared__ __attribute__((aligned(16))) int8_t rb[2][kDigits * kBlockSolves * kRbStride];  // 2 x 4.5 KB
+  const int nsb = T_pad / kBlockSolves;
+  const int sb0 = (int)blockIdx.y * kSB;      // the block's first slot block
+  if (sb0 * kBlockSolves >= live) return;     // no live slot in this block (uniform)
+  const int nsbb = min(kSB, nsb - sb0);       // slot blocks that exist (uniform)
+  // Operands in LDS, in a ring of four tiles, copied from global memory straight into LDS (no
+  // registers) two tiles ahead: the three 1 KB digit planes of each of the block's slot blocks and
+  // the block's packed genotype segments (8 bytes per SNP, 1 KB per copy). Copy c of a tile is
+  // issued by wave c % kWaves, so a wave issues kCopies(w) copies per iteration; before the barrier
+  // that hands tile t + 1 to every wave it waits until at most this iteration's copies are
+  // outstanding (vector-memory operations complete in issue order). No register receives a global
+  // load inside the loop, and the loop is unrolled over the ring, so the ring slots are constant
+  // offsets and the compiler can see that an LDS read of slot t does not wait for the copy into
+  // slot t + 2.
+  constexpr int kRing = 4;
+  constexpr int kSegKB = kBlockSnps * 8 / 1024;  // genotype copies per tile (1 KB each)
+  constexpr int kNC = kDigits * kSB + kSegKB;    // copies per tile
+  __shared__ __attribute__((aligned(16))) int8_t rb[kRing][kSB][kDigits * 1024];
+  __shared__ __attribute__((aligned(16))) uint2 sg_lds[kRing][kBlockSnps];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int kh = lane >> 5;  // k-half: subjects 16 kh .. 16 kh + 15 of the tile
   const int col = lane & 31;
+  const int my_copies = (kNC - w + kWaves - 1) / kWaves;  // copies w, w + kWaves, ... < kNC
 
-  const int64_t j0 = (int64_t)blockIdx.x * kBlockSnps + 32 * kGroups * w;
-  const int64_t jA = j0 + col, jB = j0 + 32 + col;  // this lane's SNP in group 0 / group 1
-  const int tb = blockIdx.y * kBlockSolves;
+  const int64_t jb = (int64_t)blockIdx.x * kBlockSnps;  // the block's first SNP
+  const int64_t j0 = jb + 32 * w;
+  const int64_t jA = j0 + col;  // this lane's SNP
   // un-rotation selector: group g of the tile sits in segment byte (g - j) mod 8; this lane needs
   // groups 4 kh .. 4 kh + 3 in order (v_perm over the segment {hi dword, lo dword}).
   const uint32_t rot = (uint32_t)(jA & 7);
@@ -173,84 +202,113 @@ __global__ __launch_bounds__(64 * (kBlockSnps / (32 * kGroups)), kMinBlocks) voi
 #pragma unroll
   for (int e = 0; e < 4; ++e) sel |= ((4u * kh + e - rot) & 7u) << (8 * e);
 
-  // R digit chunk of this block for tile t: 3 x 1 KB at [(t*3 + d)*T_pad + tb][32], staged with a
-  // 48-byte row per slot
-  auto stage_r = [&](int t, int buf) {
-    if (tid < 192) {
-      const int d = tid >> 6, part = tid & 63;
-      const int4 x = *reinterpret_cast<const int4*>(R8 + (((int64_t)t * kDigits + d) * T_pad + tb) * 32 + part * 16);
-      *reinterpret_cast<int4*>(&rb[buf][d * (kBlockSolves * kRbStride) + (part >> 1) * kRbStride + (part & 1) * 16]) = x;
+  // this wave's copies of tile t into ring slot S (p_pad is a multiple of every block's SNPs)
+  auto stage = [&](int t, auto S) {
+    constexpr int slot = decltype(S)::value;
+#pragma unroll
+    for (int i = 0; i < (kNC + kWaves - 1) / kWaves; ++i) {
+      const int c = w + i * kWaves;
+      if (c < kDigits * kSB) {
+        const int sbk = c / kDigits, d = c % kDigits;
+        if (sbk < nsbb) {
+          const int8_t* src = R8 + (((int64_t)t * nsb + sb0 + sbk) * kDigits + d) * 1024 + lane * 16;
+          __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(&rb[slot][sbk][d * 1024]), 16, 0,
+                                           0);
+        }
+      } else if (c < kNC) {
+        const int part = c - kDigits * kSB;
+        const uint2* src = tiled + (int64_t)t * p_pad + jb + part * 128 + lane * 2;
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(&sg_lds[slot][part * 128]), 16, 0, 0);
+      }
     }
   };
-  auto load_seg = [&](int t, int64_t j) -> uint2 {
-    const int64_t jj = j < p_pad ? j : 0;
-    return tiled[(int64_t)t * p_pad + jj];
-  };
+  // copies this wave issued in an iteration: my_copies, less the digit copies of a missing slot block
+  int issued = 0;
+  for (int i = 0; i < my_copies; ++i) {
+    const int c = w + i * kWaves;
+    issued += (c >= kDigits * kSB || c / kDigits < nsbb) ? 1 : 0;
+  }
 
-  v16i acc[kGroups][2][kDigits];  // [snp group][dose|miss][digit]
+  v16i acc[kSB][2][kDigits];  // [slot block][dose|miss][digit]
 #pragma unroll
-  for (int h = 0; h < kGroups; ++h)
+  for (int b = 0; b < kSB; ++b)
 #pragma unroll
     for (int o = 0; o < 2; ++o)
 #pragma unroll
-      for (int d = 0; d < kDigits; ++d) acc[h][o][d] = v16i{};
+      for (int d = 0; d < kDigits; ++d) acc[b][o][d] = v16i{};
 
-  uint2 segA = load_seg(0, jA), segB = kGroups > 1 ? load_seg(0, jB) : segA;
-  stage_r(0, 0);
-  __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
-    const int buf = t & 1;
-    uint2 nA = segA, nB = segB;
-    if (t + 1 < ntiles) {
-      nA = load_seg(t + 1, jA);
-      if (kGroups > 1) nB = load_seg(t + 1, jB);
-      stage_r(t + 1, buf ^ 1);
-    }
-    // A operands: 4 packed bytes (16 subjects) of each SNP; code plane q (the q-th code of every
+  // tile t of the ring position U (t % kRing == U)
+  auto step = [&](int t, auto U) {
+    constexpr int u = decltype(U)::value;
+    const bool ahead = t + 2 < ntiles;
+    if (ahead) stage(t + 2, std::integral_constant<int, (u + 2) % kRing>{});  // slot last read two tiles ago
+    // A operands: 4 packed bytes (16 subjects) of the SNP; code plane q (the q-th code of every
     // byte) gives the dosage and flag bytes of dword q
-    v4i op[kGroups][2];
-#pragma unroll
-    for (int h = 0; h < kGroups; ++h) {
-      const uint2 sg = h ? segB : segA;
+    v4i op[2];
+    {
+      const uint2 sg = sg_lds[u][32 * w + col];
       const uint32_t g4 = __builtin_amdgcn_perm(sg.y, sg.x, sel);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t codes = (g4 >> (2 * q)) & 0x03030303u;
-        op[h][0][q] = (int32_t)__builtin_amdgcn_perm(0u, kDoseBytes, codes);
-        op[h][1][q] = (int32_t)__builtin_amdgcn_perm(0u, kMissBytes, codes);
+        op[0][q] = (int32_t)__builtin_amdgcn_perm(0u, kDoseBytes, codes);
+        op[1][q] = (int32_t)__builtin_amdgcn_perm(0u, kMissBytes, codes);
       }
     }
 #pragma unroll
-    for (int d = 0; d < kDigits; ++d) {
-      const v4i bop = *reinterpret_cast<const v4i*>(&rb[buf][d * (kBlockSolves * kRbStride) + col * kRbStride + kh * 16]);
+    for (int b = 0; b < kSB; ++b) {
+      if (b > 0 && b >= nsbb) break;  // uniform: the block's last slot block does not exist
 #pragma unroll
-      for (int h = 0; h < kGroups; ++h)
+      for (int d = 0; d < kDigits; ++d) {
+        const v4i bop = *reinterpret_cast<const v4i*>(&rb[u][b][d * 1024 + kh * 512 + col * 16]);
 #pragma unroll
-        for (int o = 0; o < 2; ++o) acc[h][o][d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(op[h][o], bop, acc[h][o][d], 0, 0, 0);
+        for (int o = 0; o < 2; ++o)
+          acc[b][o][d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(op[o], bop, acc[b][o][d], 0, 0, 0);
+      }
     }
-    __syncthreads();
-    segA = nA;
-    segB = nB;
+    if (!ahead || issued == 0)
+      __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    else if (issued == 1)
+      __builtin_amdgcn_s_waitcnt(kWaitVm1);
+    else
+      __builtin_amdgcn_s_waitcnt(kWaitVm2);
+    // LDS is the only memory the waves share in the loop: a barrier without a memory fence (the
+    // compiler barriers keep LDS accesses on their side of it)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+  };
+
+  stage(0, std::integral_constant<int, 0>{});
+  if (ntiles > 1) stage(1, std::integral_constant<int, 1>{});
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; t += kRing) {
+    step(t, std::integral_constant<int, 0>{});
+    if (t + 1 < ntiles) step(t + 1, std::integral_constant<int, 1>{});
+    if (t + 2 < ntiles) step(t + 2, std::integral_constant<int, 2>{});
+    if (t + 3 < ntiles) step(t + 3, std::integral_constant<int, 3>{});
   }
 
-  // Epilogue: column col = slot tb + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
-  const int sl = tb + col;
-  if (sl >= live) return;
-  const int t = slots ? slots[sl] : sl;
-  const double s = scale[sl], Rt = rsum[sl];
-  const double* u = sv[t].u;
-  const double* v = sv[t].v;
+  // Epilogue: column col = slot (sb0 + b) 32 + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
   const double i1 = 1.0 / kBase, i2 = 1.0 / (kBase * kBase);
 #pragma unroll
-  for (int h = 0; h < kGroups; ++h)
+  for (int b = 0; b < kSB; ++b) {
+    const int sl = (sb0 + b) * kBlockSolves + col;
+    if (sl >= live) continue;
+    const int t = slots ? slots[sl] : sl;
+    const double s = scale[sl], Rt = rsum[sl];
+    const double* u = sv[t].u;
+    const double* v = sv[t].v;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int64_t j = j0 + 32 * h + 8 * (r / 4) + 4 * kh + (r % 4);
+      const int64_t j = j0 + 8 * (r / 4) + 4 * kh + (r % 4);
       if (j >= p) continue;
-      const double A = s * (((double)acc[h][0][0][r] + (double)acc[h][0][1][r] * i1) + (double)acc[h][0][2][r] * i2);
-      const double B = s * (((double)acc[h][1][0][r] + (double)acc[h][1][1][r] * i1) + (double)acc[h][1][2][r] * i2);
+      const double A = s * (((double)acc[b][0][0][r] + (double)acc[b][0][1][r] * i1) + (double)acc[b][0][2][r] * i2);
+      const double B = s * (((double)acc[b][1][0][r] + (double)acc[b][1][1][r] * i1) + (double)acc[b][1][2][r] * i2);
       G[(int64_t)t * ldg + j] = v[j] * (A - u[j] * (Rt - B));
     }
+  }
 }
 
 }  // namespace
@@ -261,22 +319,25 @@ size_t batch_r8_bytes(const Layout& L, int32_t T) { return (size_t)L.ntiles * kD
 
 namespace {
 
-// Block shapes of k_gradB the launcher chooses from: (SNPs per block, blocks per CU).
+// Block shapes of k_gradB the launcher chooses from: (SNPs per block, blocks per CU, slot blocks).
 struct GradBShape {
   int snps;
+  int sb;
   void (*kernel)(const uint2*, int64_t, int64_t, int32_t, const int8_t*, int32_t, int32_t, const BatchSolve*,
                  const int32_t*, const int32_t*, const double*, const double*, double*, int64_t);
 };
-const GradBShape kShapes[] = {{256, &k_gradB<256, 2>}, {128, &k_gradB<128, 4>}, {512, &k_gradB<512, 1>}};
+const GradBShape kShapes[] = {{256, 1, &k_gradB<256, 2, 1>}, {128, 1, &k_gradB<128, 4, 1>}, {256, 2, &k_gradB<256, 1, 2>},
+                              {128, 2, &k_gradB<128, 2, 2>}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 hipError_t launch_shape(int si, const uint8_t* tiled, const Layout& L, const int8_t* R8, int32_t T, int32_t T_pad,
                         const BatchSolve* sv, const int32_t* slots, const int32_t* count, const double* scale,
                         const double* rsum, double* G, int64_t ldg, hipStream_t st) {
   const GradBShape& S = kShapes[si];
-  const dim3 grid((unsigned)((L.p + S.snps - 1) / S.snps), (unsigned)(T_pad / kBlockSolves));
-  hipLaunchKernelGGL(S.kernel, grid, dim3(64 * S.snps / (32 * kGroups)), 0, st, reinterpret_cast<const uint2*>(tiled), L.p,
-                     L.p_pad, (int32_t)L.ntiles, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
+  const int32_t nsb = T_pad / kBlockSolves;
+  const dim3 grid((unsigned)((L.p + S.snps - 1) / S.snps), (unsigned)((nsb + S.sb - 1) / S.sb));
+  hipLaunchKernelGGL(S.kernel, grid, dim3(2 * S.snps), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad,
+                     (int32_t)L.ntiles, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
   return hipGetLastError();
 }
 
