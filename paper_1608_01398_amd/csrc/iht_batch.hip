@@ -140,11 +140,9 @@ __global__ __launch_bounds__(1024) void k_quant(const double* __restrict__ R, in
 // 0-3 of the table): code 0 -> (0, 0), 1 (missing) -> (0, 1), 2 -> (1, 0), 3 -> (2, 0).
 constexpr uint32_t kDoseBytes = 0x02010000u;
 constexpr uint32_t kMissBytes = 0x00000100u;
-// s_waitcnt immediates of gfx9-family targets for "at most N vector-memory operations outstanding"
-// (vmcnt bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+// s_waitcnt immediate of gfx9-family targets for "no vector-memory operation outstanding" (vmcnt
+// bits 3:0 and 15:14 zero, expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
 constexpr int kWaitVm0 = 0x0F70;
-constexpr int kWaitVm1 = 0x0F71;
-constexpr int kWaitVm2 = 0x0F72;
 
 // One 32-SNP group per wave. With one slot block its 6 accumulator tiles (96 registers) leave 128
 // registers per wave, so 16 waves share a CU; with two slot blocks (192 accumulator registers, 8
@@ -173,14 +171,14 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
   if (sb0 * kBlockSolves >= live) return;     // no live slot in this block (uniform)
   const int nsbb = min(kSB, nsb - sb0);       // slot blocks that exist (uniform)
   // Operands in LDS, in a ring of four tiles, copied from global memory straight into LDS (no
-  // registers) two tiles ahead: the three 1 KB digit planes of each of the block's slot blocks and
-  // the block's packed genotype segments (8 bytes per SNP, 1 KB per copy). Copy c of a tile is
-  // issued by wave c % kWaves, so a wave issues kCopies(w) copies per iteration; before the barrier
-  // that hands tile t + 1 to every wave it waits until at most this iteration's copies are
-  // outstanding (vector-memory operations complete in issue order). No register receives a global
-  // load inside the loop, and the loop is unrolled over the ring, so the ring slots are constant
-  // offsets and the compiler can see that an LDS read of slot t does not wait for the copy into
-  // slot t + 2.
+  // registers): the three 1 KB digit planes of each of the block's slot blocks and the block's
+  // packed genotype segments (8 bytes per SNP, 1 KB per copy). Copy c of a tile is issued by wave
+  // c % kWaves. The loop takes two tiles per barrier: at the start of a step each wave issues its
+  // copies of the next two tiles (into the two slots read in the previous step), then does the
+  // matrix-core work of the current two, waits for its copies and meets the others at the barrier.
+  // No register receives a global load inside the loop, and the loop is unrolled over the ring, so
+  // the ring slots are constant offsets and the compiler can see that an LDS read of one slot does
+  // not wait for the copies into the others.
   constexpr int kRing = 4;
   constexpr int kSegKB = kBlockSnps * 8 / 1024;  // genotype copies per tile (1 KB each)
   constexpr int kNC = kDigits * kSB + kSegKB;    // copies per tile
@@ -190,7 +188,6 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
   const int lane = tid & 63, w = tid >> 6;
   const int kh = lane >> 5;  // k-half: subjects 16 kh .. 16 kh + 15 of the tile
   const int col = lane & 31;
-  const int my_copies = (kNC - w + kWaves - 1) / kWaves;  // copies w, w + kWaves, ... < kNC
 
   const int64_t jb = (int64_t)blockIdx.x * kBlockSnps;  // the block's first SNP
   const int64_t j0 = jb + 32 * w;
@@ -222,13 +219,6 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
       }
     }
   };
-  // copies this wave issued in an iteration: my_copies, less the digit copies of a missing slot block
-  int issued = 0;
-  for (int i = 0; i < my_copies; ++i) {
-    const int c = w + i * kWaves;
-    issued += (c >= kDigits * kSB || c / kDigits < nsbb) ? 1 : 0;
-  }
-
   v16i acc[kSB][2][kDigits];  // [slot block][dose|miss][digit]
 #pragma unroll
   for (int b = 0; b < kSB; ++b)
@@ -237,11 +227,9 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
 #pragma unroll
       for (int d = 0; d < kDigits; ++d) acc[b][o][d] = v16i{};
 
-  // tile t of the ring position U (t % kRing == U)
-  auto step = [&](int t, auto U) {
+  // the matrix-core work of the tile in ring slot U
+  auto compute = [&](auto U) {
     constexpr int u = decltype(U)::value;
-    const bool ahead = t + 2 < ntiles;
-    if (ahead) stage(t + 2, std::integral_constant<int, (u + 2) % kRing>{});  // slot last read two tiles ago
     // A operands: 4 packed bytes (16 subjects) of the SNP; code plane q (the q-th code of every
     // byte) gives the dosage and flag bytes of dword q
     v4i op[2];
@@ -266,12 +254,15 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
           acc[b][o][d] = __builtin_amdgcn_mfma_i32_32x32x32_i8(op[o], bop, acc[b][o][d], 0, 0, 0);
       }
     }
-    if (!ahead || issued == 0)
-      __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    else if (issued == 1)
-      __builtin_amdgcn_s_waitcnt(kWaitVm1);
-    else
-      __builtin_amdgcn_s_waitcnt(kWaitVm2);
+  };
+  // tiles t, t + 1 of the ring slots U, U + 1 (t % kRing == U), with one barrier
+  auto step = [&](int t, auto U) {
+    constexpr int u = decltype(U)::value;
+    if (t + 2 < ntiles) stage(t + 2, std::integral_constant<int, (u + 2) % kRing>{});
+    if (t + 3 < ntiles) stage(t + 3, std::integral_constant<int, (u + 3) % kRing>{});
+    compute(U);
+    if (t + 1 < ntiles) compute(std::integral_constant<int, u + 1>{});
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     // LDS is the only memory the waves share in the loop: a barrier without a memory fence (the
     // compiler barriers keep LDS accesses on their side of it)
     __asm__ volatile("" ::: "memory");
@@ -285,9 +276,7 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
   __syncthreads();
   for (int t = 0; t < ntiles; t += kRing) {
     step(t, std::integral_constant<int, 0>{});
-    if (t + 1 < ntiles) step(t + 1, std::integral_constant<int, 1>{});
     if (t + 2 < ntiles) step(t + 2, std::integral_constant<int, 2>{});
-    if (t + 3 < ntiles) step(t + 3, std::integral_constant<int, 3>{});
   }
 
   // Epilogue: column col = slot (sb0 + b) 32 + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
