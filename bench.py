@@ -427,7 +427,7 @@ def bench_batched(args, torch, iht, synth, prob, geno, y, pass_bytes):
         f"{T * pass_bytes / (bpass_ms * 1e-3) / 1e9:.0f} GB/s-equivalent of single-trait passes")
     return {
         "workload": f"{T} solves on the resident n={n} x p={p} matrix: 5 training folds x k=1..20 on one trait "
-                    "+ 8 traits at k=20 on all subjects; int8 matrix-core gradient, FP64 polish",
+                    "+ 8 traits at k=20 on all subjects; int8 matrix-core gradient, FP64 decisions",
         "solves": T,
         "solves_per_s": round(T / bt, 2),
         "ms_per_batch": round(bt * 1e3, 2),
