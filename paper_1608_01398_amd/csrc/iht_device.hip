@@ -411,6 +411,7 @@ constexpr int kLocalEPT = 8;   // entries per thread in pass 1: chunks of 8192
 constexpr int kFinalEPT = 8;   // candidates per thread in pass 2: up to 8192 per row
 constexpr int64_t kSmallChunk = 256 * kLocalEPT;   // pass-1 chunk of a 256-thread block
 constexpr int64_t kLargeChunk = 1024 * kLocalEPT;  // pass-1 chunk of a 1024-thread block
+constexpr int64_t kRankMax = 256;  // pass-2 lists ranked pairwise; longer ones by radix selection
 typedef unsigned __int128 u128;
 
 __device__ __forceinline__ u128 sel_comp(uint64_t key, int32_t idx) {
@@ -842,9 +843,11 @@ __global__ __launch_bounds__(1024) void k_topk_final(TopkJob J, int64_t p, int32
   }
   for (int q = tid; q < kLocalMaxK; q += 1024) sel[q] = 0;
   __syncthreads();
-  if (total <= 1024) {
+  if (total <= kRankMax || (total <= 1024 && total < k)) {  // (fewer than k: flagged below)
     // short lists (a warm-started projection): the exact rank of each candidate in the total order
-    // (|w| descending, index ascending) against the others in LDS; the k of rank < k are the result
+    // (|w| descending, index ascending) against the others in LDS; the k of rank < k are the result.
+    // Every thread reads the whole list, so the LDS traffic grows with its square: past kRankMax
+    // entries the radix selection below is faster (a 1000-entry list reads 12 MB of LDS on one CU).
     uint64_t* ck = reinterpret_cast<uint64_t*>(hist);  // the histogram's 8 KB hold the 1024 keys
     __shared__ int32_t cidx[1024];
     if (tid < total) {
