@@ -218,11 +218,15 @@ def test_project_all_equal_and_zeros():
 @pytest.mark.parametrize("p,k,kind", [(1000, 1, "perfect"), (100_000, 1, "random"), (100_000, 20, "perfect"),
                                       (100_000, 20, "random"), (100_000, 20, "zero"),
                                       (5000, 64, "random"), (300_000, 500, "perfect"), (40_000, 700, "random"),
-                                      (20_000, 7, "out_of_range")])
+                                      (20_000, 7, "out_of_range"), (100_000, 20, "rank250"), (100_000, 20, "rank300"),
+                                      (100_000, 20, "rank1000"), (100_000, 200, "rank900"), (100_000, 5, "rank5000")])
 def test_project_hint_parity(p, k, kind):
     """Warm-started projection: any k distinct indices give the result of the plain projection. A
     hint on an entry of value 0 makes every entry a candidate (more than fit in registers: the
-    candidates are selected from global memory); k > 512 takes the plain path."""
+    candidates are selected from global memory); k > 512 takes the plain path. "rankL": the k - 1
+    largest entries and the L-th largest, so that about L entries (more with the ties of the
+    rounded values) pass the filter: lists on both sides of the switch from pairwise ranking to
+    radix selection."""
     say(f"project_hint p={p} k={k} {kind}")
     rng = np.random.default_rng(p + 3 * k)
     w = np.round(rng.standard_normal(p), 2)
@@ -230,6 +234,9 @@ def test_project_hint_parity(p, k, kind):
     rs, ro = oracle.project(w, k)
     if kind == "perfect":
         hint = rs.copy()
+    elif kind.startswith("rank"):
+        order = np.lexsort((np.arange(p), -np.abs(w)))  # |w| descending, index ascending
+        hint = np.concatenate([order[:k - 1], [order[int(kind[4:]) - 1]]])
     elif kind == "zero":
         w[5] = 0.0
         rs, ro = oracle.project(w, k)
