@@ -229,20 +229,50 @@ __device__ __forceinline__ double decode_entry(const uint8_t* __restrict__ tiled
   return v[j] * (d - u[j]);
 }
 
-// Wide decode (grid: subjects / 256 x kmax x T) of the columns of S (which = 0, into the current
-// cache) or of S+ (which = 1, into the other cache) of the solves in `phase`.
+// Wide decode (grid: subjects / 256 x kmax / kDecodeCols x T) of the columns of S (which = 0, into
+// the current cache) or of S+ (which = 1, into the other cache) of the solves in `phase`: each
+// thread takes one subject and up to kDecodeCols columns, their loads issued together. (One column
+// per workgroup row made kmax x T rows of workgroups, most of them gated off in a server's launch,
+// and their dispatch alone cost more than the decode.)
+constexpr int kDecodeCols = 8;
 __global__ __launch_bounds__(256) void k_decode(const uint8_t* __restrict__ tiled, SolveSet Q, int32_t which, int32_t phase) {
   const int t = blockIdx.z;
   const FitState* fs = Q.fs + t;
   if (!fs_selected(fs, phase)) return;
-  const int q = blockIdx.y;
-  if (q >= Q.ks[t]) return;
+  const int q0 = blockIdx.y * kDecodeCols;
+  const int k = Q.ks[t];
+  if (q0 >= k) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Q.n_pad) return;
   const int64_t* cols = (which ? Q.Sp : Q.S) + (int64_t)t * Q.kmax;
   const int cache = which ? 1 - fs->xcur : fs->xcur;
-  double* out = Q.X + (((int64_t)t * 2 + cache) * Q.kmax + q) * Q.n_pad;
-  out[i] = decode_entry(tiled, Q.p_pad, cols[q], i, Q.sv[t].u, Q.sv[t].v, Q.sv[t].mask);
+  double* out = Q.X + ((int64_t)t * 2 + cache) * Q.kmax * Q.n_pad;
+  const BatchSolve& sv = Q.sv[t];
+  // every load first (columns past k repeat the last one), then the arithmetic: no branch between
+  // the loads, so all of them are in flight together
+  const int64_t tile = i / kTileSubjects;
+  const int grp = (int)((i % kTileSubjects) >> 2);
+  const int sh = 2 * (int)(i & 3);
+  const bool in = sv.mask[i] != 0.0;
+  int64_t j[kDecodeCols];
+  uint8_t byte[kDecodeCols];
+  double uj[kDecodeCols], vj[kDecodeCols];
+#pragma unroll
+  for (int c = 0; c < kDecodeCols; ++c) j[c] = cols[min(q0 + c, k - 1)];
+#pragma unroll
+  for (int c = 0; c < kDecodeCols; ++c) {
+    const int b = (grp - (int)(j[c] & (kSegBytes - 1))) & (kSegBytes - 1);
+    byte[c] = tiled[(tile * Q.p_pad + j[c]) * kSegBytes + b];
+    uj[c] = sv.u[j[c]];
+    vj[c] = sv.v[j[c]];
+  }
+#pragma unroll
+  for (int c = 0; c < kDecodeCols; ++c) {
+    const int code = (byte[c] >> sh) & 3;
+    const double d = (code == 0) ? 0.0 : (double)(code - 1);
+    const double x = (!in || code == 1) ? 0.0 : vj[c] * (d - uj[c]);
+    if (q0 + c < k) out[(int64_t)(q0 + c) * Q.n_pad + i] = x;
+  }
 }
 
 // ---------------------------------------------------------------------------- subject-split steps
@@ -884,7 +914,7 @@ hipError_t solve_residual0(const SolveSet& Q, hipStream_t st) {
 }
 
 hipError_t solve_decode(const uint8_t* tiled, const SolveSet& Q, int32_t which, int32_t phase, hipStream_t st) {
-  const dim3 grid((unsigned)((Q.n_pad + 255) / 256), (unsigned)Q.kmax, (unsigned)Q.T);
+  const dim3 grid((unsigned)((Q.n_pad + 255) / 256), (unsigned)((Q.kmax + kDecodeCols - 1) / kDecodeCols), (unsigned)Q.T);
   hipLaunchKernelGGL(k_decode, grid, dim3(256), 0, st, tiled, Q, which, phase);
   return hipGetLastError();
 }
