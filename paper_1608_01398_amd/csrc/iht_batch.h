@@ -17,9 +17,13 @@ int32_t batch_tuned_snps(const Layout& L, int32_t T);
 // a bound on |G_tj - (X_st^T R_t)_j| valid for every SNP j (the quantisation error of the residual,
 // summed against a standardised column: |T_t| s_t / 254^2, twice the rounding bound); with rq
 // (device, row t at rq + t * ldr, n_pad entries), the centred residual the digits were taken from.
+// With gmax (device, row t at gmax + t * batch_gmax_ld(L)), entry c of solve t's row receives the
+// largest |G_tj| over the SNPs j in [128 c, 128 c + 128) (as the integer key of the FP64 bits).
 hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
                                  const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
                                  double* rsum, double* G, int64_t ldg, hipStream_t st, FitState* fs = nullptr,
-                                 double* rq = nullptr);
+                                 double* rq = nullptr, uint64_t* gmax = nullptr);
+// Row length of the per-128-SNP maxima of launch_gradient_batch.
+inline int64_t batch_gmax_ld(const Layout& L) { return (L.p_pad + kGmaxSnps - 1) / kGmaxSnps; }
 
 }  // namespace iht

@@ -163,8 +163,9 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
                                                                      const int32_t* __restrict__ count,
                                                                      const double* __restrict__ scale,
                                                                      const double* __restrict__ rsum, double* __restrict__ G,
-                                                                     int64_t ldg) {
+                                                                     int64_t ldg, uint64_t* __restrict__ gmax, int64_t ldm) {
   constexpr int kWaves = kBlockSnps / 32;
+  static_assert(kBlockSnps % kGmaxSnps == 0, "whole 128-SNP groups per block");
   const int live = count ? *count : T;
   const int nsb = T_pad / kBlockSolves;
   const int sb0 = (int)blockIdx.y * kSB;      // the block's first slot block
@@ -280,22 +281,45 @@ __global__ __launch_bounds__(2 * kBlockSnps, kMinBlocks) void k_gradB(const uint
   }
 
   // Epilogue: column col = slot (sb0 + b) 32 + col; rows of register r: 8 (r / 4) + 4 kh + (r % 4).
+  // With gmax, the largest |G| of each 128-SNP group and slot (waves 4 g .. 4 g + 3 hold group g of
+  // the block) is left for the projection's filter, which skips the groups below its threshold.
+  __shared__ uint64_t gm[kWaves][kBlockSolves];
   const double i1 = 1.0 / kBase, i2 = 1.0 / (kBase * kBase);
 #pragma unroll
   for (int b = 0; b < kSB; ++b) {
     const int sl = (sb0 + b) * kBlockSolves + col;
-    if (sl >= live) continue;
-    const int t = slots ? slots[sl] : sl;
-    const double s = scale[sl], Rt = rsum[sl];
-    const double* u = sv[t].u;
-    const double* v = sv[t].v;
+    const bool on = sl < live;  // (false for a slot block past the last)
+    uint64_t mk = 0;
+    if (on) {
+      const int t = slots ? slots[sl] : sl;
+      const double s = scale[sl], Rt = rsum[sl];
+      const double* u = sv[t].u;
+      const double* v = sv[t].v;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t j = j0 + 8 * (r / 4) + 4 * kh + (r % 4);
-      if (j >= p) continue;
-      const double A = s * (((double)acc[b][0][0][r] + (double)acc[b][0][1][r] * i1) + (double)acc[b][0][2][r] * i2);
-      const double B = s * (((double)acc[b][1][0][r] + (double)acc[b][1][1][r] * i1) + (double)acc[b][1][2][r] * i2);
-      G[(int64_t)t * ldg + j] = v[j] * (A - u[j] * (Rt - B));
+      for (int r = 0; r < 16; ++r) {
+        const int64_t j = j0 + 8 * (r / 4) + 4 * kh + (r % 4);
+        if (j >= p) continue;
+        const double A = s * (((double)acc[b][0][0][r] + (double)acc[b][0][1][r] * i1) + (double)acc[b][0][2][r] * i2);
+        const double B = s * (((double)acc[b][1][0][r] + (double)acc[b][1][1][r] * i1) + (double)acc[b][1][2][r] * i2);
+        const double gj = v[j] * (A - u[j] * (Rt - B));
+        G[(int64_t)t * ldg + j] = gj;
+        const uint64_t key = (uint64_t)__double_as_longlong(fabs(gj));
+        mk = key > mk ? key : mk;
+      }
+    }
+    if (gmax) {  // uniform
+      const uint64_t o = __shfl_xor(mk, 32, 64);  // the other k-half of the same slot
+      mk = o > mk ? o : mk;
+      if (kh == 0) gm[w][col] = mk;
+      __syncthreads();
+      if ((w & 3) == 0 && kh == 0 && on) {
+        uint64_t m = gm[w][col];
+#pragma unroll
+        for (int x = 1; x < 4; ++x) m = gm[w + x][col] > m ? gm[w + x][col] : m;
+        const int t = slots ? slots[sl] : sl;
+        gmax[(int64_t)t * ldm + jb / kGmaxSnps + w / 4] = m;
+      }
+      __syncthreads();  // gm is reused by the next slot block
     }
   }
 }
@@ -313,7 +337,7 @@ struct GradBShape {
   int snps;
   int sb;
   void (*kernel)(const uint2*, int64_t, int64_t, int32_t, const int8_t*, int32_t, int32_t, const BatchSolve*,
-                 const int32_t*, const int32_t*, const double*, const double*, double*, int64_t);
+                 const int32_t*, const int32_t*, const double*, const double*, double*, int64_t, uint64_t*, int64_t);
 };
 const GradBShape kShapes[] = {{256, 1, &k_gradB<256, 2, 1>}, {128, 1, &k_gradB<128, 4, 1>}, {256, 2, &k_gradB<256, 1, 2>},
                               {128, 2, &k_gradB<128, 2, 2>}};
@@ -321,12 +345,12 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 hipError_t launch_shape(int si, const uint8_t* tiled, const Layout& L, const int8_t* R8, int32_t T, int32_t T_pad,
                         const BatchSolve* sv, const int32_t* slots, const int32_t* count, const double* scale,
-                        const double* rsum, double* G, int64_t ldg, hipStream_t st) {
+                        const double* rsum, double* G, int64_t ldg, hipStream_t st, uint64_t* gmax = nullptr) {
   const GradBShape& S = kShapes[si];
   const int32_t nsb = T_pad / kBlockSolves;
   const dim3 grid((unsigned)((L.p + S.snps - 1) / S.snps), (unsigned)((nsb + S.sb - 1) / S.sb));
   hipLaunchKernelGGL(S.kernel, grid, dim3(2 * S.snps), 0, st, reinterpret_cast<const uint2*>(tiled), L.p, L.p_pad,
-                     (int32_t)L.ntiles, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg);
+                     (int32_t)L.ntiles, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, gmax, batch_gmax_ld(L));
   return hipGetLastError();
 }
 
@@ -402,14 +426,15 @@ int32_t batch_tuned_snps(const Layout& L, int32_t T) {
 
 hipError_t launch_gradient_batch(const uint8_t* tiled, const Layout& L, const double* R, int64_t ldr, int32_t T,
                                  const BatchSolve* sv, const int32_t* slots, const int32_t* count, int8_t* R8, double* scale,
-                                 double* rsum, double* G, int64_t ldg, hipStream_t st, FitState* fs, double* rq) {
+                                 double* rsum, double* G, int64_t ldg, hipStream_t st, FitState* fs, double* rq,
+                                 uint64_t* gmax) {
   const int32_t T_pad = batch_t_pad(T);
   hipLaunchKernelGGL(k_quant, dim3((unsigned)T_pad), dim3(1024), 0, st, R, ldr, L.n, L.n_pad, T, T_pad, sv, slots, count, R8,
                      scale, rsum, fs, rq);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int si = tuned_shape(tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st);
-  return launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st);
+  return launch_shape(si, tiled, L, R8, T, T_pad, sv, slots, count, scale, rsum, G, ldg, st, gmax);
 }
 
 }  // namespace iht

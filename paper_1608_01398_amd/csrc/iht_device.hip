@@ -734,6 +734,27 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
     }
   }
   const int64_t base = (int64_t)blockIdx.x * kSmallChunk;
+  if (J.gmax && on_support) {
+    // the chunk's largest |g| from the gradient pass (per 128 indices): when even |mu| times it is
+    // below the threshold, no entry of the chunk can pass (the product rounds monotonically)
+    __shared__ uint64_t chunk_max;
+    const int64_t g0 = base / kGmaxSnps;
+    const int64_t ng = min((int64_t)(kSmallChunk / kGmaxSnps), (p + kGmaxSnps - 1) / kGmaxSnps - g0);
+    uint64_t m = (tid < ng) ? J.gmax[(int64_t)blockIdx.y * J.ldm + g0 + tid] : 0ull;
+    if (w == 0) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+      }
+      if (lane == 0) chunk_max = m;
+    }
+    __syncthreads();
+    if (abs_key(__dmul_rn(fabs(src.mu), key_value(chunk_max))) < tk) {
+      if (bad) atomicOr(&src.tw.state[3], 1u);
+      return;
+    }
+  }
   uint64_t key[kLocalEPT];
 #pragma unroll
   for (int e = 0; e < kLocalEPT; ++e) {

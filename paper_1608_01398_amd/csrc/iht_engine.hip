@@ -64,6 +64,7 @@ std::vector<std::pair<DevBuf*, size_t>> SolveWork::plan(const Layout& L, int32_t
     P.push_back({&slots, Tz * 4});
     P.push_back({&count, 4});
     P.push_back({&rg, Tz * L.n_pad * 8});
+    P.push_back({&gmax, Tz * (size_t)batch_gmax_ld(L) * 8});
   }
   P.push_back({&topk.small, TopkArea::small_bytes(T)});
   P.push_back({&topk.cand, TopkArea::cand_bytes(L.p, T)});
@@ -106,7 +107,7 @@ int SolveWork::provide(const Layout& L, int32_t T, int32_t kmax, int32_t nc, boo
 int64_t SolveWork::device_bytes() const {
   const DevBuf* b[] = {&beta, &g,    &partial, &r,     &rc,   &S,     &Sp,    &betap, &X,     &bc,
                        &bcp,  &gc,   &fs,      &part,  &pmu,  &ysum,  &pw,    &ks,    &sv,    &flags,
-                       &rows, &r8,   &scale,   &rsum,  &slots, &count, &rg,   &topk.small, &topk.cand};
+                       &rows, &r8,   &scale,   &rsum,  &slots, &count, &rg,   &gmax, &topk.small, &topk.cand};
   int64_t s = 0;
   for (const DevBuf* d : b) s += (int64_t)d->bytes;
   return s;
@@ -213,6 +214,8 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, SolveStage* Pp, int32_t T, i
     J.n = L.n;
     J.p_pad = L.p_pad;
     J.ntiles = L.ntiles;
+    J.gmax = W.gmax.as<uint64_t>();
+    J.ldm = batch_gmax_ld(L);
   }
   // every slot starts idle (not fresh, not active, not retiring)
   HIPCHK(launch_zero_u32(reinterpret_cast<uint32_t*>(Q.fs), (int64_t)(Tz * sizeof(FitState) / 4), st));
@@ -253,7 +256,7 @@ int Engine::gradient(int32_t phase) {
     HIPCHK(solve_slots(Q_.fs, T_, phase, W.slots.as<int32_t>(), W.count.as<int32_t>(), st_));
     HIPCHK(launch_gradient_batch(tiled, L_, Q_.r, L_.n_pad, T_, Q_.sv, W.slots.as<int32_t>(), W.count.as<int32_t>(),
                                  W.r8.as<int8_t>(), W.scale.as<double>(), W.rsum.as<double>(), Q_.g, L_.p, st_, Q_.fs,
-                                 W.rg.as<double>()));
+                                 W.rg.as<double>(), W.gmax.as<uint64_t>()));
     // the accepted proposals' own entries exactly (the initial support is certified by its projection)
     if (phase == kPhaseGo) HIPCHK(solve_exact_support(Q_, W.rg.as<double>(), st_));
     return IHT_OK;

@@ -153,6 +153,7 @@ struct TopkArea {
 struct SolveWork {
   DevBuf beta, g, partial, r, rc, S, Sp, betap, X, bc, bcp, gc, fs, part, pmu, ysum, pw, ks, sv, flags, rows;
   DevBuf r8, scale, rsum, slots, count, rg;  // matrix-core pass work; rg: centred residual of each slot's gradient
+  DevBuf gmax;  // matrix-core pass: largest |g| per 128 SNPs of each slot's gradient (the filter skips below it)
   TopkArea topk;
 
   // Every device buffer of T slots with model sizes up to kmax and nc unpenalised columns, with its

@@ -152,7 +152,13 @@ struct TopkJob {
   const double* rc;      // row t at rc + t * ldr: the centred residual the gradient was taken at
   int64_t ldr;
   int64_t n, p_pad, ntiles;
+  // Optional (rows with beta): gmax + t * ldm holds the largest |g_j| of each 128 indices of row t as
+  // the gradient pass left it (integer keys of the FP64 bits); the filter skips every 2048-entry
+  // chunk whose largest |mu g| is below its threshold.
+  const uint64_t* gmax;
+  int64_t ldm;
 };
+constexpr int kGmaxSnps = 128;  // indices per entry of TopkJob::gmax
 
 // ---- launchers (all asynchronous on `st`; return hipSuccess or the launch error) ----
 
