@@ -676,7 +676,7 @@ __global__ __launch_bounds__(1024) void k_topk_bound(TopkJob J, int64_t p) {
 // indices is at most the k-th largest key, so every entry at or above it is a candidate (a superset
 // of the k first, ties included); for a solver row the tighter bound of k_topk_bound is used. Each wave appends its candidates to the row's list with one atomic add;
 // the order of the list does not matter to pass 2.
-__global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
+__global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p, int32_t cpb) {
   TopkRow src;
   if (!topk_row(J, blockIdx.y, src)) return;
   __shared__ uint64_t shk[4];
@@ -733,54 +733,51 @@ __global__ __launch_bounds__(256) void k_topk_filter(TopkJob J, int64_t p) {
       append(q < src.k, abs_key(v), q < src.k ? prev[q] : 0);
     }
   }
-  const int64_t base = (int64_t)blockIdx.x * kSmallChunk;
-  if (J.gmax && on_support) {
-    // the chunk's largest |g| from the gradient pass (per 128 indices): when even |mu| times it is
-    // below the threshold, no entry of the chunk can pass (the product rounds monotonically)
-    __shared__ uint64_t chunk_max;
-    const int64_t g0 = base / kGmaxSnps;
-    const int64_t ng = min((int64_t)(kSmallChunk / kGmaxSnps), (p + kGmaxSnps - 1) / kGmaxSnps - g0);
-    uint64_t m = (tid < ng) ? J.gmax[(int64_t)blockIdx.y * J.ldm + g0 + tid] : 0ull;
-    if (w == 0) {
+  // chunks blockIdx.x * cpb .. + cpb - 1 of 2048 entries
+  for (int cb = 0; cb < cpb; ++cb) {
+    const int64_t base = ((int64_t)blockIdx.x * cpb + cb) * kSmallChunk;
+    if (base >= p) break;  // uniform
+    if (J.gmax && on_support) {
+      // the chunk's largest |g| from the gradient pass (per 128 indices; each wave reads them):
+      // when even |mu| times it is below the threshold, no entry of the chunk can pass (the FP64
+      // product rounds monotonically)
+      const int64_t g0 = base / kGmaxSnps;
+      const int64_t ng = min((int64_t)(kSmallChunk / kGmaxSnps), (p + kGmaxSnps - 1) / kGmaxSnps - g0);
+      uint64_t m = (lane < ng) ? J.gmax[(int64_t)blockIdx.y * J.ldm + g0 + lane] : 0ull;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const uint64_t o = __shfl_xor(m, off, 64);
         m = o > m ? o : m;
       }
-      if (lane == 0) chunk_max = m;
+      if (abs_key(__dmul_rn(fabs(src.mu), key_value(m))) < tk) continue;  // uniform
     }
-    __syncthreads();
-    if (abs_key(__dmul_rn(fabs(src.mu), key_value(chunk_max))) < tk) {
-      if (bad) atomicOr(&src.tw.state[3], 1u);
-      return;
-    }
-  }
-  uint64_t key[kLocalEPT];
+    uint64_t key[kLocalEPT];
 #pragma unroll
-  for (int e = 0; e < kLocalEPT; ++e) {
-    const int64_t j = base + (int64_t)e * 256 + tid;
-    const double v = j < p ? (on_support ? __dmul_rn(src.mu, src.g[j]) : src.at(j)) : 0.0;
-    bad |= !isfinite(v);
-    key[e] = abs_key(v);
+    for (int e = 0; e < kLocalEPT; ++e) {
+      const int64_t j = base + (int64_t)e * 256 + tid;
+      const double v = j < p ? (on_support ? __dmul_rn(src.mu, src.g[j]) : src.at(j)) : 0.0;
+      bad |= !isfinite(v);
+      key[e] = abs_key(v);
+    }
+#pragma unroll
+    for (int e = 0; e < kLocalEPT; ++e) {
+      const int64_t j = base + (int64_t)e * 256 + tid;
+      bool in = j < p && key[e] >= tk;
+      if (in && on_support) {  // rare: only entries at or above the bound search the support
+        int lo = 0, hi = src.k;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (prev[mid] < j)
+            lo = mid + 1;
+          else
+            hi = mid;
+        }
+        in = !(lo < src.k && prev[lo] == j);
+      }
+      append(in, key[e], j);
+    }
   }
   if (bad) atomicOr(&src.tw.state[3], 1u);
-#pragma unroll
-  for (int e = 0; e < kLocalEPT; ++e) {
-    const int64_t j = base + (int64_t)e * 256 + tid;
-    bool in = j < p && key[e] >= tk;
-    if (in && on_support) {  // rare: only entries at or above the bound search the support
-      int lo = 0, hi = src.k;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (prev[mid] < j)
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
-      in = !(lo < src.k && prev[lo] == j);
-    }
-    append(in, key[e], j);
-  }
 }
 
 // Radix select, by one block, of the k first of n candidates held in global memory (the same
@@ -1106,8 +1103,13 @@ hipError_t launch_topk(const TopkJob& J, int64_t p, int32_t rows, hipStream_t st
   const int64_t nb_l = (p + kLargeChunk - 1) / kLargeChunk;
   // A certified row's filtered list is selected from twice: first by the approximate values, then,
   // after k_topk_exact has made the entries near the k-th largest exact, by those.
+  // chunks per filter block: one while the launch has at most 8192 blocks, else enough (up to 8) to
+  // keep it near that; most blocks of a many-row launch read little (the summary skip) or nothing
+  // (gated rows), and their dispatch alone costs time
+  const int64_t cpb = std::min<int64_t>(8, std::max<int64_t>(1, (nb_s * rows + 8191) / 8192));
   auto filter_final = [&](const TopkJob& Jf) -> hipError_t {
-    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)nb_s, (unsigned)rows), dim3(256), 0, st, Jf, p);
+    hipLaunchKernelGGL(k_topk_filter, dim3((unsigned)((nb_s + cpb - 1) / cpb), (unsigned)rows), dim3(256), 0, st, Jf, p,
+                       (int32_t)cpb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_topk_final, dim3((unsigned)rows), dim3(1024), 0, st, Jf, p, 0, Jf.certify);
