@@ -142,6 +142,20 @@ size_t iht_workspace_bytes_batch(int64_t n, int64_t p, int32_t T, int32_t kmax, 
  * Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. The stream is synchronised before returning.
  */
 int iht_geno_create(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, int32_t flags, void *stream, iht_geno **out);
+/*
+ * The same with device memory the caller owns (for callers whose allocator owns every device
+ * buffer, e.g. PyTorch's): bed is device memory ([p][row_bytes]), and the re-tiled matrix is written
+ * into dst, at least iht_geno_bytes(n, p) bytes of device memory, 256-byte aligned. The handle
+ * borrows dst: creating it allocates no device memory, iht_geno_destroy leaves dst to the caller,
+ * and the caller keeps dst alive and unmodified while the handle lives. The work areas that later
+ * calls on the handle allocate on first use (iht_fit's solve state without a workspace, the scratch
+ * of iht_gradient and iht_gradient_batch) are the handle's own as with iht_geno_create;
+ * iht_gradient_noalloc and iht_fit with a workspace need none.
+ * Errors: IHT_EINVAL (also dst NULL, misaligned or too small), IHT_EDEVICE. Stream synchronised.
+ */
+uint64_t iht_geno_bytes(int64_t n, int64_t p); /* 0 for n or p out of range */
+int iht_geno_create_in(const uint8_t *bed, int64_t n, int64_t p, int64_t row_bytes, void *dst, uint64_t dst_bytes,
+                       void *stream, iht_geno **out);
 int iht_geno_destroy(iht_geno *g);
 /* n, p of a handle (either output may be NULL). */
 int iht_geno_shape(const iht_geno *g, int64_t *n, int64_t *p);
@@ -155,6 +169,15 @@ int iht_geno_shape(const iht_geno *g, int64_t *n, int64_t *p);
  * so u and v are bitwise reproducible. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE.
  */
 int iht_stats_create(const iht_geno *g, const uint8_t *subset, void *stream, iht_stats **out);
+/*
+ * The same in device memory the caller owns: u, v, the subject mask and bits are written into dst,
+ * at least iht_stats_bytes(g) bytes, 256-byte aligned, which the handle borrows (no device
+ * allocation; iht_stats_destroy leaves dst to the caller, who keeps it alive and unmodified while
+ * the handle lives). Errors as iht_stats_create, plus IHT_EINVAL for dst NULL, misaligned or too small.
+ */
+uint64_t iht_stats_bytes(const iht_geno *g); /* 0 for a NULL handle */
+int iht_stats_create_in(const iht_geno *g, const uint8_t *subset, void *dst, uint64_t dst_bytes, void *stream,
+                        iht_stats **out);
 int iht_stats_destroy(iht_stats *s);
 /* Copy u and v (device pointers, p doubles each; either may be NULL) out of a stats handle. */
 int iht_stats_read(const iht_stats *s, double *u, double *v, void *stream);

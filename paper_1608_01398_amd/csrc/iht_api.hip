@@ -60,25 +60,44 @@ const char* iht_status_str(int s) {
   }
 }
 
-int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes, int32_t flags, void* stream, iht_geno** out) {
-  if (!out) return fail(IHT_EINVAL, "iht_geno_create: out is NULL");
+}  // extern "C"
+
+namespace {
+
+size_t tiled_bytes_of(const Layout& L) { return (size_t)L.ntiles * (size_t)L.p_pad * kSegBytes; }
+
+// iht_geno_create and iht_geno_create_in: the re-tiled matrix in memory of the handle's own, or in
+// the caller's dst (borrowed) when dst is not NULL.
+int geno_make(const char* who, const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes, int32_t flags, void* dst,
+              uint64_t dst_bytes, void* stream, iht_geno** out) {
+  if (!out) return fail(IHT_EINVAL, std::string(who) + ": out is NULL");
   *out = nullptr;
-  if (!bed) return fail(IHT_EINVAL, "iht_geno_create: bed is NULL");
+  if (!bed) return fail(IHT_EINVAL, std::string(who) + ": bed is NULL");
   if (n < 1 || p < 1 || n > (int64_t(1) << 24) || p > (int64_t(1) << 28) - kSnpAlign)
-    return fail(IHT_EINVAL, "iht_geno_create: n or p out of range");
-  if (row_bytes < (n + 3) / 4) return fail(IHT_EINVAL, "iht_geno_create: row_bytes < ceil(n/4)");
-  if (flags != IHT_HOST_PTR && flags != IHT_DEVICE_PTR) return fail(IHT_EINVAL, "iht_geno_create: bad flags");
+    return fail(IHT_EINVAL, std::string(who) + ": n or p out of range");
+  if (row_bytes < (n + 3) / 4) return fail(IHT_EINVAL, std::string(who) + ": row_bytes < ceil(n/4)");
+  if (flags != IHT_HOST_PTR && flags != IHT_DEVICE_PTR) return fail(IHT_EINVAL, std::string(who) + ": bad flags");
+  const Layout L0 = make_layout(n, p);
+  if (dst) {
+    if ((reinterpret_cast<uintptr_t>(dst) & 255u) != 0) return fail(IHT_EINVAL, std::string(who) + ": dst not 256-byte aligned");
+    if (dst_bytes < tiled_bytes_of(L0))
+      return fail(IHT_EINVAL, std::string(who) + ": dst holds " + std::to_string(dst_bytes) + " bytes, the matrix needs " +
+                                  std::to_string(tiled_bytes_of(L0)));
+  }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   iht_geno* G = new (std::nothrow) iht_geno();
-  if (!G) return fail(IHT_ENOMEM, "iht_geno_create: host allocation");
+  if (!G) return fail(IHT_ENOMEM, std::string(who) + ": host allocation");
   int rc = IHT_OK;
   do {
     hipError_t e = hipGetDevice(&G->device);
     if (e != hipSuccess) { rc = hip_fail(e, "hipGetDevice"); break; }
-    G->L = make_layout(n, p);
-    const size_t tiled_bytes = (size_t)G->L.ntiles * (size_t)G->L.p_pad * kSegBytes;
-    e = G->tiled.ensure(tiled_bytes);
-    if (e != hipSuccess) { rc = hip_fail(e, "hipMalloc(tiled)"); break; }
+    G->L = L0;
+    if (dst) {
+      G->tiled.borrow(dst, tiled_bytes_of(G->L));
+    } else {
+      e = G->tiled.ensure(tiled_bytes_of(G->L));
+      if (e != hipSuccess) { rc = hip_fail(e, "hipMalloc(tiled)"); break; }
+    }
     const uint8_t* src = bed;
     DevBuf staging;
     if (flags == IHT_HOST_PTR) {
@@ -101,6 +120,28 @@ int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes,
   return IHT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int iht_geno_create(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes, int32_t flags, void* stream, iht_geno** out) {
+  return geno_make("iht_geno_create", bed, n, p, row_bytes, flags, nullptr, 0, stream, out);
+}
+
+uint64_t iht_geno_bytes(int64_t n, int64_t p) {
+  if (n < 1 || p < 1 || n > (int64_t(1) << 24) || p > (int64_t(1) << 28) - kSnpAlign) return 0;
+  return tiled_bytes_of(make_layout(n, p));
+}
+
+int iht_geno_create_in(const uint8_t* bed, int64_t n, int64_t p, int64_t row_bytes, void* dst, uint64_t dst_bytes,
+                       void* stream, iht_geno** out) {
+  if (!dst) {
+    if (out) *out = nullptr;
+    return fail(IHT_EINVAL, "iht_geno_create_in: dst is NULL");
+  }
+  return geno_make("iht_geno_create_in", bed, n, p, row_bytes, IHT_DEVICE_PTR, dst, dst_bytes, stream, out);
+}
+
 int iht_geno_destroy(iht_geno* g) {
   delete g;
   return IHT_OK;
@@ -113,11 +154,27 @@ int iht_geno_shape(const iht_geno* g, int64_t* n, int64_t* p) {
   return IHT_OK;
 }
 
-int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht_stats** out) {
-  if (!out) return fail(IHT_EINVAL, "iht_stats_create: out is NULL");
+}  // extern "C"
+
+namespace {
+
+// u [p], v [p], the FP64 subject mask [n_pad], then the subject bits [ntiles]
+size_t stats_bytes_of(const Layout& L) { return (size_t)(2 * L.p + L.n_pad) * 8 + (size_t)L.ntiles * 4; }
+
+// iht_stats_create and iht_stats_create_in: the statistics in memory of the handle's own, or in the
+// caller's dst (borrowed) when dst is not NULL.
+int stats_make(const char* who, const iht_geno* g, const uint8_t* subset, void* dst, uint64_t dst_bytes, void* stream,
+               iht_stats** out) {
+  if (!out) return fail(IHT_EINVAL, std::string(who) + ": out is NULL");
   *out = nullptr;
-  if (!g) return fail(IHT_EINVAL, "iht_stats_create: NULL geno");
+  if (!g) return fail(IHT_EINVAL, std::string(who) + ": NULL geno");
   const Layout& L = g->L;
+  if (dst) {
+    if ((reinterpret_cast<uintptr_t>(dst) & 255u) != 0) return fail(IHT_EINVAL, std::string(who) + ": dst not 256-byte aligned");
+    if (dst_bytes < stats_bytes_of(L))
+      return fail(IHT_EINVAL, std::string(who) + ": dst holds " + std::to_string(dst_bytes) + " bytes, the statistics need " +
+                                  std::to_string(stats_bytes_of(L)));
+  }
   // the subject bits of a subset (the whole set is built on the device)
   std::vector<uint32_t> bits;
   int64_t nT = L.n;
@@ -126,24 +183,26 @@ int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht
     nT = 0;
     for (int64_t i = 0; i < L.n; ++i) {
       const uint8_t m = subset[i];
-      if (m > 1) return fail(IHT_EINVAL, "iht_stats_create: subset entries must be 0 or 1");
+      if (m > 1) return fail(IHT_EINVAL, std::string(who) + ": subset entries must be 0 or 1");
       if (m) {
         bits[i / kTileSubjects] |= uint32_t(1) << (i % kTileSubjects);
         ++nT;
       }
     }
-    if (nT < 1) return fail(IHT_EINVAL, "iht_stats_create: empty subject set");
+    if (nT < 1) return fail(IHT_EINVAL, std::string(who) + ": empty subject set");
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   iht_stats* S = new (std::nothrow) iht_stats();
-  if (!S) return fail(IHT_ENOMEM, "iht_stats_create: host allocation");
+  if (!S) return fail(IHT_ENOMEM, std::string(who) + ": host allocation");
   S->geno = g;
   S->nT = nT;
   int rc = IHT_OK;
   do {
     const size_t fbytes = (size_t)(2 * L.p + L.n_pad) * 8;
-    hipError_t e = S->buf.ensure(fbytes + (size_t)L.ntiles * 4);
-    if (e != hipSuccess) {
+    hipError_t e = hipSuccess;
+    if (dst) {
+      S->buf.borrow(dst, stats_bytes_of(L));
+    } else if ((e = S->buf.ensure(stats_bytes_of(L))) != hipSuccess) {
       rc = hip_fail(e, "hipMalloc(stats)");
       break;
     }
@@ -174,6 +233,25 @@ int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht
   }
   *out = S;
   return IHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int iht_stats_create(const iht_geno* g, const uint8_t* subset, void* stream, iht_stats** out) {
+  return stats_make("iht_stats_create", g, subset, nullptr, 0, stream, out);
+}
+
+uint64_t iht_stats_bytes(const iht_geno* g) { return g ? stats_bytes_of(g->L) : 0; }
+
+int iht_stats_create_in(const iht_geno* g, const uint8_t* subset, void* dst, uint64_t dst_bytes, void* stream,
+                        iht_stats** out) {
+  if (!dst) {
+    if (out) *out = nullptr;
+    return fail(IHT_EINVAL, "iht_stats_create_in: dst is NULL");
+  }
+  return stats_make("iht_stats_create_in", g, subset, dst, dst_bytes, stream, out);
 }
 
 int iht_stats_destroy(iht_stats* s) {

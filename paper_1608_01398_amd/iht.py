@@ -26,7 +26,8 @@ EXPORTS = ("iht_opts_default", "iht_geno_create", "iht_geno_destroy", "iht_geno_
            "iht_project_hint", "iht_fit", "iht_fit_batch", "iht_cv", "iht_predict", "iht_server_create", "iht_server_submit", "iht_server_step",
            "iht_server_poll", "iht_server_info", "iht_server_destroy", "iht_batch_tuning", "iht_status_str",
            "iht_last_error", "iht_workspace_bytes", "iht_workspace_bytes_batch",
-           "iht_gradient_noalloc", "iht_gradient_noalloc_max_bytes")
+           "iht_gradient_noalloc", "iht_gradient_noalloc_max_bytes", "iht_geno_bytes", "iht_geno_create_in",
+           "iht_stats_bytes", "iht_stats_create_in")
 
 
 class IHTError(RuntimeError):
@@ -64,6 +65,14 @@ def load():
     L.iht_opts_default.argtypes = [ctypes.POINTER(Opts)]
     L.iht_opts_default.restype = None
     L.iht_geno_create.argtypes = [P, I64, I64, I64, I32, P, PP]
+    L.iht_geno_bytes.argtypes = [I64, I64]
+    L.iht_geno_bytes.restype = ctypes.c_uint64
+    L.iht_geno_create_in.argtypes = [P, I64, I64, I64, P, ctypes.c_uint64, P, PP]
+    L.iht_geno_create_in.restype = ctypes.c_int
+    L.iht_stats_bytes.argtypes = [P]
+    L.iht_stats_bytes.restype = ctypes.c_uint64
+    L.iht_stats_create_in.argtypes = [P, P, P, ctypes.c_uint64, P, PP]
+    L.iht_stats_create_in.restype = ctypes.c_int
     L.iht_geno_destroy.argtypes = [P]
     L.iht_geno_shape.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
     L.iht_stats_create.argtypes = [P, P, P, PP]
@@ -169,12 +178,30 @@ def workspace_bytes(n: int, p: int, k: int, c: int, precision: int = 0, T: int |
 
 
 class Geno:
-    """Resident, re-tiled PLINK genotype matrix (iht_geno_create)."""
+    """Resident, re-tiled PLINK genotype matrix (iht_geno_create). With borrow=True the re-tiled
+    matrix lives in a torch tensor (`self.storage`) that the handle borrows (iht_geno_create_in: the
+    library allocates no device memory for it); `bed` is then uploaded to the device first."""
 
-    def __init__(self, bed, n: int):
+    def __init__(self, bed, n: int, borrow: bool = False):
         torch = _torch()
         L = load()
         self._h = ctypes.c_void_p()
+        self.storage = None
+        if borrow:
+            src = bed if isinstance(bed, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(bed, dtype=np.uint8))
+            if src.dtype != torch.uint8 or src.dim() != 2:
+                raise TypeError("bed must be a 2-D uint8 array [p, row_bytes]")
+            src = src.to("cuda").contiguous()
+            p, rb = src.shape
+            nbytes = int(L.iht_geno_bytes(n, p))
+            if nbytes == 0:
+                raise ValueError("n or p out of range")
+            self.storage = torch.empty(nbytes, dtype=torch.uint8, device="cuda")  # 256-byte aligned by torch
+            _check(L.iht_geno_create_in(ctypes.c_void_p(src.data_ptr()), n, p, rb, ctypes.c_void_p(self.storage.data_ptr()),
+                                        nbytes, _stream(), ctypes.byref(self._h)))
+            self._pid = os.getpid()
+            self.n, self.p = int(n), int(p)
+            return
         if isinstance(bed, torch.Tensor):
             if bed.dtype != torch.uint8 or bed.dim() != 2:
                 raise TypeError("bed must be a 2-D uint8 tensor [p, row_bytes]")
@@ -208,19 +235,28 @@ class Geno:
 
 
 class Stats:
-    """u, v over a subject subset (iht_stats_create)."""
+    """u, v over a subject subset (iht_stats_create). With borrow=True they live in a torch tensor
+    (`self.storage`) that the handle borrows (iht_stats_create_in)."""
 
-    def __init__(self, geno: Geno, subset=None):
+    def __init__(self, geno: Geno, subset=None, borrow: bool = False):
         L = load()
         self.geno = geno
         self._h = ctypes.c_void_p()
+        self.storage = None
         m = None
         if subset is not None:
             m = np.ascontiguousarray(subset, dtype=np.uint8)
             if m.shape != (geno.n,):
                 raise ValueError("subset must have n entries")
-        _check(L.iht_stats_create(geno._h, None if m is None else m.ctypes.data_as(ctypes.c_void_p), _stream(),
-                                  ctypes.byref(self._h)))
+        mp = None if m is None else m.ctypes.data_as(ctypes.c_void_p)
+        if borrow:
+            torch = _torch()
+            nbytes = int(L.iht_stats_bytes(geno._h))
+            self.storage = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            _check(L.iht_stats_create_in(geno._h, mp, ctypes.c_void_p(self.storage.data_ptr()), nbytes, _stream(),
+                                         ctypes.byref(self._h)))
+        else:
+            _check(L.iht_stats_create(geno._h, mp, _stream(), ctypes.byref(self._h)))
         self._pid = os.getpid()
 
     def read(self):

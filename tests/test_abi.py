@@ -117,3 +117,18 @@ def test_workspace_bytes_host_only(lib_path):
     for args in ((0, 10, 1, 1, 0), (10, 0, 1, 1, 0), (10, 10, 0, 1, 0), (10, 10, 1, -1, 0), (10, 10, 1, 65, 0)):
         assert L.iht_workspace_bytes(*args) == 0, args
     assert L.iht_workspace_bytes_batch(10, 10, 0, 1, 1, 0) == 0
+
+
+def test_borrowed_handle_sizes_host_only(lib_path):
+    """iht_geno_bytes and iht_stats_bytes size the caller's buffers on the host: the re-tiled matrix
+    holds every packed byte (at least ceil(n / 4) p) in 32-subject tiles of 8-byte segments; arguments
+    out of range, or a NULL handle, give 0."""
+    from paper_1608_01398_amd import iht
+
+    L = iht.load()
+    for n, p in ((1, 1), (1000, 5000), (5000, 500_000), (20_000, 2_000_000)):
+        b = L.iht_geno_bytes(n, p)
+        assert b >= (n + 3) // 4 * p and b % 8 == 0, (n, p, b)
+        assert b % (((n + 31) // 32) * 8) == 0  # whole tiles of 8-byte segments per SNP
+    assert L.iht_geno_bytes(0, 10) == 0 and L.iht_geno_bytes(10, 0) == 0 and L.iht_geno_bytes(1 << 25, 10) == 0
+    assert L.iht_stats_bytes(None) == 0

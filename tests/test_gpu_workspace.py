@@ -1,5 +1,7 @@
 """Fits in a caller-supplied workspace (iht_opts.workspace, sized by iht_workspace_bytes): no device
 allocation by the library, results bitwise equal to the fits whose state the genotype handle owns."""
+import gc
+
 import numpy as np
 import pytest
 
@@ -48,10 +50,16 @@ def test_fit_batch_in_workspace_allocates_nothing(precision):
     del warm  # its output blocks go back to torch's cache, where the next call's outputs find them
     torch.cuda.synchronize()
     ws.fill_(0xA5)  # whatever the workspace holds on entry does not matter
-    free0 = torch.cuda.mem_get_info()[0]
-    res = iht.fit_batch(g, stats, Y, ks, Z=Z, precision=precision, workspace=ws)
-    torch.cuda.synchronize()
-    free1 = torch.cuda.mem_get_info()[0]
+    # handles left by earlier tests are finalised now, not by a collection during the measured call
+    gc.collect()
+    gc.disable()
+    try:
+        free0 = torch.cuda.mem_get_info()[0]
+        res = iht.fit_batch(g, stats, Y, ks, Z=Z, precision=precision, workspace=ws)
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+    finally:
+        gc.enable()
     assert free1 == free0, (free0, free1)
     same(res, owned)
 

@@ -4,6 +4,7 @@ row with the second on a smaller matrix (the array keeps the first call's larger
 the device's free memory unchanged across the calls; sizes past the fixed scratch are rejected
 before any device work."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -41,13 +42,19 @@ def test_noalloc_gradient_equals_gradient_twice_shrinking(precision):
     torch.cuda.synchronize()
     assert call_noalloc(*mats[0][:3], mats[0][4], precision) == iht.OK  # scratch address looked up here
     torch.cuda.synchronize()
+    gc.collect()  # handles left by earlier tests are finalised now, not inside a measured call
     for g, s, r, ref, out in mats:
         out.fill_(float("nan"))
-        free0 = torch.cuda.mem_get_info()[0]
-        rc = call_noalloc(g, s, r, out, precision)
-        torch.cuda.synchronize()
+        gc.disable()
+        try:
+            free0 = torch.cuda.mem_get_info()[0]
+            rc = call_noalloc(g, s, r, out, precision)
+            torch.cuda.synchronize()
+            free1 = torch.cuda.mem_get_info()[0]
+        finally:
+            gc.enable()
         assert rc == iht.OK, iht.load().iht_last_error()
-        assert torch.cuda.mem_get_info()[0] == free0
+        assert free1 == free0
         assert torch.equal(out, ref)
 
 
