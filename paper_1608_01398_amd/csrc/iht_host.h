@@ -188,9 +188,10 @@ int check_kmax(const iht_opts& o, int32_t kmax, const char* who);
 //
 // A turn: halving rounds for the slots whose proposal was rejected, then kAhead speculative
 // iterations [gradient of the accepted proposals, commit + next step size, next proposal (top-k
-// warm-started by S), column decode, residual + backtracking test + decision]. A proposal step is
-// idempotent for a slot waiting for a halving (same step size, same proposal, same rejection), so
-// running ahead never changes a result; slots that finished skip the extra launches.
+// warm-started by S), column decode, residual + backtracking test + decision]. A slot waiting for
+// a halving would only repeat its proposal (same step size, same proposal, same rejection), so the
+// speculative proposals skip it, as they skip the slots that finished: running ahead never changes
+// a result.
 class Engine {
  public:
   static constexpr int kAhead = 2;

@@ -66,10 +66,12 @@ struct FitState {
   int32_t retire;  // finished and being written out (refinement and outputs run for it)
 };
 
-// Launch phases of the per-solve kernels: every solve; solves still iterating; those whose
-// proposal needs a halving; those whose proposal was accepted; newly admitted solves with finite
-// inputs (the initial residual, gradient and support); newly admitted solves still iterating (the
-// first step size and proposal); solves being written out.
+// Launch phases of the per-solve kernels: every solve; solves still iterating and not waiting for
+// a halving (the next proposal: a solve whose proposal was rejected would only repeat it, since
+// the step size changes only by a halving); those whose proposal needs a halving; those whose
+// proposal was accepted; newly admitted solves with finite inputs (the initial residual, gradient
+// and support); newly admitted solves still iterating (the first step size and proposal); solves
+// being written out.
 enum : int32_t {
   kPhaseAll = 0,
   kPhaseActive = 1,
@@ -85,7 +87,7 @@ __device__ __forceinline__ bool fs_selected(const FitState* fs, int32_t phase) {
   if (phase == kPhaseInit) return fs->fresh != 0 && fs->nonfinite == 0;
   if (phase == kPhaseFresh) return fs->fresh != 0 && fs->active != 0;
   if (phase == kPhaseRetire) return fs->retire != 0;
-  if (phase == kPhaseActive) return fs->active != 0;
+  if (phase == kPhaseActive) return fs->active != 0 && fs->need_bt == 0;
   if (phase == kPhaseBacktrack) return fs->active != 0 && fs->need_bt != 0;
   return fs->active != 0 && fs->go != 0;
 }
