@@ -410,9 +410,10 @@ int iht_server_destroy(iht_server *s);
 /*
  * Block shape of the matrix-core pass (iht_gradient_batch, IHT_MIXED_I8 fits, the server) for this
  * matrix and T solves: the pass is compiled for several shapes (SNPs per workgroup x workgroups per
- * compute unit) and the first launch for a (matrix, T) shape times each three times and keeps the
- * one of least median time for the process. Every shape computes the same exact integer sums, so the choice never changes a
- * result. *snps_per_block = the chosen shape's SNPs per workgroup, or 0 if not tuned yet.
+ * compute unit x 32-solve blocks per workgroup) and the first launch for a (matrix, T) shape times
+ * each three times and keeps the one of least median time for the process. Every shape computes the
+ * same exact integer sums, so the choice never changes a result. *snps_per_block = the chosen
+ * shape's SNPs per workgroup, or 0 if not tuned yet.
  */
 int iht_batch_tuning(const iht_geno *g, int32_t T, int32_t *snps_per_block);
 
