@@ -608,6 +608,10 @@ __global__ __launch_bounds__(1024) void k_topk_bound(TopkJob J, int64_t p) {
     }
     return;
   }
+  // the support in LDS for the membership searches (k <= kLocalMaxK on this path)
+  __shared__ int64_t sprev[kLocalMaxK];
+  for (int q = tid; q < k; q += 1024) sprev[q] = prev[q];
+  __syncthreads();
   int32_t idx[kBoundEPT];
   uint64_t key[kBoundEPT];
   uint32_t nv = 0;
@@ -618,7 +622,7 @@ __global__ __launch_bounds__(1024) void k_topk_bound(TopkJob J, int64_t p) {
     bool ok;
     double v = 0.0;
     if (i < k) {
-      j = prev[i];
+      j = sprev[i];
       ok = j >= 0 && j < p;
       if (ok) v = src.at(j);
     } else {
@@ -628,12 +632,12 @@ __global__ __launch_bounds__(1024) void k_topk_bound(TopkJob J, int64_t p) {
         int lo = 0, hi = k;
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (prev[mid] < j)
+          if (sprev[mid] < j)
             lo = mid + 1;
           else
             hi = mid;
         }
-        ok = !(lo < k && prev[lo] == j);
+        ok = !(lo < k && sprev[lo] == j);
         if (ok) v = __dmul_rn(src.mu, src.g[j]);  // beta is zero off the support
       }
     }
@@ -966,6 +970,12 @@ __global__ __launch_bounds__(256) void k_topk_exact(TopkJob J, int64_t p) {
   const uint64_t kkey = (uint64_t)atomic_load_u32(&src.tw.counters[6]) | ((uint64_t)atomic_load_u32(&src.tw.counters[7]) << 32);
   const double lo = key_value(kkey) - 2.0 * row_err(J, t, src);
   const int64_t* prev = J.prev + (int64_t)t * J.ldprev;
+  // the row's support in LDS for the membership searches (k <= kLocalMaxK on certified rows)
+  __shared__ int64_t sprev[kLocalMaxK];
+  if (J.prev_exact) {
+    for (int q = threadIdx.x; q < src.k; q += blockDim.x) sprev[q] = prev[q];
+    __syncthreads();
+  }
   const BatchSolve sv = J.sv[t];
   const double* rc = J.rc + (int64_t)t * J.ldr;
   double* g = const_cast<double*>(src.g);
@@ -982,12 +992,12 @@ __global__ __launch_bounds__(256) void k_topk_exact(TopkJob J, int64_t p) {
         int a = 0, b = src.k;
         while (a < b) {
           const int mid = (a + b) >> 1;
-          if (prev[mid] < j)
+          if (sprev[mid] < j)
             a = mid + 1;
           else
             b = mid;
         }
-        need = !(a < src.k && prev[a] == j);
+        need = !(a < src.k && sprev[a] == j);
       }
     }
     uint64_t m = __ballot(need);
