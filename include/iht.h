@@ -87,7 +87,8 @@ typedef struct iht_stats iht_stats; /* u, v [p] FP64 and the subject set T they 
  * error), the gradient on the support is recomputed in FP64 from the decoded support columns, and
  * every projection is certified: the entries whose value lies within that bound of the k-th largest
  * are recomputed in FP64 before the selection. Supports, step sizes, backtracking and the stopping
- * rule (at tol) are then those of IHT_FP64; k <= 512 (else IHT_EUNSUPPORTED). With IHT_FP32 the
+ * rule (at tol) are then those of IHT_FP64; k <= 512 and n <= 8 454 660 subjects (the int32 sums
+ * stay exact while 254 n <= 2^31 - 1), else IHT_EUNSUPPORTED. With IHT_FP32 the
  * iteration stops at max(tol, mixed_tol); each converged solve is then refined in FP64 on its final
  * support to the least-squares fit on S and the unpenalised columns (the fixed point of the IHT map
  * on a fixed support), with at most polish_iter conjugate-gradient steps and the stopping rule at tol.
@@ -221,7 +222,9 @@ size_t iht_gradient_noalloc_max_bytes(void);
  *   stats  host array of T stats handles of this matrix (handles may repeat).
  *   R      device [T][n] FP64 residuals (row t for solve t); entries outside a solve's set ignored.
  *   G      device [T][p] FP64 output (row t = gradient of solve t).
- *   1 <= T <= 65535. Errors: IHT_EINVAL, IHT_ENOMEM, IHT_EDEVICE. Synchronises the stream.
+ *   1 <= T <= 65535; n <= 8 454 660 (the int32 sums stay exact while 254 n <= 2^31 - 1), else
+ *   IHT_EUNSUPPORTED. Errors: IHT_EINVAL, IHT_EUNSUPPORTED, IHT_ENOMEM, IHT_EDEVICE. Synchronises
+ *   the stream.
  */
 int iht_gradient_batch(const iht_geno *g, const iht_stats *const *stats, int32_t T, const double *R, double *G, void *stream);
 

@@ -287,6 +287,8 @@ int iht_gradient(const iht_geno* g, const iht_stats* s, const double* r, double*
 int iht_gradient_batch(const iht_geno* g, const iht_stats* const* stats, int32_t T, const double* R, double* G, void* stream) {
   if (!g || !stats || !R || !G) return fail(IHT_EINVAL, "iht_gradient_batch: NULL argument");
   if (T < 1 || T > 65535) return fail(IHT_EINVAL, "iht_gradient_batch: T out of range");
+  if (g->L.n > kBatchMaxSubjects)
+    return fail(IHT_EUNSUPPORTED, "iht_gradient_batch: n > " + std::to_string(kBatchMaxSubjects) + " subjects");
   std::vector<BatchSolve> sv((size_t)T);
   for (int32_t t = 0; t < T; ++t) {
     if (!stats[t]) return fail(IHT_EINVAL, "iht_gradient_batch: NULL stats handle");

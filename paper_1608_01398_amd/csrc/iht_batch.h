@@ -4,6 +4,10 @@
 
 namespace iht {
 
+// Most subjects the matrix-core pass takes: its int32 sums (dosage <= 2 times a digit of
+// magnitude <= 127, per subject) stay exact while 254 n <= 2^31 - 1.
+constexpr int64_t kBatchMaxSubjects = 2147483647LL / 254;
+
 int32_t batch_t_pad(int32_t T);
 size_t batch_r8_bytes(const Layout& L, int32_t T);
 // SNPs per block of the matrix-core pass the autotuner chose for this matrix and T (0: not tuned yet).

@@ -135,6 +135,8 @@ int Engine::setup(const iht_geno* g, SolveWork* Wp, SolveStage* Pp, int32_t T, i
   nc_ = U.cz + U.icpt;
   mixed_ = o.precision == IHT_MIXED_I8;
   if (int rc = check_kmax(o, kmax, "engine")) return rc;
+  if (mixed_ && L.n > kBatchMaxSubjects)
+    return fail(IHT_EUNSUPPORTED, "IHT_MIXED_I8 takes n <= " + std::to_string(kBatchMaxSubjects) + " subjects");
   if (exec_) (void)hipGraphExecDestroy(exec_);
   exec_ = nullptr;
   // the matrix-core path follows the FP64 iteration exactly (certified projection, FP64 gradient on

@@ -275,3 +275,35 @@ def test_fit_batch_c3_shape_sampled():
         say(f"  oracle solve {t}: fold {f} trait {tr} k {k}")
         ref = oracle.fit(prob["bed"], prob["n"], traits[tr], k, intercept=True, subset=masks[f])
         check_solve(out, t, k, ref, exact_path=True)
+
+
+def test_matrix_core_subject_limit():
+    """The int8 matrix-core pass keeps its int32 sums exact only while 254 n <= 2^31 - 1 (dosage 2
+    times a digit of magnitude 127 per subject): at that n the batched gradient still agrees with
+    the FP64 pass to the residual's quantisation; one subject more and the batched gradient and
+    IHT_MIXED_I8 fits are refused with IHT_EUNSUPPORTED."""
+    n_max = (2**31 - 1) // 254
+    p = 5
+    rng = np.random.default_rng(11)
+    for n in (n_max, n_max + 1):
+        nb = (n + 3) // 4
+        bed = rng.integers(0, 256, size=(p, nb), dtype=np.uint8)
+        bed[:, -1] &= np.uint8((1 << (2 * (n - 4 * (nb - 1)))) - 1)  # clear the codes past n
+        g = iht.Geno(bed, n)
+        s = iht.Stats(g)
+        R = torch.randn((1, n), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+        say(f"  n = {n}")
+        if n == n_max:
+            G = iht.gradient_batch(g, [s], R)
+            ref = iht.gradient(g, s, R[0].contiguous())
+            err = float(torch.linalg.norm(G[0] - ref) / torch.linalg.norm(ref))
+            say(f"  batched vs FP64 rel err {err:.2e}")
+            assert err < 2e-6
+        else:
+            with pytest.raises(iht.IHTError) as e:
+                iht.gradient_batch(g, [s], R)
+            assert e.value.code == iht.EUNSUPPORTED
+            with pytest.raises(iht.IHTError) as e:
+                iht.fit_batch(g, [s], R, [2], precision=iht.MIXED_I8)
+            assert e.value.code == iht.EUNSUPPORTED
+        del g, s, R
